@@ -1,0 +1,201 @@
+"""Pins of the oracle's solve: B matrix, recursion, rates, emission and energy
+balance, against brute force, closed forms, special cases and invariants
+(CPU only)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import model as om
+from oracle.physics import H, C, K, HC
+from synth.fields import make_fields, FieldRecipe
+
+
+def _random_rates(n, rng, decades=6):
+    A = np.tril(10.0 ** rng.uniform(-decades, 0, size=(n, n)), k=-1)
+    cool = np.zeros(n)
+    cool[1:] = 10.0 ** rng.uniform(-3, 1, size=n - 1)
+    return A, cool
+
+
+def test_b_recurrence_equals_triple_sum():
+    rng = np.random.default_rng(1)
+    A, _ = _random_rates(13, rng)
+    Br = om.b_matrix_recurrence(A)
+    Bt = om.b_matrix_triple_sum(A)
+    assert np.allclose(Br, Bt, rtol=1e-14, atol=0)
+    # nothing on or above the diagonal
+    assert np.all(np.triu(Br) == 0.0)
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+def test_recursion_equals_dense_master_equation(n):
+    rng = np.random.default_rng(100 + n)
+    for _ in range(5):
+        A, cool = _random_rates(n, rng)
+        P, _, _ = om.recursion(om.b_matrix_recurrence(A), cool)
+        Pd = oracle.dense_steady_state(A, cool)
+        assert np.allclose(P, Pd, rtol=1e-13, atol=0)
+        assert abs(P.sum() - 1.0) < 1e-15
+
+
+def test_two_bin_closed_form():
+    A = np.array([[0.0, 0.0], [3.7e-3, 0.0]])
+    cool = np.array([0.0, 2.9e-2])
+    P, _, _ = om.recursion(om.b_matrix_recurrence(A), cool)
+    p1 = 3.7e-3 / (3.7e-3 + 2.9e-2)
+    assert abs(P[1] / p1 - 1.0) < 4e-16 and abs(P[0] / (1.0 - p1) - 1.0) < 4e-16
+
+
+def test_dense_matrix_is_thermal_continuous():
+    rng = np.random.default_rng(7)
+    A, cool = _random_rates(9, rng)
+    from oracle.dense import transition_matrix
+    T = transition_matrix(A, cool)
+    # eq:adjacent: T_ij = 0 for i < j - 1
+    for i in range(9):
+        for j in range(9):
+            if i < j - 1:
+                assert T[i, j] == 0.0
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = synth.workload("c1_tiny")
+    u = make_fields(w.lam_cm, w.field_recipe, w.n_cells)
+    setup = oracle.grain_setup(w.grains[0], w.lam_cm)
+    return w, u, setup
+
+
+def test_recursion_matches_dense_on_physical_rates():
+    # a tiny physical grain with 16 bins: the dense LU solve of the full master
+    # equation agrees with the recursion
+    lam = synth.wavelength_grid_cm(400)
+    g = synth.make_grain("carbonaceous", 6.0e-8, lam, n_bins=16, E_range_erg=(0.05 * oracle.EV, 40.0 * oracle.EV))
+    u = make_fields(lam, FieldRecipe(9, (1.0, 1.0), 0.0, None), 1)[0]
+    s = oracle.grain_setup(g, lam)
+    A = om.heating_matrix(u, s)
+    P, _, _ = om.recursion(om.b_matrix_recurrence(A), s.cool)
+    Pd = oracle.dense_steady_state(A, s.cool)
+    assert np.allclose(P, Pd, rtol=1e-13, atol=0)
+
+
+def test_sum_P_and_rescale_invariance(c1):
+    w, u, s = c1
+    for c in range(0, 64, 9):
+        A = om.heating_matrix(u[c], s)
+        B = om.b_matrix_recurrence(A)
+        P1, _, n1 = om.recursion(B, s.cool)
+        P2, _, n2 = om.recursion(B, s.cool, threshold=2.0 ** 20, factor=2.0 ** -20)
+        assert n2 > n1
+        assert abs(P1.sum() - 1.0) < 1e-14
+        big = P1 > 1e-250
+        assert np.max(np.abs(P2[big] / P1[big] - 1.0)) < 1e-12
+
+
+def test_zero_field_gives_ground_state(c1):
+    # pruning appendix: no non-zero heating term -> P_i = delta_i0
+    w, u, s = c1
+    P, j = oracle.solve_pair(np.zeros_like(u[0]), w.grains[0], w.lam_cm)
+    assert P[0] == 1.0 and np.all(P[1:] == 0.0)
+    assert np.allclose(j, s.cabs * s.planck[0], rtol=1e-15, atol=0)
+
+
+def test_loglog_interpolation_exact_on_power_laws(c1):
+    # with u C a power law in lambda, the interpolated heating rate equals the
+    # closed form Omega(lambda_fi) lambda_fi^3 dE_f / (h^2 c) everywhere on the grid
+    w, u, s = c1
+    lam = w.lam_cm
+    q = 1.3
+    u_pl = 1e-9 * (lam / 1e-4) ** q / s.cabs          # u * C = 1e-9 (lambda / 1 um)^q
+    A = om.heating_matrix(u_pl, s, intrabin=False)
+    E, dE = s.E, s.dE
+    n = E.shape[0]
+    f, i = np.tril_indices(n, k=-1)
+    lf = HC / (E[f] - E[i])
+    inside = (lf >= lam[0]) & (lf <= lam[-1])
+    ref = np.where(inside, 1e-9 * (lf / 1e-4) ** q * lf ** 3 * dE[f] / (H * H * C), 0.0)
+    got = A[f, i]
+    assert np.all((got == 0) == (ref == 0))
+    nz = ref > 0
+    assert np.max(np.abs(got[nz] / ref[nz] - 1.0)) < 1e-12
+
+
+def test_heating_rate_counts_photons(c1):
+    # A_fi equals the photon absorption rate into bin f: c u_E C dE_f / eps with
+    # u_E = u_lambda lambda^2 / (h c) the energy density per unit photon energy.
+    # Checked where lambda_fi falls exactly on a grid node (no interpolation).
+    w, u, s = c1
+    lam = w.lam_cm
+    E, dE = s.E, s.dE
+    # construct a pair (f, i) with lambda_fi = lam[123] by moving E_i
+    f = 200
+    target = lam[123]
+    eps = HC / target
+    Ei = E[f] - eps
+    s2 = om.GrainSetup(lam=lam, cabs=s.cabs, longwave_index=s.longwave_index,
+                       E=np.array([Ei, E[f]]), dE=np.array([dE[0], dE[f]]), T=s.T[:2], cool=s.cool[:2],
+                       planck=s.planck[:2])
+    A = om.heating_matrix(u[3], s2, intrabin=False)
+    uE = u[3][123] * target ** 2 / HC
+    photons = C * uE * s.cabs[123] * dE[f] / eps
+    assert abs(A[1, 0] / photons - 1.0) < 1e-12
+
+
+def test_energy_balance_c1(c1):
+    w, u, s = c1
+    for c in (0, 17, 40, 63):
+        P, j, d = oracle.solve_pair(u[c], w.grains[0], w.lam_cm, with_diag=True)
+        # (i) discrete heating power = discrete cooling power in the steady state
+        assert abs(d["heat"] / d["cool"] - 1.0) < 1e-12
+        # (ii) emission on the grid vs cooling power: differs only by emission beyond the grid
+        assert abs(d["emitted"] / d["cool"] - 1.0) < 1e-3
+        # (iii) emission vs the representable absorbed power
+        assert abs(d["emitted"] / d["A_rep"] - 1.0) < 1e-2
+
+
+def test_emission_cutoff(c1):
+    # eq:emission-lambda: Lambda = 0 when E_i < h nu; no bin reaches 13.8 eV here
+    # when E_max = 10 eV, so the shortest wavelengths carry no emission
+    w, u, s = c1
+    P, j = oracle.solve_pair(u[5], w.grains[0], w.lam_cm)
+    cut = HC / w.lam_cm > s.E[-1]
+    assert np.any(cut) and np.all(j[cut] == 0.0) and np.all(j[~cut] >= 0.0)
+
+
+def test_large_grain_collapses_to_equilibrium_and_needs_intrabin():
+    # a 250 A grain with 128 bins: P collapses to a narrow peak at T_eq.  The
+    # paper-literal rates (no continuous intrabin term) miss the energy budget.
+    lam = synth.wavelength_grid_cm(500)
+    g = synth.make_grain("carbonaceous", 250e-8, lam)
+    assert g.n_bins == 128
+    s = oracle.grain_setup(g, lam)
+    for U in (0.1, 1.0, 1e3, 1e5):
+        u = make_fields(lam, FieldRecipe(5, (U, U), 0.0, None), 1)[0]
+        P, j, d = oracle.solve_pair(u, g, lam, with_diag=True)
+        Teq = oracle.equilibrium_temperature(u, s)
+        k = int(np.argmax(P))
+        width = s.T[k + 1] - s.T[k]
+        Tmean = float(np.sum(P * s.T))
+        Tsd = float(np.sqrt(np.sum(P * (s.T - Tmean) ** 2)))
+        # the peak sits within 1.5 bins of T_eq, and its width is the few-bin
+        # random walk that 128 bins allow (P_i ratio per bin ~ (T_i+1/T_i)^(4+p))
+        assert abs(Tmean - Teq) <= 1.5 * width and abs(s.T[k] - Teq) <= 1.5 * width
+        assert Tsd / Tmean < 0.12
+        assert abs(d["emitted"] / d["absorbed"] - 1.0) < 0.01
+        P0, j0, d0 = oracle.solve_pair(u, g, lam, intrabin=False, with_diag=True)
+        assert d0["emitted"] / d0["absorbed"] < 0.5
+
+
+def test_small_grain_is_stochastic():
+    # a 3.5 A grain: broad P spanning many decades, still in energy balance
+    lam = synth.wavelength_grid_cm(500)
+    g = synth.make_grain("carbonaceous", 3.5e-8, lam)
+    assert g.n_bins == 1024
+    u = make_fields(lam, FieldRecipe(5, (1.0, 1.0), 0.0, None), 1)[0]
+    P, j, d = oracle.solve_pair(u, g, lam, with_diag=True)
+    assert abs(d["emitted"] / d["A_rep"] - 1.0) < 0.01
+    assert P.max() < 0.1 and np.count_nonzero(P > 1e-3) > 50
