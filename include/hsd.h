@@ -1,0 +1,163 @@
+/*
+ * hsd.h -- C ABI of the MI355X stochastic-heating emissivity library.
+ *
+ * For every (cell radiation field, grain size) pair the library computes the
+ * steady-state enthalpy-bin probabilities P_i of a radiatively heated grain and
+ * its emission spectrum j_lambda, with the matrix formalism summarised in
+ * Porter & Vladimirov, arXiv:1311.4627, Sec. 2 (Guhathakurta & Draine; Draine &
+ * Li) in the "thermal continuous" approximation:
+ *
+ *   heating  A_fi = Omega(lambda_fi) lambda_fi^3 dE_f / (h^2 c), f > i,
+ *            Omega = u_lambda C_abs interpolated log-log on the wavelength grid
+ *            (Sec. 2.2, eq:heating, eq:interpolation), plus the continuous
+ *            intrabin term of Draine & Li on A_(i+1)i;
+ *   cooling  T_(f-1)f = [8 pi / (h^3 c^2)] int_0^{E_f} E^3 C_abs / (e^{E/kT_f} - 1) dE
+ *            / (E_f - E_(f-1))   (Sec. 2.2, eq:cooling);
+ *   B_fj = sum_{k>=f} A_kj (eq:bmatrix), X_0 = 1,
+ *   X_f = sum_{j<f} B_fj X_j / T_(f-1)f (eq:xf), P = X / sum X (eq:renormalization);
+ *   j_lambda = C_abs(lambda) sum_i P_i B_lambda(T_i) [E_i >= hc/lambda]
+ *            (Sec. 2.3, eq:emission, eq:emission-lambda).
+ *
+ * Units are CGS throughout: wavelength cm, energy erg, cross-section cm^2,
+ * field energy density u_lambda erg cm^-3 cm^-1, emissivity j_lambda
+ * erg s^-1 sr^-1 cm^-1 per grain.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns an hsd_status; on failure hsd_last_error() holds a
+ *    message.  No C++ exception crosses the ABI.
+ *  - Pointers named *_dev are device pointers on the context's device (for
+ *    instance the data_ptr() of a PyTorch tensor).  Pointers named *_host are
+ *    host pointers.  The caller owns every buffer it passes; the library never
+ *    frees or retains them past the call (asynchronous calls read and write
+ *    them until the stream reaches the enqueued work).
+ *  - The library owns its per-grain tables and workspaces; they persist, grow
+ *    on demand and are released by hsd_destroy().
+ *  - Asynchronous entry points take a hipStream_t as void*; NULL means the
+ *    null stream.  Errors raised by device work surface at the next
+ *    hsd_sync() (or the next synchronous call).
+ *  - A context is not re-entrant: calls on one context must be serialised by
+ *    the caller (the paper's library serialises concurrent calls the same
+ *    way, appendix on usage in parallel platforms).  Separate contexts are
+ *    independent.
+ */
+#ifndef HSD_H
+#define HSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HSD_OK = 0,
+    HSD_ERR_INVALID_ARG = -1,       /* null pointer, bad size, bad id */
+    HSD_ERR_UNSUPPORTED_GRID = -2,  /* wavelength grid not log-uniform or too long */
+    HSD_ERR_OOM = -3,               /* device allocation failed */
+    HSD_ERR_HIP = -4,               /* a HIP runtime call failed */
+    HSD_ERR_NONFINITE_INPUT = -5,   /* a field value was NaN, infinite or negative */
+    HSD_ERR_STATE = -6              /* call not valid in the context's state */
+} hsd_status;
+
+typedef struct hsd_ctx hsd_ctx;
+
+/* One grain size of one composition (the paper's GrainModel row plus the
+ * engine's enthalpy grid, appendix on the library interface). */
+typedef struct {
+    double radius_cm;        /* grain radius (informational; C_abs carries the size) */
+    double n_atoms;          /* N: 3N Debye modes, real-valued                        */
+    double theta_debye_K;    /* Debye temperature of the heat capacity               */
+    int32_t n_bins;          /* M + 1 enthalpy bins; 16 <= n_bins <= 1024, multiple of 16 */
+    double E_lo_erg;         /* E_0: lowest bin enthalpy, > 0                          */
+    double E_hi_erg;         /* E_M: highest bin enthalpy, > E_lo; bins are log-uniform */
+    const double* cabs_host; /* [n_lambda] C_abs on the context's wavelength grid, > 0 */
+    double longwave_index;   /* p: C_abs ~ lambda^-p beyond the grid's long end (used by
+                                the cooling integral only)                              */
+} hsd_grain_desc;
+
+/* Create a context on HIP device `device` for the wavelength grid
+ * lambda_host[0..n_lambda-1] (cm, strictly increasing, log-uniform to 1e-9
+ * relative, 16 <= n_lambda <= 2048).  Rates are evaluated at arbitrary
+ * wavelengths by the closed-form grid index of a log-uniform grid; another
+ * grid gives HSD_ERR_UNSUPPORTED_GRID.  *out receives the context. */
+hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambda, hsd_ctx** out);
+
+/* Release every device allocation of the context and the context itself.
+ * Waits for the context's outstanding work.  NULL is ignored. */
+void hsd_destroy(hsd_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none).  The string belongs to
+ * the context and stays valid until the next call on it. */
+const char* hsd_last_error(const hsd_ctx* ctx);
+
+/* Register a grain and build its device tables (Sec. 2.2: everything that does
+ * not depend on the field is precomputed once): bin enthalpies and widths,
+ * bin temperatures from the Debye heat capacity, cooling rates, the scaled
+ * Planck table for the emission contraction, and the closed-form
+ * interpolation tables for the heating rates.  Synchronous.  *grain_id
+ * receives a small non-negative id. */
+hsd_status hsd_add_grain(hsd_ctx* ctx, const hsd_grain_desc* desc, int32_t* grain_id);
+
+/* Copy a grain's field-independent tables to host arrays of n_bins doubles
+ * each (any pointer may be NULL): bin enthalpies E_i (erg), bin widths dE_i
+ * (erg), bin temperatures T_i (K) and cooling rates T_(f-1)f (s^-1, entry 0 is
+ * 0).  Synchronous. */
+hsd_status hsd_grain_tables(hsd_ctx* ctx, int32_t grain_id, double* E_host, double* dE_host,
+                            double* T_host, double* cool_host);
+
+/* The plain solve (Sec. 2): for every cell c < n_cells and every listed grain
+ * g, compute P and j_lambda.
+ *   u_dev      [n_cells][n_lambda] double: field energy density per unit
+ *              wavelength, finite and >= 0 (a violation is flagged per pair and
+ *              reported as HSD_ERR_NONFINITE_INPUT by hsd_sync; the pair is
+ *              solved with the bad values read as 0).
+ *   grain_ids_host [n_grains] ids from hsd_add_grain (repeats allowed).
+ *   j_dev      [n_cells][n_grains][n_lambda] float: emissivity per grain,
+ *              erg s^-1 sr^-1 cm^-1.
+ *   diag_dev   optional [n_cells][n_grains][4] float: absorbed power
+ *              int c u C_abs dlambda, emitted power 4 pi int j dlambda (both
+ *              erg s^-1 on the grid, trapezoid), the representable absorbed
+ *              power A_rep, and the pair's flags as an exact small integer
+ *              (bit 0: no heating term, P = delta_i0; bit 1: X was rescaled;
+ *              bit 2: non-finite or negative field value).
+ * Asynchronous on `stream`; grows the context's workspace if needed (that
+ * growth allocates and synchronises). */
+hsd_status hsd_solve(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                     const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream);
+
+/* Same solve for one grain, returning the bin probabilities in double
+ * precision instead of the spectrum: P_dev [n_cells][n_bins] double.
+ * Asynchronous on `stream`. */
+hsd_status hsd_solve_P(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t grain_id,
+                       double* P_dev, void* stream);
+
+/* The FP64 steps alone, on rates the caller supplies: B sums, the X
+ * recursion with power-of-two rescaling and the renormalisation
+ * (eq:bmatrix, eq:xf, eq:renormalization), for n_pairs independent systems.
+ *   A_dev    [n_pairs][n_bins][n_bins] double, row-major: A[f][i] is the
+ *            heating rate from bin i to bin f; only f > i is read.
+ *   cool_dev [n_pairs][n_bins] double: cool[f] = T_(f-1)f > 0 for f >= 1.
+ *   P_dev    [n_pairs][n_bins] double out.
+ * n_bins: 16 <= n_bins <= 1024, multiple of 16.  Asynchronous on `stream`.
+ * Needs no grain; any context works. */
+hsd_status hsd_solve_from_rates(hsd_ctx* ctx, int32_t n_bins, int32_t n_pairs, const double* A_dev,
+                                const double* cool_dev, double* P_dev, void* stream);
+
+/* Wait for all device work of the context's device and report deferred
+ * errors (including HSD_ERR_NONFINITE_INPUT raised by a previous hsd_solve). */
+hsd_status hsd_sync(hsd_ctx* ctx);
+
+/* Phase timing (profiling aid).  With enable != 0, every following hsd_solve
+ * records HIP events on its stream around its three phases: the fused
+ * rates/recursion kernels, the emission contraction, and the diagnostics.
+ * hsd_phase_ms waits for the last timed solve and writes the elapsed
+ * milliseconds of the three phases to ms_host[0..2].  Timing adds no
+ * synchronisation to hsd_solve itself. */
+hsd_status hsd_set_timing(hsd_ctx* ctx, int32_t enable);
+hsd_status hsd_phase_ms(hsd_ctx* ctx, double* ms_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSD_H */

@@ -1,0 +1,147 @@
+// Internal declarations of the HIP library behind include/hsd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hsd.h"
+
+namespace hsd {
+
+// CODATA 2018 exact values (CGS); the library's own copy.
+constexpr double kPlanck = 6.62607015e-27;   // erg s
+constexpr double kLight = 2.99792458e10;     // cm s^-1
+constexpr double kBoltzmann = 1.380649e-16;  // erg K^-1
+constexpr double kHC = kPlanck * kLight;
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kMaxBins = 1024;
+constexpr int kMaxLambda = 1024;
+
+// Per-step (column) parameters of the heating-rate recursion, one per lower
+// bin i.  Read with wave-uniform addresses.
+struct alignas(32) ColPar {
+    double invcool;   // 1 / T_(i-1)i (0 for i = 0)
+    int ia;           // integer part of the column's grid coordinate, minus 1
+    float fa;         // fractional part plus 1, in [1, 2)
+    int kb, ke;       // rows k with a grid-resident transition i -> k: kb..ke (kb > ke: none)
+    int pad0, pad1;
+};
+
+// Interpolation constants of a transition distance d = f - i: grid
+// coordinate b_d = ln(r^d - 1) / dln(lambda) split as -floor and fraction.
+struct alignas(8) DPar {
+    int nib;          // -floor(b_d)
+    float fb;         // b_d - floor(b_d), in [0, 1)
+};
+
+// Device tables of one registered grain (all owned by the context).
+struct Grain {
+    int n_bins = 0;
+    double E_lo = 0, E_hi = 0, n_atoms = 0, theta = 0, longwave = 0;
+    double* E = nullptr;       // [n]
+    double* dE = nullptr;      // [n]
+    double* T = nullptr;       // [n]
+    double* cool = nullptr;    // [n]
+    ColPar* colpar = nullptr;  // [n]
+    DPar* dpar = nullptr;      // [n]   entry d = 1..n-1
+    double* gam = nullptr;     // [n]   log2(dE_k) + 3 log2(lambda_0) - log2(h^2 c)
+    double* invgap = nullptr;  // [n]   1 / (E_(i+1) - E_i)
+    int* jstar = nullptr;      // [n]   first grid index of continuous (intrabin) photons, L = none
+    int* jrep = nullptr;       // [n]   first grid index of representable photons from bin i
+    double* cabs = nullptr;    // [L]
+    float* Bt = nullptr;       // [n][Lp] C_abs B_lambda(T_i) [E_i >= hc/lambda] / s_lambda
+    float* bscale = nullptr;   // [Lp]   s_lambda (0 where the column is empty)
+};
+
+// Kernel-side view of a grain for the solver.
+struct GrainView {
+    const ColPar* colpar;
+    const DPar* dpar;
+    const double* gam;
+    const double* invgap;
+    const int* jstar;
+    const double* cabs;
+    int nb;
+    int pad;
+};
+
+struct Ctx {
+    int device = 0;
+    int L = 0, Lp = 0;
+    double lnlam0 = 0, dlnlam = 0;
+    double* lam = nullptr;        // [L] device copy of the grid
+    std::vector<double> lam_host;
+    std::vector<Grain> grains;
+    std::string err;
+    // workspace (grown on demand)
+    float* Pt = nullptr;          size_t Pt_cap = 0;       // scaled P rows
+    float* pscale = nullptr;      size_t pscale_cap = 0;   // max P per pair
+    float* diag_tmp = nullptr;    size_t diag_cap = 0;
+    GrainView* views = nullptr;   size_t views_cap = 0;
+    long long* offs = nullptr;    size_t offs_cap = 0;
+    int2* items = nullptr;        size_t items_cap = 0;
+    unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
+    bool timing = false;
+    bool timed = false;           // events of the last solve are recorded
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+// Gauss-Legendre rules used by the precompute kernels (nodes on [-1, 1]).
+struct GLRule {
+    int n;
+    double x[24];
+    double w[24];
+};
+GLRule gauss_legendre(int n);
+
+// ---- launchers (host functions, defined in the .hip files) ----
+hipError_t build_grain_tables(Ctx& c, Grain& g);                        // hsd_precompute.hip
+
+struct SolveLaunch {
+    const double* u;
+    int n_cells, n_gslots;
+    const GrainView* views;   // device [n_gslots]
+    const long long* offs;    // device [n_gslots] element offset of each slot in Pt
+    float* Pt;
+    float* pscale;            // [n_cells * n_gslots]
+    float* diag;              // [n_cells * n_gslots * 4] or null
+    double* P64;              // [n_cells * nb] (single-slot P output) or null
+    unsigned* errword;
+};
+// Launch the fused rates -> B -> recursion kernel for every pair of the
+// listed (slot, cell block) items of one bin-count class.
+hipError_t launch_solve(const Ctx& c, const SolveLaunch& a, int nb_max, const int2* items_dev,
+                        int n_items, int cells_per_item_out_hint, hipStream_t s);
+int solve_cells_per_item(int nb_max);
+
+hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool,
+                             double* P, hipStream_t s);
+
+struct ContractLaunch {
+    const float* Pt;          // rows of the slot: [n_cells][nb]
+    const float* pscale;      // [n_cells * n_gslots] (stride n_gslots)
+    const float* Bt;          // [nb][Lp]
+    const float* bscale;      // [Lp]
+    float* j;                 // [n_cells][n_gslots][L]
+    int n_cells, nb, L, Lp, n_gslots, gslot;
+};
+hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
+
+struct DiagLaunch {
+    const double* u;
+    const double* cabs;
+    const double* lam;
+    const int* jrep;
+    const float* Pt;          // slot rows
+    const float* pscale;
+    const float* j;
+    float* diag;
+    int n_cells, nb, L, n_gslots, gslot;
+};
+hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
+
+}  // namespace hsd

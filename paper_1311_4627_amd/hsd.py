@@ -1,0 +1,224 @@
+"""Python binding of libhsd.so (include/hsd.h): argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels; this module checks
+shapes and dtypes of PyTorch tensors, passes their device pointers and the
+current HIP stream through ctypes, and turns status codes into exceptions.
+It raises at import time if the library has not been built, and never falls
+back to any other implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsd.so")
+
+HSD_OK = 0
+STATUS_NAMES = {
+    0: "HSD_OK", -1: "HSD_ERR_INVALID_ARG", -2: "HSD_ERR_UNSUPPORTED_GRID", -3: "HSD_ERR_OOM",
+    -4: "HSD_ERR_HIP", -5: "HSD_ERR_NONFINITE_INPUT", -6: "HSD_ERR_STATE",
+}
+
+# exported symbols declared in include/hsd.h
+SYMBOLS = (
+    "hsd_create", "hsd_destroy", "hsd_last_error", "hsd_add_grain", "hsd_grain_tables",
+    "hsd_solve", "hsd_solve_P", "hsd_solve_from_rates", "hsd_sync", "hsd_set_timing", "hsd_phase_ms",
+)
+
+
+class HsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hsd_grain_desc(ctypes.Structure):
+    _fields_ = [
+        ("radius_cm", ctypes.c_double),
+        ("n_atoms", ctypes.c_double),
+        ("theta_debye_K", ctypes.c_double),
+        ("n_bins", ctypes.c_int32),
+        ("E_lo_erg", ctypes.c_double),
+        ("E_hi_erg", ctypes.c_double),
+        ("cabs_host", ctypes.POINTER(ctypes.c_double)),
+        ("longwave_index", ctypes.c_double),
+    ]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1311_4627_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    lib.hsd_create.argtypes = [i32, dp, i32, ctypes.POINTER(vp)]
+    lib.hsd_create.restype = ctypes.c_int
+    lib.hsd_destroy.argtypes = [vp]
+    lib.hsd_destroy.restype = None
+    lib.hsd_last_error.argtypes = [vp]
+    lib.hsd_last_error.restype = ctypes.c_char_p
+    lib.hsd_add_grain.argtypes = [vp, ctypes.POINTER(hsd_grain_desc), ctypes.POINTER(i32)]
+    lib.hsd_add_grain.restype = ctypes.c_int
+    lib.hsd_grain_tables.argtypes = [vp, i32, dp, dp, dp, dp]
+    lib.hsd_grain_tables.restype = ctypes.c_int
+    lib.hsd_solve.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
+    lib.hsd_solve.restype = ctypes.c_int
+    lib.hsd_solve_P.argtypes = [vp, i32, vp, i32, vp, vp]
+    lib.hsd_solve_P.restype = ctypes.c_int
+    lib.hsd_solve_from_rates.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.hsd_solve_from_rates.restype = ctypes.c_int
+    lib.hsd_sync.argtypes = [vp]
+    lib.hsd_sync.restype = ctypes.c_int
+    lib.hsd_set_timing.argtypes = [vp, i32]
+    lib.hsd_set_timing.restype = ctypes.c_int
+    lib.hsd_phase_ms.argtypes = [vp, dp]
+    lib.hsd_phase_ms.restype = ctypes.c_int
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_dev(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """Owns one hsd_ctx.  Methods mirror the C entry points one to one."""
+
+    def __init__(self, lam_cm: np.ndarray, device: int = 0):
+        self._lib = lib()
+        lam = np.ascontiguousarray(lam_cm, dtype=np.float64)
+        h = ctypes.c_void_p()
+        st = self._lib.hsd_create(int(device), _dptr(lam), int(lam.shape[0]), ctypes.byref(h))
+        if st != HSD_OK:
+            raise HsdError(st, "hsd_create failed")
+        self._h = h
+        self.L = int(lam.shape[0])
+        self.n_bins = {}
+
+    def _raise(self, st: int, what: str):
+        msg = self._lib.hsd_last_error(self._h).decode()
+        raise HsdError(st, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hsd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hsd_add_grain(self, n_atoms: float, theta_K: float, n_bins: int, E_lo: float, E_hi: float,
+                      cabs: np.ndarray, longwave_index: float, radius_cm: float = 0.0) -> int:
+        c = np.ascontiguousarray(cabs, dtype=np.float64)
+        if c.shape != (self.L,):
+            raise ValueError("C_abs table must have one value per grid wavelength")
+        d = hsd_grain_desc(radius_cm, n_atoms, theta_K, int(n_bins), E_lo, E_hi, _dptr(c), longwave_index)
+        gid = ctypes.c_int32()
+        st = self._lib.hsd_add_grain(self._h, ctypes.byref(d), ctypes.byref(gid))
+        if st != HSD_OK:
+            self._raise(st, "hsd_add_grain")
+        self.n_bins[gid.value] = int(n_bins)
+        return gid.value
+
+    def add_grain(self, grain) -> int:
+        """Register a synth.Grain."""
+        return self.hsd_add_grain(grain.n_atoms, grain.theta_K, grain.n_bins, grain.E_lo_erg, grain.E_hi_erg,
+                                  grain.cabs_cm2, grain.longwave_index, grain.radius_cm)
+
+    def hsd_grain_tables(self, gid: int):
+        n = self.n_bins[gid]
+        E, dE, T, cool = (np.empty(n) for _ in range(4))
+        st = self._lib.hsd_grain_tables(self._h, gid, _dptr(E), _dptr(dE), _dptr(T), _dptr(cool))
+        if st != HSD_OK:
+            self._raise(st, "hsd_grain_tables")
+        return E, dE, T, cool
+
+    def hsd_solve(self, u, grain_ids: Sequence[int], j, diag=None, stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(j, torch.float32, (n_cells, ids.shape[0], self.L), "j")
+        if diag is not None:
+            _check_dev(diag, torch.float32, (n_cells, ids.shape[0], 4), "diag")
+        st = self._lib.hsd_solve(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                 ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), j.data_ptr(),
+                                 diag.data_ptr() if diag is not None else None, _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_solve")
+
+    def hsd_solve_P(self, u, gid: int, P, stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(P, torch.float64, (n_cells, self.n_bins[gid]), "P")
+        st = self._lib.hsd_solve_P(self._h, n_cells, u.data_ptr(), int(gid), P.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_solve_P")
+
+    def hsd_solve_from_rates(self, A, cool, P, stream=None):
+        import torch
+        n_pairs, nb = int(A.shape[0]), int(A.shape[1])
+        _check_dev(A, torch.float64, (n_pairs, nb, nb), "A")
+        _check_dev(cool, torch.float64, (n_pairs, nb), "cool")
+        _check_dev(P, torch.float64, (n_pairs, nb), "P")
+        st = self._lib.hsd_solve_from_rates(self._h, nb, n_pairs, A.data_ptr(), cool.data_ptr(), P.data_ptr(),
+                                            _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_solve_from_rates")
+
+    def hsd_set_timing(self, enable: bool):
+        st = self._lib.hsd_set_timing(self._h, 1 if enable else 0)
+        if st != HSD_OK:
+            self._raise(st, "hsd_set_timing")
+
+    def hsd_phase_ms(self):
+        ms = np.zeros(3)
+        st = self._lib.hsd_phase_ms(self._h, _dptr(ms))
+        if st != HSD_OK:
+            self._raise(st, "hsd_phase_ms")
+        return ms
+
+    def hsd_sync(self):
+        st = self._lib.hsd_sync(self._h)
+        if st != HSD_OK:
+            self._raise(st, "hsd_sync")
