@@ -22,7 +22,7 @@ __device__ __forceinline__ void transition_index(int ia1, float fa1, int nib, fl
     const float fd = fa1 - fb;
     const int fl = static_cast<int>(fd);
     jlo = ia1 + nib + fl;
-    w = fd - static_cast<float>(fl);
+    w = __builtin_amdgcn_fractf(fd);   // fd - floor(fd), exact for fd in (0, 2)
 }
 
 }  // namespace hsd

@@ -28,7 +28,8 @@ struct alignas(32) ColPar {
     int ia;           // integer part of the column's grid coordinate, minus 1
     float fa;         // fractional part plus 1, in [1, 2)
     int kb, ke;       // rows k with a grid-resident transition i -> k: kb..ke (kb > ke: none)
-    int pad0, pad1;
+    int jstar;        // first grid index of the photons that heat i -> i+1 continuously (L: none)
+    float invgap;     // 1 / (E_(i+1) - E_i) (0 for the top bin)
 };
 
 // Interpolation constants of a transition distance d = f - i: grid

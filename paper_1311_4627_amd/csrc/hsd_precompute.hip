@@ -275,7 +275,8 @@ __global__ void k_tables(int n, int L, double E_lo, double E_hi, double lnlam0, 
         dpar[i].nib = -ib;
         dpar[i].fb = fb;
     } else {
-        dpar[0].nib = 0;
+        // distance 0 (a row at or below the diagonal) lands far below the grid
+        dpar[0].nib = -(1 << 20);
         dpar[0].fb = 0.0f;
     }
     // column parameters
@@ -288,7 +289,8 @@ __global__ void k_tables(int n, int L, double E_lo, double E_hi, double lnlam0, 
     cp.invcool = (i >= 1) ? 1.0 / cool[i] : 0.0;
     cp.ia = ia - 1;
     cp.fa = fa + 1.0f;
-    cp.pad0 = cp.pad1 = 0;
+    cp.jstar = L;
+    cp.invgap = 0.0f;
     int kb = n, ke = -1;
     for (int k = i + 1; k < n; ++k) {
         const int d = k - i;
@@ -306,7 +308,6 @@ __global__ void k_tables(int n, int L, double E_lo, double E_hi, double lnlam0, 
     }
     cp.kb = kb;
     cp.ke = ke;
-    colpar[i] = cp;
     // row constant of the rate exponent: log2(dE_k) + 3 log2(lambda_0) - log2(h^2 c)
     gam[i] = log2(dE[i]) + 3.0 * lnlam0 / log(2.0) - log2(kPlanck * kPlanck * kLight);
     // continuous heating below the step to the next bin (Draine & Li intrabin term)
@@ -321,10 +322,13 @@ __global__ void k_tables(int n, int L, double E_lo, double E_hi, double lnlam0, 
             js = eps_lo > 0.0 ? first_at_least(lam, L, lnlam0, dlnlam, kHC / eps_lo) : L;
         }
         jstar[i] = js;
+        cp.jstar = js;
+        cp.invgap = static_cast<float>(1.0 / gap);
     } else {
         invgap[i] = 0.0;
         jstar[i] = L;
     }
+    colpar[i] = cp;
     // photons a grain in bin i can absorb without leaving the grid's top bin
     const double edge = E[M] + 0.5 * dE[M] - E[i];
     jrep[i] = edge > 0.0 ? first_at_least(lam, L, lnlam0, dlnlam, kHC / edge) : L;

@@ -15,7 +15,8 @@
 // instead of row by row: every term is the same non-negative product A_kj X_j,
 // nothing is ever subtracted (the direct solve's cancellation that the paper's
 // Sec. 2.1 warns about cannot occur), and B is never stored.  The suffix sum
-// over k is a segmented wavefront reduction in FP64.
+// over k is a segmented wavefront reduction in FP64 (DPP within rows of 16
+// lanes, lane-swap instructions across rows).
 //
 // Rates.  Column f's rates A_kf are produced in the update itself: on
 // log-uniform grids the transition's wavelength-grid coordinate is
@@ -26,12 +27,20 @@
 // with tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) (per pair, in LDS) and
 // gamma_k = log2(dE_k) + 3 log2(lambda_0) - log2(h^2 c) (per row, in registers).
 // The exponent and exp2 are single precision; the product with X_f and every
-// sum are double precision.
+// sum are double precision.  Row slots are processed in groups of four with
+// straight-line bodies, so the LDS reads of a group overlap; a group wholly
+// outside the column's grid-resident rows kb..ke skips its rates.
+//
+// Continuous (intrabin) heating of row f+1 from column f adds
+// X_f Cum(jstar_f) / (E_(f+1) - E_f), Cum_j being the absorbed power of photons at
+// wavelengths >= lambda_j; each lane keeps the value for its own rows.
 //
 // Rescaling.  When a new X_f exceeds 2^500 the pair's whole state (X_0..X_f and
 // every pending G) is multiplied by 2^-500, exactly (the appendix on precision
 // control rescales by 1e-30 above 1e30 in single precision).
 #include <cmath>
+#include <cstdlib>
+#include <utility>
 
 #include "hsd_index.h"
 #include "hsd_internal.h"
@@ -43,17 +52,90 @@ constexpr double kBig = 0x1p500;
 constexpr double kShrink = 0x1p-500;
 constexpr float kNoField = -1.0e30f;   // log2 table entry of a non-positive Omega
 
+// v from another lane of the same 16-lane row (a full permutation, so every
+// lane has a source).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Column parameters are read with wave-uniform addresses from memory the
+// kernel never writes; the constant address space lets them come in through
+// scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) ColPar* ConstColPar;
+
+__device__ __forceinline__ ColPar load_colpar(const ColPar* p, int i) {
+    ConstColPar c = (ConstColPar)p + i;
+    ColPar v;
+    v.invcool = c->invcool;
+    v.ia = c->ia;
+    v.fa = c->fa;
+    v.kb = c->kb;
+    v.ke = c->ke;
+    v.jstar = c->jstar;
+    v.invgap = c->invgap;
+    return v;
+}
+
+// Two values of v, one from each 16-lane row of a pair of rows (ROW16) or
+// from each 32-lane half of the wave; their combination is the same on every
+// lane of the 32-lane (64-lane) group.
+template <bool ROW16>
+__device__ __forceinline__ void swap_halves(double v, double& a, double& b) {
+    const unsigned lo = static_cast<unsigned>(__double2loint(v));
+    const unsigned hi = static_cast<unsigned>(__double2hiint(v));
+    if constexpr (ROW16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        a = __hiloint2double(static_cast<int>(h[0]), static_cast<int>(l[0]));
+        b = __hiloint2double(static_cast<int>(h[1]), static_cast<int>(l[1]));
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        a = __hiloint2double(static_cast<int>(h[0]), static_cast<int>(l[0]));
+        b = __hiloint2double(static_cast<int>(h[1]), static_cast<int>(l[1]));
+    }
+}
+
+// Sum over the P lanes of each segment; every lane of a segment gets the same
+// bits (each combining step is symmetric).
 template <int P>
 __device__ __forceinline__ double seg_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < P; m <<= 1) v += __shfl_xor(v, m, 64);
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    if constexpr (P >= 32) {
+        double a, b;
+        swap_halves<true>(v, a, b);
+        v = a + b;
+    }
+    if constexpr (P >= 64) {
+        double a, b;
+        swap_halves<false>(v, a, b);
+        v = a + b;
+    }
     return v;
 }
 
 template <int P>
 __device__ __forceinline__ double seg_max(double v) {
-#pragma unroll
-    for (int m = 1; m < P; m <<= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    if constexpr (P >= 32) {
+        double a, b;
+        swap_halves<true>(v, a, b);
+        v = fmax(a, b);
+    }
+    if constexpr (P >= 64) {
+        double a, b;
+        swap_halves<false>(v, a, b);
+        v = fmax(a, b);
+    }
     return v;
 }
 
@@ -85,11 +167,159 @@ __device__ __forceinline__ double clean_field(double u, bool& bad) {
     return u;
 }
 
+template <int R>
+struct Rec {
+    double G[R];       // inflow G(k) of the lane's rows, then X_k once row k is passed
+    float gm[R];       // gamma_k of the rows (with the pair's table offset)
+    float intra[R];    // continuous-heating rate into each row from the row below
+    double part;       // this lane's share of sum_{k >= f} G(k) for the next step
+    int nres;          // rescales so far
+    ColPar cnext;      // prefetched parameters of the next column
+};
+
+struct StepEnv {
+    int q, nb, Lm1;
+    const ColPar* colpar;
+    const DPar* dpar;  // LDS
+    const float* tab;  // LDS, this pair's log2 table
+    const double* Ap;  // given-rates hook: this pair's rate matrix
+    const double* cp;  // given-rates hook: this pair's cooling rates
+};
+
+// Rate of the transition column f -> row k (k in the column's grid-resident
+// range unless MASKED, where out-of-range lanes read clamped addresses and the
+// caller discards their value).
+// All steps f = RO*P .. RO*P + P - 1 (the columns whose rows sit in slot RO).
+// Slots below RO are finished and untouched; slot RO holds the diagonal.
+//
+// Rates need no per-lane masks on the physical path: the log2 table carries a
+// non-field sentinel one entry below lambda_0 and two above lambda_(L-1), the
+// interval index is clamped into [-1, L], distance 0 (rows at or below the
+// diagonal) maps far below the grid, and rows past the grain's top bin carry a
+// sentinel gamma, so every transition off the wavelength grid evaluates to
+// exp2(-1e30-ish) = 0 exactly.  Slots are handled KG at a time as straight-line
+// code, so the LDS reads of a group are in flight together; a group wholly
+// outside the column's grid-resident rows kb..ke is skipped by a wave-uniform
+// test.
+template <int P, int R, int KG, bool GIVEN, int RO>
+__device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
+    const int q = e.q, nb = e.nb;
+    if (RO * P >= nb) return;
+#pragma unroll 1
+    for (int l = 0; l < P; ++l) {
+        const int f = RO * P + l;
+        if (f >= nb) break;
+        ColPar cc{};
+        if constexpr (!GIVEN) {
+            cc = st.cnext;
+            st.cnext = load_colpar(e.colpar, min(f + 1, nb - 1));      // prefetch the next column
+        }
+        double Xf = 1.0;
+        if (f > 0) {
+            const double S = seg_sum<P>(st.part);
+            if constexpr (GIVEN) Xf = S / e.cp[f];
+            else Xf = S * cc.invcool;
+        }
+        if (Xf > kBig) {
+            Xf *= kShrink;
+#pragma unroll
+            for (int r = 0; r < R; ++r) st.G[r] *= kShrink;
+            ++st.nres;
+        }
+        if (q == l) st.G[RO] = Xf;
+        int kb, ke;
+        if constexpr (GIVEN) {
+            kb = f + 1;
+            ke = nb - 1;
+        } else {
+            kb = max(cc.kb, f + 1);
+            ke = cc.ke;
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int r0 = RO; r0 < R; r0 += KG) {
+            const int ns = (R - r0) < KG ? (R - r0) : KG;
+            const int lo_row = r0 * P, hi_row = (r0 + ns) * P - 1;
+            if (lo_row >= nb) break;
+            if (hi_row >= kb && lo_row <= ke) {
+                double A[KG];
+                if constexpr (GIVEN) {
+#pragma unroll
+                    for (int s = 0; s < KG; ++s) {
+                        if (s >= ns) break;
+                        const int k = (r0 + s) * P + q;
+                        const double v = e.Ap[static_cast<size_t>(min(k, nb - 1)) * nb + f];
+                        A[s] = (k >= kb && k <= ke) ? v : 0.0;
+                    }
+                } else {
+                    DPar dp[KG];
+#pragma unroll
+                    for (int s = 0; s < KG; ++s) {
+                        if (s >= ns) break;
+                        const int d = (r0 + s) * P + q - f;
+                        dp[s] = e.dpar[r0 + s == RO ? max(d, 0) : d];
+                    }
+                    float t0[KG], t1[KG], w[KG];
+#pragma unroll
+                    for (int s = 0; s < KG; ++s) {
+                        if (s >= ns) break;
+                        int jlo;
+                        transition_index(cc.ia, cc.fa, dp[s].nib, dp[s].fb, jlo, w[s]);
+                        jlo = min(max(jlo, -1), e.Lm1 + 1);
+                        t0[s] = e.tab[jlo];
+                        t1[s] = e.tab[jlo + 1];
+                    }
+#pragma unroll
+                    for (int s = 0; s < KG; ++s) {
+                        if (s >= ns) break;
+                        A[s] = static_cast<double>(
+                            __builtin_amdgcn_exp2f(fmaf(w[s], t1[s] - t0[s], t0[s]) + st.gm[r0 + s]));
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < KG; ++s) {
+                    if (s >= ns) break;
+                    st.G[r0 + s] = fma(A[s], Xf, st.G[r0 + s]);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < KG; ++s) {
+                if (s >= ns) break;
+                const int r = r0 + s;
+                if (r > RO) part += st.G[r];
+                else part += (q > l) ? st.G[r] : 0.0;
+            }
+        }
+        if constexpr (!GIVEN) {
+            // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1)
+            if (l + 1 < P) {
+                if (q == l + 1 && f + 1 < nb) {
+                    const double inc = static_cast<double>(st.intra[RO]) * Xf;
+                    st.G[RO] += inc;
+                    part += inc;
+                }
+            } else if constexpr (RO + 1 < R) {
+                if (q == 0 && f + 1 < nb) {
+                    const double inc = static_cast<double>(st.intra[RO + 1]) * Xf;
+                    st.G[RO + 1] += inc;
+                    part += inc;
+                }
+            }
+        }
+        st.part = part;
+    }
+}
+
+template <int P, int R, int KG, bool GIVEN, int... RO>
+__device__ __forceinline__ void all_columns(Rec<R>& st, const StepEnv& e, std::integer_sequence<int, RO...>) {
+    (column_block<P, R, KG, GIVEN, RO>(st, e), ...);
+}
+
 struct KArgs {
     const double* u;
     const double* lam;
     int L;
-    int tabstride;
+    int tabstride;             // floats per pair in LDS: the log2 table and its 3 sentinels, padded
     float dlam2;               // log2(lambda_(j+1) / lambda_j)
     int n_cells;
     int n_gslots;
@@ -108,7 +338,7 @@ struct KArgs {
     int n_pairs;
 };
 
-template <int P, int R, int WAVES, bool GIVEN>
+template <int P, int R, int KG, int WAVES, bool GIVEN>
 __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     constexpr int PPW = 64 / P;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -142,11 +372,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
 
     if constexpr (!GIVEN) {
         const int L = a.L;
-        tab = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride;
+        // log2 table with sentinels: tab[-1], tab[L], tab[L+1] hold kNoField
+        tab = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride + 1;
+        float* cum = tab;       // pass 1 keeps Cum where pass 2 later writes the log2 table
         for (int d = threadIdx.x; d < nb; d += 64 * WAVES) dpar_s[d] = gv.dpar[d];
 
         // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
-        // (trapezoid), FP64, chunked over the segment's lanes.
+        // (trapezoid), FP64, chunked over the segment's lanes; kept normalised by
+        // the total in FP32.
         const double* uc = a.u + static_cast<size_t>(cellc) * L;
         const int cs = (L + P - 1) / P;
         const int j0 = q * cs;
@@ -166,13 +399,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         total = seg_sum<P>(csum);
         const double inv_total = total > 0.0 ? 1.0 / total : 0.0;
         if (j0 < j1) {
-            double cum = carry;
+            double c = carry;
             double rho_n = (j1 < L) ? kLight * clean_field(uc[j1], bad) * gv.cabs[j1] : 0.0;
             for (int j = j1 - 1; j >= j0; --j) {
                 const double rho = kLight * clean_field(uc[j], bad) * gv.cabs[j];
-                if (j + 1 < L) cum += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
+                if (j + 1 < L) c += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
                 rho_n = rho;
-                tab[j] = static_cast<float>(cum * inv_total);
+                cum[j] = static_cast<float>(c * inv_total);
             }
         }
         __syncthreads();
@@ -185,7 +418,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             if (k >= 1 && k < nb) {
                 const int js = gv.jstar[k - 1];
                 if (js < L && total > 0.0)
-                    intra[r] = static_cast<float>(static_cast<double>(tab[js]) * total * gv.invgap[k - 1]);
+                    intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
             }
         }
         __syncthreads();
@@ -209,11 +442,16 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             const float v = tab[j];
             tab[j] = (v > kNoField) ? v - off : kNoField;
         }
-        if (q == 0) tab[L] = kNoField;
+        if (q == 0) {
+            tab[-1] = kNoField;
+            tab[L] = kNoField;
+            tab[L + 1] = kNoField;
+        }
+        // rows past the top bin: a sentinel exponent, so their rates are 0
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int k = r * P + q;
-            gm[r] = (k < nb) ? static_cast<float>(gv.gam[k] + static_cast<double>(off)) : 0.0f;
+            gm[r] = (k < nb) ? static_cast<float>(gv.gam[k] + static_cast<double>(off)) : kNoField;
         }
         __syncthreads();
     } else {
@@ -225,101 +463,31 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     }
 
     // ---- recursion ----
-    double G[R];
+    Rec<R> st;
 #pragma unroll
-    for (int r = 0; r < R; ++r) G[r] = 0.0;
-    double part = 0.0;
-    int nres = 0;
-    const double* Ap = nullptr;
-    const double* cp = nullptr;
+    for (int r = 0; r < R; ++r) {
+        st.G[r] = 0.0;
+        st.gm[r] = gm[r];
+        st.intra[r] = intra[r];
+    }
+    st.part = 0.0;
+    st.nres = 0;
+    StepEnv env;
+    env.q = q;
+    env.nb = nb;
+    env.Lm1 = a.L - 1;
+    env.colpar = gv.colpar;
+    env.dpar = dpar_s;
+    env.tab = tab;
     if constexpr (GIVEN) {
-        Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
-        cp = a.cool + static_cast<size_t>(cellc) * nb;
+        env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
+        env.cp = a.cool + static_cast<size_t>(cellc) * nb;
+    } else {
+        st.cnext = load_colpar(gv.colpar, 0);
     }
-
-#pragma unroll
-    for (int ro = 0; ro < R; ++ro) {
-        if (ro * P < nb) {
-            for (int l = 0; l < P; ++l) {
-                const int f = ro * P + l;
-                if (f >= nb) break;
-                double Xf = 1.0;
-                if (f > 0) {
-                    const double S = seg_sum<P>(part);
-                    if constexpr (GIVEN) Xf = S / cp[f];
-                    else Xf = S * gv.colpar[f].invcool;
-                }
-                if (Xf > kBig) {
-                    Xf *= kShrink;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) G[r] *= kShrink;
-                    ++nres;
-                }
-                if (q == l) G[ro] = Xf;
-
-                int kb, ke, ia = 0;
-                float fa = 0.0f;
-                if constexpr (GIVEN) {
-                    kb = f + 1;
-                    ke = nb - 1;
-                } else {
-                    const ColPar c = gv.colpar[f];
-                    kb = max(c.kb, f + 1);
-                    ke = c.ke;
-                    ia = c.ia;
-                    fa = c.fa;
-                }
-                part = 0.0;
-#pragma unroll
-                for (int r = ro; r < R; ++r) {
-                    const int kbase = r * P;
-                    if (kbase < nb) {
-                        const bool first = (r == ro);
-                        const int k = kbase + q;
-                        if (kbase + P - 1 >= kb && kbase <= ke) {
-                            const bool whole = !first && kbase >= kb && kbase + P - 1 <= ke;
-                            const bool on = whole || ((k >= kb) && (k <= ke) && (!first || q > l));
-                            if (on) {
-                                double A;
-                                if constexpr (GIVEN) {
-                                    A = Ap[static_cast<size_t>(k) * nb + f];
-                                } else {
-                                    const DPar dp = dpar_s[k - f];
-                                    int jlo;
-                                    float w;
-                                    transition_index(ia, fa, dp.nib, dp.fb, jlo, w);
-                                    // kb..ke already keep jlo in [0, L-1]; the clamp is a
-                                    // single v_med3 and guards the LDS read regardless
-                                    jlo = min(max(jlo, 0), a.L - 1);
-                                    const float lo = tab[jlo];
-                                    const float hi = tab[jlo + 1];
-                                    const float x = fmaf(w, hi - lo, lo) + gm[r];
-                                    A = static_cast<double>(__builtin_amdgcn_exp2f(x));
-                                }
-                                G[r] = fma(A, Xf, G[r]);
-                            }
-                        }
-                        if (!first || q > l) part += G[r];
-                    }
-                }
-                if constexpr (!GIVEN) {
-                    if (l + 1 < P) {
-                        if (q == l + 1 && f + 1 < nb) {
-                            const double inc = static_cast<double>(intra[ro]) * Xf;
-                            G[ro] += inc;
-                            part += inc;
-                        }
-                    } else if (ro + 1 < R) {
-                        if (q == 0 && f + 1 < nb) {
-                            const double inc = static_cast<double>(intra[ro + 1]) * Xf;
-                            G[ro + 1] += inc;
-                            part += inc;
-                        }
-                    }
-                }
-            }
-        }
-    }
+    all_columns<P, R, KG, GIVEN>(st, env, std::make_integer_sequence<int, R>{});
+    double* G = st.G;
+    const int nres = st.nres;
 
     // ---- normalisation (eq:renormalization) and outputs ----
     double sx = 0.0, mxx = 0.0;
@@ -368,9 +536,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
 }
 
 template <int P, int R, int WAVES>
-hipError_t launch_phys(const KArgs& ka, int n_items, hipStream_t s) {
+hipError_t launch_phys(const KArgs& ka, int n_items, int kg, hipStream_t s) {
     const size_t lds = sizeof(DPar) * R * P + sizeof(float) * static_cast<size_t>(WAVES) * (64 / P) * ka.tabstride;
-    hipLaunchKernelGGL((k_solve<P, R, WAVES, false>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+    if (kg == 4)
+        hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, false>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+    else
+        hipLaunchKernelGGL((k_solve<P, R, 2, WAVES, false>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
     return hipGetLastError();
 }
 
@@ -378,7 +549,7 @@ template <int P, int R, int WAVES>
 hipError_t launch_given(const KArgs& ka, int n_pairs, hipStream_t s) {
     const int per_block = WAVES * (64 / P);
     const int blocks = (n_pairs + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_solve<P, R, WAVES, true>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
+    hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, true>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
     return hipGetLastError();
 }
 
@@ -399,7 +570,7 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const i
     ka.u = sl.u;
     ka.lam = c.lam;
     ka.L = c.L;
-    ka.tabstride = (c.L + 2 + 1) & ~1;
+    ka.tabstride = (c.L + 3 + 3) & ~3;
     ka.dlam2 = static_cast<float>(c.dlnlam / std::log(2.0));
     ka.n_cells = sl.n_cells;
     ka.n_gslots = sl.n_gslots;
@@ -411,10 +582,14 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const i
     ka.P64 = sl.P64;
     ka.errword = sl.errword;
     ka.items = items_dev;
-    if (nb_max <= 128) return launch_phys<16, 8, kWaves>(ka, n_items, s);
-    if (nb_max <= 256) return launch_phys<16, 16, kWaves>(ka, n_items, s);
-    if (nb_max <= 512) return launch_phys<32, 16, kWaves>(ka, n_items, s);
-    return launch_phys<64, 16, kWaves>(ka, n_items, s);
+    static const int kg = [] {
+        const char* v = std::getenv("HSD_KGROUP");
+        return (v && std::atoi(v) == 2) ? 2 : 4;
+    }();
+    if (nb_max <= 128) return launch_phys<16, 8, kWaves>(ka, n_items, kg, s);
+    if (nb_max <= 256) return launch_phys<16, 16, kWaves>(ka, n_items, kg, s);
+    if (nb_max <= 512) return launch_phys<32, 16, kWaves>(ka, n_items, kg, s);
+    return launch_phys<64, 16, kWaves>(ka, n_items, kg, s);
 }
 
 hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool, double* P,
@@ -425,6 +600,7 @@ hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A,
     ka.nb_given = nb;
     ka.n_pairs = n_pairs;
     ka.P64 = P;
+    ka.L = 1;
     if (nb <= 128) return launch_given<16, 8, kWaves>(ka, n_pairs, s);
     if (nb <= 256) return launch_given<16, 16, kWaves>(ka, n_pairs, s);
     if (nb <= 512) return launch_given<32, 16, kWaves>(ka, n_pairs, s);
