@@ -76,7 +76,7 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     int nb_hi = 0;
     for (int g = 0; g < n_grains; ++g) {
         const Grain& gr = c.grains[ids[g]];
-        hsd::GrainView v{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.cabs, gr.n_bins, 0};
+        hsd::GrainView v{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs, gr.n_bins, 0};
         ctx->views_h[g] = v;
         ctx->offs_h[g] = rows;
         rows += static_cast<long long>(n_cells) * gr.n_bins;
@@ -142,12 +142,8 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     }
     if (c.timing) HSD_HIP(ctx, hipEventRecord(c.ev[2], s));
     if (diag && j) {
-        for (int g = 0; g < n_grains; ++g) {
-            const Grain& gr = c.grains[ids[g]];
-            hsd::DiagLaunch dl{u, gr.cabs, c.lam, gr.jrep, c.Pt + ctx->offs_h[g], c.pscale, j, diag, n_cells,
-                               gr.n_bins, c.L, n_grains, g};
-            HSD_HIP(ctx, hsd::launch_diag(dl, s));
-        }
+        hsd::DiagLaunch dl{c.lam, j, diag, n_cells, c.L, n_grains};
+        HSD_HIP(ctx, hsd::launch_diag(dl, s));
     }
     if (c.timing) {
         HSD_HIP(ctx, hipEventRecord(c.ev[3], s));

@@ -1,4 +1,4 @@
-// Emission contraction and per-pair energy diagnostics.
+// Emission contraction and the emitted-power diagnostic.
 //
 // j[c, g, lambda] = C_abs(lambda) sum_i P_i B_lambda(T_i) [E_i >= hc/lambda]
 // (Sec. 2.3, eq:emission with eq:emission-lambda) is, for one grain g and all
@@ -86,58 +86,20 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
     }
 }
 
-// Energy bookkeeping of one pair per wavefront: emitted power 4 pi int j dlambda
-// and the representable absorbed power A_rep = sum_i P_i Cum_(jrep(i)), with
-// Cum_j = int_{lambda_j} c u C_abs dlambda (trapezoid), all in FP64.
+// Emitted power of each pair, 4 pi int j dlambda (trapezoid, FP64 sum), one
+// 16-lane segment per pair; the other diagnostics come from the solver.
 __global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
-    extern __shared__ double cum_s[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int cell_raw = blockIdx.x * 4 + wave;
-    const bool valid = cell_raw < a.n_cells;
-    const int cell = valid ? cell_raw : a.n_cells - 1;   // dead waves still reach the barriers
-    const int L = a.L;
-    double* cum = cum_s + wave * (L + 1);
-    const size_t pair = static_cast<size_t>(cell) * a.n_gslots + a.gslot;
-    const float* jr = a.j + pair * L;
+    const int lane = threadIdx.x & 15;
+    const size_t pair = static_cast<size_t>(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const size_t n_pairs = static_cast<size_t>(a.n_cells) * a.n_gslots;
+    const bool valid = pair < n_pairs;
+    const float* jr = a.j + (valid ? pair : 0) * a.L;
     double em = 0.0;
-    for (int j = lane; j + 1 < L; j += 64) em += 0.5 * (static_cast<double>(jr[j]) + jr[j + 1]) * (a.lam[j + 1] - a.lam[j]);
-    const double* uc = a.u + static_cast<size_t>(cell) * L;
-    // segment integrals, then a serial suffix sum per 64-entry chunk and chunk carries
-    for (int j = lane; j < L; j += 64) {
-        double s = 0.0;
-        if (j + 1 < L) {
-            const double u0 = uc[j] >= 0.0 && uc[j] < INFINITY ? uc[j] : 0.0;
-            const double u1 = uc[j + 1] >= 0.0 && uc[j + 1] < INFINITY ? uc[j + 1] : 0.0;
-            s = 0.5 * kLight * (u0 * a.cabs[j] + u1 * a.cabs[j + 1]) * (a.lam[j + 1] - a.lam[j]);
-        }
-        cum[j] = s;
-    }
-    __syncthreads();
-    if (lane == 0) {
-        double run = 0.0;
-        cum[L] = 0.0;
-        for (int j = L - 1; j >= 0; --j) {
-            run += cum[j];
-            cum[j] = run;
-        }
-    }
-    __syncthreads();
-    const float* prow = a.Pt + static_cast<size_t>(cell) * a.nb;
-    const double ps = a.pscale[pair];
-    double ar = 0.0;
-    for (int i = lane; i < a.nb; i += 64) {
-        const int jr_i = a.jrep[i];
-        ar += static_cast<double>(prow[i]) * ps * cum[jr_i < L ? jr_i : L];
-    }
+    for (int j = lane; j + 1 < a.L; j += 16)
+        em += 0.5 * (static_cast<double>(jr[j]) + jr[j + 1]) * (a.lam[j + 1] - a.lam[j]);
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        em += __shfl_xor(em, m, 64);
-        ar += __shfl_xor(ar, m, 64);
-    }
-    if (lane == 0 && valid) {
-        a.diag[pair * 4 + 1] = static_cast<float>(4.0 * kPi * em);
-        a.diag[pair * 4 + 2] = static_cast<float>(ar);
-    }
+    for (int m = 1; m < 16; m <<= 1) em += __shfl_xor(em, m, 16);
+    if (lane == 0 && valid) a.diag[pair * 4 + 1] = static_cast<float>(4.0 * kPi * em);
 }
 
 }  // namespace
@@ -150,9 +112,9 @@ hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s) {
-    if (a.n_cells <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * 4 * (a.L + 1);
-    hipLaunchKernelGGL(k_diag, dim3((a.n_cells + 3) / 4), dim3(256), lds, s, a);
+    const size_t n_pairs = static_cast<size_t>(a.n_cells) * a.n_gslots;
+    if (n_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag, dim3(static_cast<unsigned>((n_pairs + 15) / 16)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

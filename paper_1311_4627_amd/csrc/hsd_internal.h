@@ -65,6 +65,7 @@ struct GrainView {
     const double* gam;
     const double* invgap;
     const int* jstar;
+    const int* jrep;
     const double* cabs;
     int nb;
     int pad;
@@ -133,15 +134,10 @@ struct ContractLaunch {
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
 
 struct DiagLaunch {
-    const double* u;
-    const double* cabs;
     const double* lam;
-    const int* jrep;
-    const float* Pt;          // slot rows
-    const float* pscale;
-    const float* j;
-    float* diag;
-    int n_cells, nb, L, n_gslots, gslot;
+    const float* j;           // [n_cells][n_gslots][L]
+    float* diag;              // [n_cells][n_gslots][4]; writes entry 1
+    int n_cells, L, n_gslots;
 };
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
 

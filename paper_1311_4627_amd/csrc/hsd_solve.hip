@@ -365,6 +365,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
 
     float gm[R];
     float intra[R];
+    float rep[R];      // representable absorbed power from each row's bin, / total
     double total = 0.0;
     bool bad = false;
     DPar* dpar_s = reinterpret_cast<DPar*>(smem);
@@ -420,6 +421,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
                 if (js < L && total > 0.0)
                     intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
             }
+            rep[r] = 0.0f;
+            if (k < nb) {
+                const int jr = gv.jrep[k];
+                if (jr < L) rep[r] = cum[jr];
+            }
         }
         __syncthreads();
         // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off, off = the
@@ -459,6 +465,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         for (int r = 0; r < R; ++r) {
             gm[r] = 0.0f;
             intra[r] = 0.0f;
+            rep[r] = 0.0f;
         }
     }
 
@@ -490,17 +497,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     const int nres = st.nres;
 
     // ---- normalisation (eq:renormalization) and outputs ----
-    double sx = 0.0, mxx = 0.0;
+    double sx = 0.0, mxx = 0.0, srep = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int k = r * P + q;
         if (k < nb) {
             sx += G[r];
             mxx = fmax(mxx, G[r]);
+            srep += G[r] * static_cast<double>(rep[r]);
         }
     }
     sx = seg_sum<P>(sx);
     mxx = seg_max<P>(mxx);
+    srep = seg_sum<P>(srep);
     const double x0 = __shfl(G[0], seg * P, 64);
     bad = seg_maxf<P>(bad ? 1.0f : 0.0f) > 0.0f;
     if (!live) return;
@@ -528,6 +537,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             const unsigned flags = (sx == x0 ? 1u : 0u) | (nres > 0 ? 2u : 0u) | (bad ? 4u : 0u);
             if (a.diag) {
                 a.diag[pair * 4 + 0] = static_cast<float>(total);
+                a.diag[pair * 4 + 2] = static_cast<float>(total * (srep / sx));
                 a.diag[pair * 4 + 3] = static_cast<float>(flags);
             }
             if (bad && a.errword) atomicOr(a.errword, 1u);
