@@ -76,7 +76,8 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     int nb_hi = 0;
     for (int g = 0; g < n_grains; ++g) {
         const Grain& gr = c.grains[ids[g]];
-        hsd::GrainView v{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs, gr.n_bins, 0};
+        hsd::GrainView v{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs,
+                         std::pow(gr.E_hi / gr.E_lo, 1.0 / (gr.n_bins - 1)), gr.n_bins, 0};
         ctx->views_h[g] = v;
         ctx->offs_h[g] = rows;
         rows += static_cast<long long>(n_cells) * gr.n_bins;

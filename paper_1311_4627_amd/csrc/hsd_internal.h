@@ -33,10 +33,14 @@ struct alignas(32) ColPar {
 };
 
 // Interpolation constants of a transition distance d = f - i: grid
-// coordinate b_d = ln(r^d - 1) / dln(lambda) split as -floor and fraction.
-struct alignas(8) DPar {
+// coordinate b_d = ln(r^d - 1) / dln(lambda) split as -floor and fraction, and
+// the distance's share d log2(r) of the log2 rate (the upper bin's width grows
+// by r per bin).
+struct alignas(16) DPar {
     int nib;          // -floor(b_d)
     float fb;         // b_d - floor(b_d), in [0, 1)
+    float dlr;        // d log2(r)
+    int pad;
 };
 
 // Device tables of one registered grain (all owned by the context).
@@ -67,6 +71,7 @@ struct GrainView {
     const int* jstar;
     const int* jrep;
     const double* cabs;
+    double rbin;      // r = E_(i+1) / E_i
     int nb;
     int pad;
 };

@@ -170,45 +170,115 @@ __device__ __forceinline__ double clean_field(double u, bool& bad) {
 template <int R>
 struct Rec {
     double G[R];       // inflow G(k) of the lane's rows, then X_k once row k is passed
-    float gm[R];       // gamma_k of the rows (with the pair's table offset)
-    float intra[R];    // continuous-heating rate into each row from the row below
+    float intra[R];    // continuous-heating rate into each row from the row below (register variant)
     double part;       // this lane's share of sum_{k >= f} G(k) for the next step
+    double cf;         // 2^(gamma_f + off): the column's share of the rate factor
     int nres;          // rescales so far
     ColPar cnext;      // prefetched parameters of the next column
 };
 
 struct StepEnv {
     int q, nb, Lm1;
+    int s0;            // row k sits at position k + s0 (s0 = R P - nb): the tail slot holds the top bin
+    double rbin;       // cf grows by r per column
+    double total;      // the pair's absorbed power (Cum_0)
     const ColPar* colpar;
     const DPar* dpar;  // LDS
     const float* tab;  // LDS, this pair's log2 table
+    const float* cum;  // LDS, this pair's Cum / total (LDS-table variant)
     const double* Ap;  // given-rates hook: this pair's rate matrix
     const double* cp;  // given-rates hook: this pair's cooling rates
 };
 
-// Rate of the transition column f -> row k (k in the column's grid-resident
-// range unless MASKED, where out-of-range lanes read clamped addresses and the
-// caller discards their value).
+// Per-step values the slot groups need.
+struct StepState {
+    int pf, l, kb, ke;     // column position pf = f + s0, lane of the diagonal, grid-resident rows (positions)
+    double Xg;         // X_f times the column's rate factor
+    int ia;
+    float fa;
+};
+
+// One group of KG row slots starting at slot R0 (>= RO) for step f: rates of
+// the column into the group's rows, the FP64 update G += A X, and the group's
+// share of the next suffix sum.  Straight-line, so the group's LDS reads are
+// in flight together; skipped by a wave-uniform test when none of its rows is
+// grid-resident for this column.
+template <int P, int R, int KG, bool GIVEN, int RO, int R0>
+__device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const StepState& ss, double& part) {
+    constexpr int NS = (R - R0) < KG ? (R - R0) : KG;
+    const int q = e.q, nb = e.nb;
+    const int lo_pos = R0 * P, hi_pos = (R0 + NS) * P - 1;
+    if (hi_pos >= ss.kb && lo_pos <= ss.ke) {
+        double A[NS];
+        if constexpr (GIVEN) {
+            const int f = ss.pf - e.s0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int pos = (R0 + s) * P + q;
+                const int k = min(max(pos - e.s0, 0), nb - 1);
+                const double v = e.Ap[static_cast<size_t>(k) * nb + f];
+                A[s] = (pos >= ss.kb && pos <= ss.ke) ? v : 0.0;
+            }
+        } else {
+            DPar dp[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int d = (R0 + s) * P + q - ss.pf;
+                dp[s] = e.dpar[R0 + s == RO ? max(d, 0) : d];
+            }
+            float t0[NS], t1[NS], w[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                int jlo;
+                transition_index(ss.ia, ss.fa, dp[s].nib, dp[s].fb, jlo, w[s]);
+                jlo = min(max(jlo, -1), e.Lm1 + 1);
+                t0[s] = e.tab[jlo];
+                t1[s] = e.tab[jlo + 1];
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                A[s] = static_cast<double>(__builtin_amdgcn_exp2f(fmaf(w[s], t1[s] - t0[s], t0[s]) + dp[s].dlr));
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) st.G[R0 + s] = fma(A[s], ss.Xg, st.G[R0 + s]);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (R0 + s == RO) part += (q > ss.l) ? st.G[R0 + s] : 0.0;
+        else part += st.G[R0 + s];
+    }
+}
+
+template <int P, int R, int KG, bool GIVEN, int RO, int... G>
+__device__ __forceinline__ void all_groups(Rec<R>& st, const StepEnv& e, const StepState& ss, double& part,
+                                           std::integer_sequence<int, G...>) {
+    (slot_group<P, R, KG, GIVEN, RO, RO + G * KG>(st, e, ss, part), ...);
+}
+
 // All steps f = RO*P .. RO*P + P - 1 (the columns whose rows sit in slot RO).
 // Slots below RO are finished and untouched; slot RO holds the diagonal.
 //
-// Rates need no per-lane masks on the physical path: the log2 table carries a
-// non-field sentinel one entry below lambda_0 and two above lambda_(L-1), the
-// interval index is clamped into [-1, L], distance 0 (rows at or below the
-// diagonal) maps far below the grid, and rows past the grain's top bin carry a
-// sentinel gamma, so every transition off the wavelength grid evaluates to
-// exp2(-1e30-ish) = 0 exactly.  Slots are handled KG at a time as straight-line
-// code, so the LDS reads of a group are in flight together; a group wholly
-// outside the column's grid-resident rows kb..ke is skipped by a wave-uniform
-// test.
-template <int P, int R, int KG, bool GIVEN, int RO>
+// The rate of column f into row k = f + d is
+//     A = exp2(tab[jlo] + w (tab[jlo+1] - tab[jlo]) + d log2 r) * cf,
+// cf = 2^(gamma_f + off) in FP64 (grown by r per column), folded into X_f.
+// Rates need no per-lane masks: the log2 table carries a non-field sentinel
+// one entry below lambda_0 and two above lambda_(L-1), the interval index is
+// clamped into [-1, L], and distance 0 (rows at or below the diagonal) maps far
+// below the grid, so every transition off the wavelength grid evaluates to
+// exp2(-1e30-ish) = 0 exactly.  Rows past the grain's top bin (the tail of the
+// last slot) collect junk that is never summed or written.  Slots are handled
+// KG at a time as straight-line code, so the LDS reads of a group are in
+// flight together; a group wholly outside the column's grid-resident rows
+// kb..ke is skipped by a wave-uniform test.
+template <int P, int R, int KG, bool GIVEN, bool LDSCUM, int RO>
 __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
-    const int q = e.q, nb = e.nb;
-    if (RO * P >= nb) return;
+    const int q = e.q, nb = e.nb, s0 = e.s0;
+    if (RO * P + P - 1 < s0) return;          // only positions below row 0
 #pragma unroll 1
     for (int l = 0; l < P; ++l) {
-        const int f = RO * P + l;
-        if (f >= nb) break;
+        const int pf = RO * P + l;
+        const int f = pf - s0;
+        if (f < 0) continue;
         ColPar cc{};
         if constexpr (!GIVEN) {
             cc = st.cnext;
@@ -228,79 +298,42 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
         }
         if (q == l) st.G[RO] = Xf;
         int kb, ke;
+        double Xg = Xf;
         if constexpr (GIVEN) {
-            kb = f + 1;
-            ke = nb - 1;
+            kb = pf + 1;
+            ke = nb - 1 + s0;
         } else {
-            kb = max(cc.kb, f + 1);
-            ke = cc.ke;
+            kb = max(cc.kb + s0, pf + 1);
+            ke = cc.ke + s0;
+            Xg = Xf * st.cf;
+            st.cf *= e.rbin;
         }
         double part = 0.0;
-#pragma unroll
-        for (int r0 = RO; r0 < R; r0 += KG) {
-            const int ns = (R - r0) < KG ? (R - r0) : KG;
-            const int lo_row = r0 * P, hi_row = (r0 + ns) * P - 1;
-            if (lo_row >= nb) break;
-            if (hi_row >= kb && lo_row <= ke) {
-                double A[KG];
-                if constexpr (GIVEN) {
-#pragma unroll
-                    for (int s = 0; s < KG; ++s) {
-                        if (s >= ns) break;
-                        const int k = (r0 + s) * P + q;
-                        const double v = e.Ap[static_cast<size_t>(min(k, nb - 1)) * nb + f];
-                        A[s] = (k >= kb && k <= ke) ? v : 0.0;
-                    }
-                } else {
-                    DPar dp[KG];
-#pragma unroll
-                    for (int s = 0; s < KG; ++s) {
-                        if (s >= ns) break;
-                        const int d = (r0 + s) * P + q - f;
-                        dp[s] = e.dpar[r0 + s == RO ? max(d, 0) : d];
-                    }
-                    float t0[KG], t1[KG], w[KG];
-#pragma unroll
-                    for (int s = 0; s < KG; ++s) {
-                        if (s >= ns) break;
-                        int jlo;
-                        transition_index(cc.ia, cc.fa, dp[s].nib, dp[s].fb, jlo, w[s]);
-                        jlo = min(max(jlo, -1), e.Lm1 + 1);
-                        t0[s] = e.tab[jlo];
-                        t1[s] = e.tab[jlo + 1];
-                    }
-#pragma unroll
-                    for (int s = 0; s < KG; ++s) {
-                        if (s >= ns) break;
-                        A[s] = static_cast<double>(
-                            __builtin_amdgcn_exp2f(fmaf(w[s], t1[s] - t0[s], t0[s]) + st.gm[r0 + s]));
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < KG; ++s) {
-                    if (s >= ns) break;
-                    st.G[r0 + s] = fma(A[s], Xf, st.G[r0 + s]);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < KG; ++s) {
-                if (s >= ns) break;
-                const int r = r0 + s;
-                if (r > RO) part += st.G[r];
-                else part += (q > l) ? st.G[r] : 0.0;
-            }
-        }
+        StepState ss{pf, l, kb, ke, Xg, cc.ia, cc.fa};
+        all_groups<P, R, KG, GIVEN, RO>(st, e, ss, part, std::make_integer_sequence<int, (R - RO + KG - 1) / KG>{});
         if constexpr (!GIVEN) {
             // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1)
+            double cin = 0.0;
+            if constexpr (LDSCUM) {
+                cin = (cc.jstar <= e.Lm1) ? static_cast<double>(e.cum[cc.jstar]) * e.total *
+                                                static_cast<double>(cc.invgap)
+                                          : 0.0;
+            }
             if (l + 1 < P) {
                 if (q == l + 1 && f + 1 < nb) {
-                    const double inc = static_cast<double>(st.intra[RO]) * Xf;
+                    double c;
+                    if constexpr (LDSCUM) c = cin;
+                    else c = static_cast<double>(st.intra[RO]);
+                    const double inc = c * Xf;
                     st.G[RO] += inc;
                     part += inc;
                 }
             } else if constexpr (RO + 1 < R) {
                 if (q == 0 && f + 1 < nb) {
-                    const double inc = static_cast<double>(st.intra[RO + 1]) * Xf;
+                    double c;
+                    if constexpr (LDSCUM) c = cin;
+                    else c = static_cast<double>(st.intra[RO + 1]);
+                    const double inc = c * Xf;
                     st.G[RO + 1] += inc;
                     part += inc;
                 }
@@ -310,16 +343,16 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
     }
 }
 
-template <int P, int R, int KG, bool GIVEN, int... RO>
+template <int P, int R, int KG, bool GIVEN, bool LDSCUM, int... RO>
 __device__ __forceinline__ void all_columns(Rec<R>& st, const StepEnv& e, std::integer_sequence<int, RO...>) {
-    (column_block<P, R, KG, GIVEN, RO>(st, e), ...);
+    (column_block<P, R, KG, GIVEN, LDSCUM, RO>(st, e), ...);
 }
 
 struct KArgs {
     const double* u;
     const double* lam;
     int L;
-    int tabstride;             // floats per pair in LDS: the log2 table and its 3 sentinels, padded
+    int tabstride;             // floats per pair in LDS (log2 table with sentinels, then Cum), padded
     float dlam2;               // log2(lambda_(j+1) / lambda_j)
     int n_cells;
     int n_gslots;
@@ -338,7 +371,11 @@ struct KArgs {
     int n_pairs;
 };
 
-template <int P, int R, int KG, int WAVES, bool GIVEN>
+// LDSCUM: the pair's Cum table stays in LDS for the whole solve (the
+// continuous-heating and representable-power terms read it), instead of
+// being folded into per-row registers; chosen for the large bin counts, where
+// registers are scarcer than LDS.
+template <int P, int R, int KG, int WAVES, bool GIVEN, bool LDSCUM>
 __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     constexpr int PPW = 64 / P;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -363,19 +400,26 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     const bool live = cell < n_live;
     const int cellc = live ? cell : 0;
 
-    float gm[R];
-    float intra[R];
-    float rep[R];      // representable absorbed power from each row's bin, / total
+    Rec<R> st;
+    float rep[R];      // representable absorbed power from each row's bin, / total (register variant)
     double total = 0.0;
+    double cf0 = 1.0;
     bool bad = false;
     DPar* dpar_s = reinterpret_cast<DPar*>(smem);
     float* tab = nullptr;
+    float* cum = nullptr;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        st.intra[r] = 0.0f;
+        rep[r] = 0.0f;
+    }
 
     if constexpr (!GIVEN) {
         const int L = a.L;
         // log2 table with sentinels: tab[-1], tab[L], tab[L+1] hold kNoField
-        tab = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride + 1;
-        float* cum = tab;       // pass 1 keeps Cum where pass 2 later writes the log2 table
+        float* base = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride;
+        tab = base + 1;
+        cum = LDSCUM ? base + (L + 3) : tab;   // else pass 2 overwrites Cum with the log2 table
         for (int d = threadIdx.x; d < nb; d += 64 * WAVES) dpar_s[d] = gv.dpar[d];
 
         // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
@@ -410,26 +454,26 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             }
         }
         __syncthreads();
-        // Continuous heating of row k from column k-1 (Draine & Li intrabin
-        // term): absorbed power of photons too soft for the step, per unit step.
+        if constexpr (!LDSCUM) {
+            // Continuous heating of row k from column k-1 (Draine & Li intrabin
+            // term): absorbed power of photons too soft for the step, per unit step.
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k = r * P + q;
-            intra[r] = 0.0f;
-            if (k >= 1 && k < nb) {
-                const int js = gv.jstar[k - 1];
-                if (js < L && total > 0.0)
-                    intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
+            for (int r = 0; r < R; ++r) {
+                const int k = r * P + q - (R * P - nb);
+                if (k >= 1 && k < nb) {
+                    const int js = gv.jstar[k - 1];
+                    if (js < L && total > 0.0)
+                        st.intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
+                }
+                if (k >= 0 && k < nb) {
+                    const int jr = gv.jrep[k];
+                    if (jr < L) rep[r] = cum[jr];
+                }
             }
-            rep[r] = 0.0f;
-            if (k < nb) {
-                const int jr = gv.jrep[k];
-                if (jr < L) rep[r] = cum[jr];
-            }
+            __syncthreads();
         }
-        __syncthreads();
         // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off, off = the
-        // pair's largest entry (kept in gamma, so the exponent stays small).
+        // pair's largest entry (restored through cf, so the exponent stays small).
         float mx = -INFINITY;
         for (int j = q; j < L; j += P) {
             const double om = clean_field(uc[j], bad) * gv.cabs[j];
@@ -453,72 +497,65 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             tab[L] = kNoField;
             tab[L + 1] = kNoField;
         }
-        // rows past the top bin: a sentinel exponent, so their rates are 0
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k = r * P + q;
-            gm[r] = (k < nb) ? static_cast<float>(gv.gam[k] + static_cast<double>(off)) : kNoField;
-        }
+        cf0 = exp2(gv.gam[0] + static_cast<double>(off));
         __syncthreads();
-    } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            gm[r] = 0.0f;
-            intra[r] = 0.0f;
-            rep[r] = 0.0f;
-        }
     }
 
     // ---- recursion ----
-    Rec<R> st;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        st.G[r] = 0.0;
-        st.gm[r] = gm[r];
-        st.intra[r] = intra[r];
-    }
+    for (int r = 0; r < R; ++r) st.G[r] = 0.0;
     st.part = 0.0;
     st.nres = 0;
+    st.cf = cf0;
     StepEnv env;
     env.q = q;
     env.nb = nb;
+    env.s0 = R * P - nb;
     env.Lm1 = a.L - 1;
+    env.rbin = gv.rbin;
+    env.total = total;
     env.colpar = gv.colpar;
     env.dpar = dpar_s;
     env.tab = tab;
+    env.cum = cum;
     if constexpr (GIVEN) {
         env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
         env.cp = a.cool + static_cast<size_t>(cellc) * nb;
     } else {
         st.cnext = load_colpar(gv.colpar, 0);
     }
-    all_columns<P, R, KG, GIVEN>(st, env, std::make_integer_sequence<int, R>{});
+    all_columns<P, R, KG, GIVEN, LDSCUM>(st, env, std::make_integer_sequence<int, R>{});
     double* G = st.G;
     const int nres = st.nres;
 
     // ---- normalisation (eq:renormalization) and outputs ----
+    const int s0 = R * P - nb;
     double sx = 0.0, mxx = 0.0, srep = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int k = r * P + q;
-        if (k < nb) {
+        const int k = r * P + q - s0;
+        if (k >= 0) {
             sx += G[r];
             mxx = fmax(mxx, G[r]);
-            srep += G[r] * static_cast<double>(rep[r]);
+            float rv = rep[r];
+            if constexpr (LDSCUM && !GIVEN) {
+                const int jr = gv.jrep[k];
+                rv = jr < a.L ? cum[jr] : 0.0f;
+            }
+            srep += G[r] * static_cast<double>(rv);
         }
     }
     sx = seg_sum<P>(sx);
     mxx = seg_max<P>(mxx);
     srep = seg_sum<P>(srep);
-    const double x0 = __shfl(G[0], seg * P, 64);
     bad = seg_maxf<P>(bad ? 1.0f : 0.0f) > 0.0f;
     if (!live) return;
     if (a.P64) {
         double* prow = a.P64 + static_cast<size_t>(cell) * nb;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int k = r * P + q;
-            if (k < nb) prow[k] = G[r] / sx;
+            const int k = r * P + q - s0;
+            if (k >= 0) prow[k] = G[r] / sx;
         }
     }
     if constexpr (!GIVEN) {
@@ -527,14 +564,15 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             const double inv = 1.0 / mxx;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int k = r * P + q;
-                if (k < nb) prow[k] = static_cast<float>(G[r] * inv);
+                const int k = r * P + q - s0;
+                if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
             }
         }
         const size_t pair = static_cast<size_t>(cell) * a.n_gslots + gslot;
         if (q == 0) {
             if (a.pscale) a.pscale[pair] = static_cast<float>(mxx / sx);
-            const unsigned flags = (sx == x0 ? 1u : 0u) | (nres > 0 ? 2u : 0u) | (bad ? 4u : 0u);
+            // no heating term anywhere leaves X = (1, 0, ..., 0): the sum is exactly 1
+            const unsigned flags = (sx == 1.0 && nres == 0 ? 1u : 0u) | (nres > 0 ? 2u : 0u) | (bad ? 4u : 0u);
             if (a.diag) {
                 a.diag[pair * 4 + 0] = static_cast<float>(total);
                 a.diag[pair * 4 + 2] = static_cast<float>(total * (srep / sx));
@@ -545,13 +583,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
     }
 }
 
-template <int P, int R, int WAVES>
+template <int P, int R, int WAVES, bool LDSCUM>
 hipError_t launch_phys(const KArgs& ka, int n_items, int kg, hipStream_t s) {
     const size_t lds = sizeof(DPar) * R * P + sizeof(float) * static_cast<size_t>(WAVES) * (64 / P) * ka.tabstride;
     if (kg == 4)
-        hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, false>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+        hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, false, LDSCUM>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
     else
-        hipLaunchKernelGGL((k_solve<P, R, 2, WAVES, false>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+        hipLaunchKernelGGL((k_solve<P, R, 2, WAVES, false, LDSCUM>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
     return hipGetLastError();
 }
 
@@ -559,7 +597,7 @@ template <int P, int R, int WAVES>
 hipError_t launch_given(const KArgs& ka, int n_pairs, hipStream_t s) {
     const int per_block = WAVES * (64 / P);
     const int blocks = (n_pairs + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, true>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
+    hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, true, false>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
     return hipGetLastError();
 }
 
@@ -567,10 +605,16 @@ constexpr int kWaves = 4;
 
 }  // namespace
 
+// Bin-count classes: lanes per pair P and row slots per lane R (P R >= bins).
+//   <= 128 bins: P 16, R 8;  <= 256: P 16, R 16;  <= 512: P 32, R 16;
+//   <= 1024: P 32, R 32 with the Cum table kept in LDS.
 int solve_cells_per_item(int nb_max) {
     if (nb_max <= 256) return kWaves * 4;
-    if (nb_max <= 512) return kWaves * 2;
-    return kWaves;
+    if (nb_max > 512) {
+        const char* v = std::getenv("HSD_BIGCFG");
+        if (v && std::atoi(v) == 64) return kWaves;
+    }
+    return kWaves * 2;
 }
 
 hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const int2* items_dev, int n_items,
@@ -580,7 +624,6 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const i
     ka.u = sl.u;
     ka.lam = c.lam;
     ka.L = c.L;
-    ka.tabstride = (c.L + 3 + 3) & ~3;
     ka.dlam2 = static_cast<float>(c.dlnlam / std::log(2.0));
     ka.n_cells = sl.n_cells;
     ka.n_gslots = sl.n_gslots;
@@ -594,12 +637,24 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const i
     ka.items = items_dev;
     static const int kg = [] {
         const char* v = std::getenv("HSD_KGROUP");
-        return (v && std::atoi(v) == 2) ? 2 : 4;
+        return (v && std::atoi(v) == 4) ? 4 : 2;
     }();
-    if (nb_max <= 128) return launch_phys<16, 8, kWaves>(ka, n_items, kg, s);
-    if (nb_max <= 256) return launch_phys<16, 16, kWaves>(ka, n_items, kg, s);
-    if (nb_max <= 512) return launch_phys<32, 16, kWaves>(ka, n_items, kg, s);
-    return launch_phys<64, 16, kWaves>(ka, n_items, kg, s);
+    if (nb_max <= 512) {
+        ka.tabstride = (c.L + 3 + 3) & ~3;
+        if (nb_max <= 128) return launch_phys<16, 8, kWaves, false>(ka, n_items, kg, s);
+        if (nb_max <= 256) return launch_phys<16, 16, kWaves, false>(ka, n_items, kg, s);
+        return launch_phys<32, 16, kWaves, false>(ka, n_items, kg, s);
+    }
+    static const bool wide = [] {
+        const char* v = std::getenv("HSD_BIGCFG");
+        return v && std::atoi(v) == 64;
+    }();
+    if (wide) {
+        ka.tabstride = (c.L + 3 + 3) & ~3;
+        return launch_phys<64, 16, kWaves, false>(ka, n_items, kg, s);
+    }
+    ka.tabstride = (2 * c.L + 3 + 3) & ~3;
+    return launch_phys<32, 32, kWaves, true>(ka, n_items, kg, s);
 }
 
 hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool, double* P,
