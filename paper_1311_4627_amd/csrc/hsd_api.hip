@@ -104,8 +104,21 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
         std::stable_sort(slots.begin(), slots.end(), [&](int x, int y) {
             return c.grains[ids[x]].n_bins > c.grains[ids[y]].n_bins;
         });
-        for (int g : slots)
-            for (int c0 = 0; c0 < n_cells; c0 += cpi) ctx->items_h.push_back(make_int2(g, c0));
+        // Work items (slot, first cell).  Workgroups are dealt to the 8 XCDs
+        // round-robin by id, so item b runs on XCD b % 8: give each XCD whole
+        // cell blocks, all grains of a block in a row, so the block's field rows
+        // are fetched into that XCD's L2 once for every grain of the class.
+        const int nsl = static_cast<int>(slots.size());
+        const int ncb = (n_cells + cpi - 1) / cpi;
+        if (nsl > 0) {
+            const int ncb8 = (ncb + 7) / 8 * 8;
+            for (int b = 0; b < ncb8 * nsl; ++b) {
+                const int x = b % 8, m = b / 8;
+                const int cb = 8 * (m / nsl) + x;
+                if (cb >= ncb) continue;
+                ctx->items_h.push_back(make_int2(slots[m % nsl], cb * cpi));
+            }
+        }
     }
     cls_begin[4] = static_cast<int>(ctx->items_h.size());
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(ctx->items_h.size(), 1)));

@@ -30,8 +30,16 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
     __shared__ float Bs[BK][BN + BPAD];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int row0 = blockIdx.y * BM;          // first cell of the tile
-    const int col0 = blockIdx.x * BN;          // first wavelength of the tile
+    // Workgroup b runs on XCD b % 8; each XCD takes whole row tiles with all
+    // their wavelength tiles in a row, so a tile's P~ rows are read from HBM
+    // once and then served by that XCD's L2.
+    const int nlt = a.Lp / BN;
+    const int b = blockIdx.x;
+    const int m = b / 8;
+    const int rt = 8 * (m / nlt) + (b % 8);
+    if (rt * BM >= a.n_cells) return;          // padding tile: the whole block leaves before any barrier
+    const int row0 = rt * BM;                  // first cell of the tile
+    const int col0 = (m % nlt) * BN;           // first wavelength of the tile
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
@@ -106,8 +114,8 @@ __global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
 
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
     if (a.n_cells <= 0) return hipSuccess;
-    dim3 grid(a.Lp / BN, (a.n_cells + BM - 1) / BM);
-    hipLaunchKernelGGL(k_contract, grid, dim3(256), 0, s, a);
+    const int nrt8 = ((a.n_cells + BM - 1) / BM + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_contract, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
