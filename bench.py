@@ -12,8 +12,11 @@ diagnostics stay on the device.  Prints one JSON line.
 The roofline object covers the dominant phase (the fused rates/recursion
 kernels), timed with HIP events on the solve's stream inside the timed steps.
 Its bound is the transcendental pipe: every upward rate needs one v_exp_f32,
-which issues at a quarter of the FP32 rate, so the chip evaluates at most
-256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz = 9.83e12 rates/s.
+which issues at a quarter of the FP32 FMA rate (157.3 TFLOP/s = 78.6e12 FMA/s),
+so the chip evaluates at most 19.66e12 rates/s.  The HBM traffic of that phase
+comes from the rocprofv3 FETCH_SIZE/WRITE_SIZE summary committed under
+profiles/, and is reported only while the solver sources still hash to the
+values recorded there.
 
 The CPU baseline is the FP64 oracle timed on the host cores over a bounded,
 stratified sample of the same workload (a few cells times every radius); the
@@ -41,7 +44,34 @@ import synth  # noqa: E402
 from synth.fields import make_fields  # noqa: E402
 
 METRIC = "emissivity solves/s (cell×grain) at 1e-4 rel err; surrogate vs plain speedup"
-EXP2_PEAK = 256 * 4 * 16 / 4 * 2.4e9        # v_exp_f32 issues per second on MI355X
+EXP2_PEAK = 157.3e12 / 2 / 4                 # v_exp_f32 per second: a quarter of the FP32 FMA rate
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_c2_hbm_traffic.md")
+SOLVER_SOURCES = ["paper_1311_4627_amd/csrc/hsd_solve.hip", "paper_1311_4627_amd/csrc/hsd_index.h",
+                  "paper_1311_4627_amd/csrc/hsd_internal.h"]
+
+
+def solver_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOLVER_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per solve phase from the committed counter summary, or None
+    when the summary is missing or was taken on other solver sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("solver_sources_sha256_16:"):
+            vals["hash"] = line.split(":", 1)[1].strip()
+        if line.startswith("solve_phase_hbm_bytes_per_step:"):
+            vals["bytes"] = float(line.split(":", 1)[1].strip())
+    if vals.get("hash") != solver_hash() or "bytes" not in vals:
+        return None
+    return vals["bytes"]
 
 
 def _oracle_task(args):
@@ -176,7 +206,7 @@ def main():
                    "bins": f"{max(g.n_bins for g in w.grains)}..{min(g.n_bins for g in w.grains)} "
                            f"(sum {sum(g.n_bins for g in w.grains)})"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": EXP2_PEAK / 1e12, "unit": "Texp2/s",
-                     "frac": achieved / EXP2_PEAK, "traffic": None,
+                     "frac": achieved / EXP2_PEAK, "traffic": recorded_traffic(),
                      "kernel": "fused rates/recursion (k_solve)", "kernel_ms": phase[0],
                      "rates_per_launch": rates_per_step},
         "phases_ms": {"solve": phase[0], "contract": phase[1], "diag": phase[2]},
