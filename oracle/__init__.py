@@ -26,9 +26,9 @@ approximation):
   eq:level-sum) as an independent check at small bin counts;
 * energy-balance diagnostics.
 
-Every floating-point step is IEEE double precision.  The readings of garbled
-or ambiguous passages are listed in the design doc (readings R1..R12) and cited
-at the functions that use them.
+Every floating-point step is IEEE double precision.  Each reading of a
+garbled or ambiguous passage carries a label (R1..R12) and is stated at the
+function that uses it.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, special cases, brute force or invariants; none is
