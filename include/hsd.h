@@ -60,6 +60,7 @@ typedef enum {
 } hsd_status;
 
 typedef struct hsd_ctx hsd_ctx;
+typedef struct hsd_plan hsd_plan;
 
 /* One grain size of one composition (the paper's GrainModel row plus the
  * engine's enthalpy grid, appendix on the library interface). */
@@ -77,7 +78,7 @@ typedef struct {
 
 /* Create a context on HIP device `device` for the wavelength grid
  * lambda_host[0..n_lambda-1] (cm, strictly increasing, log-uniform to 1e-9
- * relative, 16 <= n_lambda <= 2048).  Rates are evaluated at arbitrary
+ * relative, 16 <= n_lambda <= 1024).  Rates are evaluated at arbitrary
  * wavelengths by the closed-form grid index of a log-uniform grid; another
  * grid gives HSD_ERR_UNSUPPORTED_GRID.  *out receives the context. */
 hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambda, hsd_ctx** out);
@@ -155,6 +156,83 @@ hsd_status hsd_sync(hsd_ctx* ctx);
  * synchronisation to hsd_solve itself. */
 hsd_status hsd_set_timing(hsd_ctx* ctx, int32_t enable);
 hsd_status hsd_phase_ms(hsd_ctx* ctx, double* ms_host);
+
+/* ---- Launch configuration (read and set by the autotuner) ----
+ * The solver groups grains into four bin-count classes, each served by its
+ * own kernel shape: class 0 holds 513..1024 bins, class 1 257..512, class 2
+ * 129..256 and class 3 16..128.  Per class:
+ *   kg          row slots evaluated per straight-line group: 2 or 4;
+ *   wide        class 0 only: 0 = 32 lanes per pair with 32 row slots each
+ *               and the absorbed-power table in LDS, 1 = 64 lanes per pair
+ *               with 16 row slots each;
+ *   persistent  0 = one workgroup per work item (items in an order that
+ *               gives each XCD whole cell blocks), 1 = a grid of the
+ *               workgroups that fit on the device at once, fed items longest
+ *               first from an atomic counter.
+ * kg and persistent change speed only: the results are the same bit for bit.
+ * wide also changes the order of the FP64 sums, so results agree to rounding.
+ * The defaults are kg 2, wide 0, persistent 0.  Synchronous; affects later
+ * solves and later plans. */
+typedef struct {
+    int32_t kg;
+    int32_t wide;
+    int32_t persistent;
+} hsd_class_cfg;
+hsd_status hsd_get_class_cfg(hsd_ctx* ctx, int32_t cls, hsd_class_cfg* cfg_host);
+hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg_host);
+
+/* ---- Autotuner ----
+ * Time every configuration of every bin-count class that the listed grains
+ * occupy, on the given batch, and keep the fastest per class in the context
+ * (later solves and plans use it).  Each configuration runs the solver phase
+ * (rates, sums, recursion, scaled-P writes; no contraction) `runs` times on an
+ * internal stream; the first run is a warm-up and the mean of the others is
+ * the score (the paper's benchmarks time 4 runs and average the last 3, Sec. 3).  The
+ * paper picks its tile sizes by measurement in the same way (appendix on loop
+ * tiling).  One record per configuration timed is written to
+ * records_host[0..max_records-1]; *n_records receives the number timed.
+ * Synchronous; grows the context's workspace. */
+typedef struct {
+    int32_t cls;             /* bin-count class */
+    hsd_class_cfg cfg;       /* configuration timed */
+    int32_t n_grains;        /* grains of the batch in this class */
+    double ms;               /* mean solver-phase time of the timed runs */
+} hsd_tune_record;
+hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                        const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
+                        int32_t max_records, int32_t* n_records);
+
+/* ---- Plans: a batch captured once as a HIP graph ----
+ * The paper keeps its data resident on the coprocessor and reuses it across
+ * calls (appendix on offload traffic reduction); a plan does the same for a
+ * batch whose shape and buffers do not change: hsd_plan_create records every
+ * launch of one hsd_solve of (n_cells, u_dev, grain_ids_host, j_dev, diag_dev)
+ * - the solver classes (fields are read directly by the solver, no separate
+ * ingest pass), the contractions and the diagnostics - into one HIP graph,
+ * with its own workspace, using the class configurations current at creation.
+ * hsd_plan_launch replays it on `stream`; each replay computes exactly what
+ * hsd_solve would on the buffers' contents at that time.
+ *   flags  HSD_PLAN_TIMING: each phase (solver, contraction, diagnostics)
+ *          is captured as a graph of its own, and hsd_plan_launch records HIP
+ *          events between the three graph launches on `stream`;
+ *          hsd_plan_phase_ms waits for the last launch and writes the phases'
+ *          milliseconds to ms_host[0..2].
+ *          HSD_PLAN_CONCURRENT: the solver classes run as parallel branches
+ *          of the graph, so one class's tail overlaps the next class.
+ * The buffers must stay allocated, and the grains registered, while the plan
+ * lives.  A plan is used by one thread at a time; replays of one plan on
+ * different streams must not overlap (they share its workspace).
+ * hsd_plan_create allocates the workspace and synchronises; hsd_plan_launch
+ * allocates nothing.  hsd_plan_destroy waits for the device and frees the
+ * plan (NULL is ignored); destroy plans before their context. */
+#define HSD_PLAN_TIMING 1
+#define HSD_PLAN_CONCURRENT 2
+hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                           const int32_t* grain_ids_host, float* j_dev, float* diag_dev, int32_t flags,
+                           hsd_plan** out);
+hsd_status hsd_plan_launch(hsd_plan* plan, void* stream);
+hsd_status hsd_plan_phase_ms(hsd_plan* plan, double* ms_host);
+void hsd_plan_destroy(hsd_plan* plan);
 
 #ifdef __cplusplus
 }

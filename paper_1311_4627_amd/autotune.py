@@ -1,0 +1,56 @@
+"""Autotuner front end: cached launch configurations of the solver classes.
+
+The timing itself runs natively (hsd_autotune in the C ABI: every
+configuration of every occupied bin-count class is timed on the caller's
+batch, first run discarded, the rest averaged).  This module caches the
+winners as JSON, keyed by the device, the wavelength count, the bin counts of
+the grains in each class and the batch size, so that a later run on the same
+kind of batch applies them without timing again.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Optional, Sequence
+
+from . import hsd
+
+
+def batch_key(ctx: "hsd.Context", grain_ids: Sequence[int], n_cells: int, device_name: str) -> str:
+    bins = sorted(ctx.n_bins[g] for g in grain_ids)
+    per_class = []
+    for lo, hi in hsd.CLASS_BINS:
+        per_class.append([b for b in bins if lo <= b <= hi])
+    return json.dumps({"device": device_name, "L": ctx.L, "n_cells": int(n_cells), "bins": per_class},
+                      sort_keys=True)
+
+
+def _load(path: str) -> Dict[str, dict]:
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def tune(ctx: "hsd.Context", u, grain_ids: Sequence[int], cache_path: Optional[str] = None,
+         runs: int = 4, force: bool = False) -> dict:
+    """Apply the cached configuration of this batch's key, or time and cache
+    it.  Returns {"key", "cached", "cfg": [per class], "records": [...]}."""
+    import torch
+    key = batch_key(ctx, grain_ids, int(u.shape[0]), torch.cuda.get_device_name(u.device))
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        entry = cache[key]
+        for cls, cfg in enumerate(entry["cfg"]):
+            ctx.hsd_set_class_cfg(cls, **cfg)
+        return {"key": key, "cached": True, "cfg": entry["cfg"], "records": entry.get("records", [])}
+    records: List[dict] = ctx.hsd_autotune(u, grain_ids, runs=runs)
+    cfg = [ctx.hsd_get_class_cfg(c) for c in range(hsd.N_CLASSES)]
+    if cache_path:
+        cache[key] = {"cfg": cfg, "records": records}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return {"key": key, "cached": False, "cfg": cfg, "records": records}

@@ -13,11 +13,42 @@
 using hsd::Ctx;
 using hsd::Grain;
 
+// Host-side description of one batch: per-slot grain views and row offsets in
+// the scaled-P workspace, and the work items of each bin-count class.
+struct Batch {
+    std::vector<hsd::GrainView> views;
+    std::vector<long long> offs;
+    std::vector<int2> items;
+    int cls_begin[hsd::kClasses + 1] = {0, 0, 0, 0, 0};
+    long long rows = 0;
+};
+
 struct hsd_ctx {
     Ctx c;
-    std::vector<hsd::GrainView> views_h;
-    std::vector<long long> offs_h;
-    std::vector<int2> items_h;
+    Batch batch;     // host description of the last eager solve
+};
+
+// A batch bound to fixed buffers, captured once as a HIP graph.
+struct hsd_plan {
+    hsd_ctx* ctx = nullptr;
+    int32_t n_cells = 0, n_grains = 0;
+    std::vector<int32_t> ids;
+    Batch b;
+    float* Pt = nullptr;
+    float* pscale = nullptr;
+    hsd::GrainView* views = nullptr;
+    long long* offs = nullptr;
+    int2* items = nullptr;
+    unsigned* queue = nullptr;
+    hipStream_t cap = nullptr;
+    hipStream_t side[hsd::kClasses] = {};
+    hipEvent_t sev[hsd::kClasses + 1] = {};
+    hipEvent_t ev[4] = {};
+    bool timing = false;
+    bool launched = false;
+    int n_graphs = 0;                 // 1, or 3 (one per phase) with timing
+    hipGraph_t graph[3] = {};
+    hipGraphExec_t exec[3] = {};
 };
 
 namespace {
@@ -65,105 +96,159 @@ bool grain_ok(const hsd_ctx* ctx, int32_t id) {
     return id >= 0 && static_cast<size_t>(id) < ctx->c.grains.size();
 }
 
-// Solve launches shared by hsd_solve and hsd_solve_P.
-hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_grains, const int32_t* ids,
-                     float* j, float* diag, double* P64, hipStream_t s) {
-    Ctx& c = ctx->c;
-    // per-slot row offsets in the scaled-P workspace
-    ctx->views_h.resize(n_grains);
-    ctx->offs_h.resize(n_grains);
-    long long rows = 0;
-    int nb_hi = 0;
+void plan_batch(const Ctx& c, int32_t n_cells, int32_t n_grains, const int32_t* ids, Batch& b) {
+    b.views.resize(n_grains);
+    b.offs.resize(n_grains);
+    b.items.clear();
+    b.rows = 0;
     for (int g = 0; g < n_grains; ++g) {
         const Grain& gr = c.grains[ids[g]];
-        hsd::GrainView v{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs,
-                         std::pow(gr.E_hi / gr.E_lo, 1.0 / (gr.n_bins - 1)), gr.n_bins, 0};
-        ctx->views_h[g] = v;
-        ctx->offs_h[g] = rows;
-        rows += static_cast<long long>(n_cells) * gr.n_bins;
-        nb_hi = std::max(nb_hi, gr.n_bins);
+        b.views[g] = hsd::GrainView{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs,
+                                    std::pow(gr.E_hi / gr.E_lo, 1.0 / (gr.n_bins - 1)), gr.n_bins, 0};
+        b.offs[g] = b.rows;
+        b.rows += static_cast<long long>(n_cells) * gr.n_bins;
     }
-    const bool want_pt = (j != nullptr) || (diag != nullptr);
-    if (want_pt) HSD_HIP(ctx, grow(c.Pt, c.Pt_cap, static_cast<size_t>(rows)));
-    HSD_HIP(ctx, grow(c.pscale, c.pscale_cap, static_cast<size_t>(n_cells) * n_grains));
-    HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
-    HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
-    // work items: bin-count classes, longest first; within a class slots in order
-    static const int class_hi[4] = {1024, 512, 256, 128};
-    static const int class_lo[4] = {512, 256, 128, 0};
-    ctx->items_h.clear();
-    std::vector<int> cls_begin(5, 0);
-    for (int ci = 0; ci < 4; ++ci) {
-        cls_begin[ci] = static_cast<int>(ctx->items_h.size());
-        const int cpi = hsd::solve_cells_per_item(class_hi[ci]);
+    for (int ci = 0; ci < hsd::kClasses; ++ci) {
+        b.cls_begin[ci] = static_cast<int>(b.items.size());
+        const int hi = hsd::kClassHi[ci];
+        const int lo = ci + 1 < hsd::kClasses ? hsd::kClassHi[ci + 1] : 0;
+        const int cpi = hsd::solve_cells_per_item(c.cfg[ci], ci);
         std::vector<int> slots;
         for (int g = 0; g < n_grains; ++g) {
             const int nb = c.grains[ids[g]].n_bins;
-            if (nb > class_lo[ci] && nb <= class_hi[ci]) slots.push_back(g);
+            if (nb > lo && nb <= hi) slots.push_back(g);
         }
-        std::stable_sort(slots.begin(), slots.end(), [&](int x, int y) {
-            return c.grains[ids[x]].n_bins > c.grains[ids[y]].n_bins;
-        });
-        // Work items (slot, first cell).  Workgroups are dealt to the 8 XCDs
-        // round-robin by id, so item b runs on XCD b % 8: give each XCD whole
-        // cell blocks, all grains of a block in a row, so the block's field rows
-        // are fetched into that XCD's L2 once for every grain of the class.
         const int nsl = static_cast<int>(slots.size());
+        if (nsl == 0) continue;
         const int ncb = (n_cells + cpi - 1) / cpi;
-        if (nsl > 0) {
+        if (c.cfg[ci].persistent) {
+            // Atomic queue: items longest first (cost grows as bins^2), so the
+            // last items dealt out are the cheapest and the tail is short; one
+            // grain's cell blocks in a row.
+            std::stable_sort(slots.begin(), slots.end(), [&](int x, int y) {
+                return c.grains[ids[x]].n_bins > c.grains[ids[y]].n_bins;
+            });
+            for (int g : slots)
+                for (int cb = 0; cb < ncb; ++cb) b.items.push_back(make_int2(g, cb * cpi));
+        } else {
+            // One item per workgroup.  Workgroups are dealt to the 8 XCDs
+            // round-robin by id, so item k runs on XCD k % 8: give each XCD
+            // whole cell blocks, all grains of a block in a row, so the block's
+            // field rows are fetched into that XCD's L2 once for every grain
+            // of the class.
             const int ncb8 = (ncb + 7) / 8 * 8;
-            for (int b = 0; b < ncb8 * nsl; ++b) {
-                const int x = b % 8, m = b / 8;
+            for (int k = 0; k < ncb8 * nsl; ++k) {
+                const int x = k % 8, m = k / 8;
                 const int cb = 8 * (m / nsl) + x;
                 if (cb >= ncb) continue;
-                ctx->items_h.push_back(make_int2(slots[m % nsl], cb * cpi));
+                b.items.push_back(make_int2(slots[m % nsl], cb * cpi));
             }
         }
     }
-    cls_begin[4] = static_cast<int>(ctx->items_h.size());
-    HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(ctx->items_h.size(), 1)));
-    HSD_HIP(ctx, hipMemcpyAsync(c.views, ctx->views_h.data(), sizeof(hsd::GrainView) * n_grains,
-                                hipMemcpyHostToDevice, s));
-    HSD_HIP(ctx, hipMemcpyAsync(c.offs, ctx->offs_h.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
-    if (!ctx->items_h.empty())
-        HSD_HIP(ctx, hipMemcpyAsync(c.items, ctx->items_h.data(), sizeof(int2) * ctx->items_h.size(),
-                                    hipMemcpyHostToDevice, s));
+    b.cls_begin[hsd::kClasses] = static_cast<int>(b.items.size());
+}
+
+// Device buffers one batch runs on (the context's workspace, or a plan's own).
+struct Bufs {
+    float* Pt;
+    float* pscale;
+    hsd::GrainView* views;
+    long long* offs;
+    int2* items;
+    unsigned* queue;     // kClasses counters
+};
+
+struct Events {
+    hipEvent_t ev[4];    // phase boundaries, or null
+};
+
+hipError_t record(const Events& t, int i, hipStream_t s) {
+    if (!t.ev[i]) return hipSuccess;
+    return hipEventRecord(t.ev[i], s);
+}
+
+// Enqueue the whole batch on stream s: the solver classes (on the side
+// streams, in parallel, when `side` is given), then the per-grain
+// contractions and the diagnostics.
+constexpr int kPhaseSolve = 1, kPhaseContract = 2, kPhaseDiag = 4, kPhaseAll = 7;
+
+hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells, const double* u, int32_t n_grains,
+                   const int32_t* ids, float* j, float* diag, double* P64, hipStream_t s, const Events& t,
+                   hipStream_t* side, hipEvent_t* sev, int phases = kPhaseAll) {
+    Ctx& c = ctx->c;
     hsd::SolveLaunch sl{};
     sl.u = u;
     sl.n_cells = n_cells;
     sl.n_gslots = n_grains;
-    sl.views = c.views;
-    sl.offs = c.offs;
-    sl.Pt = want_pt ? c.Pt : nullptr;
-    sl.pscale = c.pscale;
+    sl.views = d.views;
+    sl.offs = d.offs;
+    sl.Pt = d.Pt;
+    sl.pscale = d.pscale;
     sl.diag = diag;
     sl.P64 = P64;
     sl.errword = c.errword;
-    if (c.timing) HSD_HIP(ctx, hipEventRecord(c.ev[0], s));
-    for (int ci = 0; ci < 4; ++ci) {
-        const int n_it = cls_begin[ci + 1] - cls_begin[ci];
-        if (n_it == 0) continue;
-        HSD_HIP(ctx, hsd::launch_solve(c, sl, class_hi[ci], c.items + cls_begin[ci], n_it, 0, s));
+    HSD_HIP(ctx, record(t, 0, s));
+    if (!(phases & kPhaseSolve)) {
+    } else if (side) {
+        HSD_HIP(ctx, hipEventRecord(sev[0], s));
+        for (int ci = 0; ci < hsd::kClasses; ++ci) {
+            const int n_it = b.cls_begin[ci + 1] - b.cls_begin[ci];
+            if (n_it == 0) continue;
+            HSD_HIP(ctx, hipStreamWaitEvent(side[ci], sev[0], 0));
+            HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, d.items + b.cls_begin[ci], n_it, d.queue + ci, side[ci]));
+            HSD_HIP(ctx, hipEventRecord(sev[1 + ci], side[ci]));
+            HSD_HIP(ctx, hipStreamWaitEvent(s, sev[1 + ci], 0));
+        }
+    } else {
+        for (int ci = 0; ci < hsd::kClasses; ++ci) {
+            const int n_it = b.cls_begin[ci + 1] - b.cls_begin[ci];
+            if (n_it == 0) continue;
+            HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, d.items + b.cls_begin[ci], n_it, d.queue + ci, s));
+        }
     }
-    if (c.timing) HSD_HIP(ctx, hipEventRecord(c.ev[1], s));
-    if (j) {
+    HSD_HIP(ctx, record(t, 1, s));
+    if (j && (phases & kPhaseContract)) {
         for (int g = 0; g < n_grains; ++g) {
             const Grain& gr = c.grains[ids[g]];
-            hsd::ContractLaunch cl{c.Pt + ctx->offs_h[g], c.pscale, gr.Bt, gr.bscale, j, n_cells, gr.n_bins,
+            hsd::ContractLaunch cl{d.Pt + b.offs[g], d.pscale, gr.Bt, gr.bscale, j, n_cells, gr.n_bins,
                                    c.L, c.Lp, n_grains, g};
             HSD_HIP(ctx, hsd::launch_contract(cl, s));
         }
     }
-    if (c.timing) HSD_HIP(ctx, hipEventRecord(c.ev[2], s));
-    if (diag && j) {
+    HSD_HIP(ctx, record(t, 2, s));
+    if (diag && j && (phases & kPhaseDiag)) {
         hsd::DiagLaunch dl{c.lam, j, diag, n_cells, c.L, n_grains};
         HSD_HIP(ctx, hsd::launch_diag(dl, s));
     }
-    if (c.timing) {
-        HSD_HIP(ctx, hipEventRecord(c.ev[3], s));
-        c.timed = true;
-    }
+    HSD_HIP(ctx, record(t, 3, s));
     return HSD_OK;
+}
+
+// Eager solve on the context's workspace (hsd_solve and hsd_solve_P).
+hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_grains, const int32_t* ids,
+                     float* j, float* diag, double* P64, hipStream_t s, bool keep_pt = false) {
+    Ctx& c = ctx->c;
+    Batch& b = ctx->batch;
+    plan_batch(c, n_cells, n_grains, ids, b);
+    const bool want_pt = keep_pt || (j != nullptr) || (diag != nullptr);
+    if (want_pt) HSD_HIP(ctx, grow(c.Pt, c.Pt_cap, static_cast<size_t>(b.rows)));
+    HSD_HIP(ctx, grow(c.pscale, c.pscale_cap, static_cast<size_t>(n_cells) * n_grains));
+    HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
+    HSD_HIP(ctx, hipMemcpyAsync(c.views, b.views.data(), sizeof(hsd::GrainView) * n_grains,
+                                hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(c.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
+    if (!b.items.empty())
+        HSD_HIP(ctx, hipMemcpyAsync(c.items, b.items.data(), sizeof(int2) * b.items.size(),
+                                    hipMemcpyHostToDevice, s));
+    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue};
+    Events t{{nullptr, nullptr, nullptr, nullptr}};
+    if (c.timing)
+        for (int i = 0; i < 4; ++i) t.ev[i] = c.ev[i];
+    hsd_status st = enqueue(ctx, b, d, n_cells, u, n_grains, ids, j, diag, P64, s, t, nullptr, nullptr);
+    if (st == HSD_OK && c.timing) c.timed = true;
+    return st;
 }
 
 }  // namespace
@@ -198,15 +283,20 @@ hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambd
     c.dlnlam = dl;
     c.lam_host.assign(lambda_host, lambda_host + n_lambda);
     if (hipMalloc(&c.lam, sizeof(double) * n_lambda) != hipSuccess ||
-        hipMalloc(&c.errword, sizeof(unsigned)) != hipSuccess) {
+        hipMalloc(&c.errword, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c.queue, sizeof(unsigned) * hsd::kClasses) != hipSuccess) {
         hipFree(c.lam);
+        hipFree(c.errword);
+        hipFree(c.queue);
         delete ctx;
         return HSD_ERR_OOM;
     }
     if (hipMemcpy(c.lam, lambda_host, sizeof(double) * n_lambda, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c.errword, 0, sizeof(unsigned)) != hipSuccess) {
+        hipMemset(c.errword, 0, sizeof(unsigned)) != hipSuccess ||
+        hipMemset(c.queue, 0, sizeof(unsigned) * hsd::kClasses) != hipSuccess) {
         hipFree(c.lam);
         hipFree(c.errword);
+        hipFree(c.queue);
         delete ctx;
         return HSD_ERR_HIP;
     }
@@ -222,6 +312,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     for (auto& g : c.grains) free_grain(g);
     hipFree(c.lam);
     hipFree(c.errword);
+    hipFree(c.queue);
     hipFree(c.Pt);
     hipFree(c.pscale);
     hipFree(c.diag_tmp);
@@ -329,6 +420,247 @@ hsd_status hsd_solve_from_rates(hsd_ctx* ctx, int32_t n_bins, int32_t n_pairs, c
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
     HSD_HIP(ctx, hsd::launch_from_rates(ctx->c, n_bins, n_pairs, A_dev, cool_dev, P_dev,
                                         static_cast<hipStream_t>(stream)));
+    return HSD_OK;
+}
+
+hsd_status hsd_get_class_cfg(hsd_ctx* ctx, int32_t cls, hsd_class_cfg* out) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!out || cls < 0 || cls >= hsd::kClasses) return fail(ctx, HSD_ERR_INVALID_ARG, "bad class or null output");
+    const hsd::ClassCfg& k = ctx->c.cfg[cls];
+    out->kg = k.kg;
+    out->wide = k.wide;
+    out->persistent = k.persistent;
+    return HSD_OK;
+}
+
+hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!cfg || cls < 0 || cls >= hsd::kClasses) return fail(ctx, HSD_ERR_INVALID_ARG, "bad class or null config");
+    if (cfg->kg != 2 && cfg->kg != 4) return fail(ctx, HSD_ERR_INVALID_ARG, "kg must be 2 or 4");
+    if (cfg->wide != 0 && (cfg->wide != 1 || cls != 0))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "wide is 0 or 1, and 1 only for class 0");
+    if (cfg->persistent != 0 && cfg->persistent != 1) return fail(ctx, HSD_ERR_INVALID_ARG, "persistent is 0 or 1");
+    hsd::ClassCfg& k = ctx->c.cfg[cls];
+    k.kg = cfg->kg;
+    k.wide = cfg->wide;
+    k.persistent = cfg->persistent;
+    return HSD_OK;
+}
+
+hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                        const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
+                        int32_t max_records, int32_t* n_records) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells <= 0 || n_grains <= 0 || runs < 2) return fail(ctx, HSD_ERR_INVALID_ARG, "need n_cells, n_grains > 0 and runs >= 2");
+    if (!u_dev || !grain_ids_host || !n_records || (max_records > 0 && !records_host))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    *n_records = 0;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hsd_status st = HSD_OK;
+    hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    const bool was_timing = c.timing;
+    c.timing = false;
+    for (int ci = 0; ci < hsd::kClasses && he == hipSuccess && st == HSD_OK; ++ci) {
+        const int hi = hsd::kClassHi[ci];
+        const int lo = ci + 1 < hsd::kClasses ? hsd::kClassHi[ci + 1] : 0;
+        std::vector<int32_t> ids;
+        for (int g = 0; g < n_grains; ++g) {
+            const int nb = c.grains[grain_ids_host[g]].n_bins;
+            if (nb > lo && nb <= hi) ids.push_back(grain_ids_host[g]);
+        }
+        if (ids.empty()) continue;
+        const hsd::ClassCfg keep = c.cfg[ci];
+        hsd::ClassCfg best = keep;
+        double best_ms = 1e300;
+        for (int wide = 0; wide <= (ci == 0 ? 1 : 0) && st == HSD_OK; ++wide)
+            for (int pers = 0; pers <= 1 && st == HSD_OK; ++pers)
+                for (int kg = 2; kg <= 4 && st == HSD_OK; kg += 2) {
+                    c.cfg[ci] = hsd::ClassCfg{kg, wide, pers};
+                    double sum = 0.0;
+                    for (int r = 0; r < runs && he == hipSuccess && st == HSD_OK; ++r) {
+                        he = hipEventRecord(e0, s);
+                        if (he != hipSuccess) break;
+                        st = run_solve(ctx, n_cells, u_dev, static_cast<int32_t>(ids.size()), ids.data(), nullptr,
+                                       nullptr, nullptr, s, true);
+                        if (st != HSD_OK) break;
+                        he = hipEventRecord(e1, s);
+                        if (he == hipSuccess) he = hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                        if (r > 0) sum += ms;      // the first run is a warm-up
+                    }
+                    if (he != hipSuccess || st != HSD_OK) break;
+                    const double mean = sum / (runs - 1);
+                    if (*n_records < max_records) {
+                        hsd_tune_record& rec = records_host[*n_records];
+                        rec.cls = ci;
+                        rec.cfg = hsd_class_cfg{kg, wide, pers};
+                        rec.n_grains = static_cast<int32_t>(ids.size());
+                        rec.ms = mean;
+                    }
+                    ++*n_records;
+                    if (mean < best_ms) {
+                        best_ms = mean;
+                        best = c.cfg[ci];
+                    }
+                }
+        c.cfg[ci] = (he == hipSuccess && st == HSD_OK) ? best : keep;
+    }
+    c.timing = was_timing;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (s) hipStreamDestroy(s);
+    if (st != HSD_OK) return st;
+    if (he != hipSuccess) return hip_fail(ctx, he, "hsd_autotune");
+    return HSD_OK;
+}
+
+void hsd_plan_destroy(hsd_plan* p) {
+    if (!p) return;
+    hipSetDevice(p->ctx->c.device);
+    hipDeviceSynchronize();
+    for (int i = 0; i < 3; ++i) {
+        if (p->exec[i]) hipGraphExecDestroy(p->exec[i]);
+        if (p->graph[i]) hipGraphDestroy(p->graph[i]);
+    }
+    for (auto& e : p->ev)
+        if (e) hipEventDestroy(e);
+    for (auto& e : p->sev)
+        if (e) hipEventDestroy(e);
+    for (auto& st : p->side)
+        if (st) hipStreamDestroy(st);
+    if (p->cap) hipStreamDestroy(p->cap);
+    hipFree(p->Pt);
+    hipFree(p->pscale);
+    hipFree(p->views);
+    hipFree(p->offs);
+    hipFree(p->items);
+    hipFree(p->queue);
+    delete p;
+}
+
+hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                           const int32_t* grain_ids_host, float* j_dev, float* diag_dev, int32_t flags,
+                           hsd_plan** out) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (n_cells <= 0 || n_grains <= 0) return fail(ctx, HSD_ERR_INVALID_ARG, "a plan needs n_cells > 0 and n_grains > 0");
+    if (!u_dev || !grain_ids_host || !j_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    if (flags & ~(HSD_PLAN_TIMING | HSD_PLAN_CONCURRENT)) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown flag");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    hsd_plan* p = new (std::nothrow) hsd_plan();
+    if (!p) return fail(ctx, HSD_ERR_OOM, "host allocation");
+    p->ctx = ctx;
+    p->n_cells = n_cells;
+    p->n_grains = n_grains;
+    p->ids.assign(grain_ids_host, grain_ids_host + n_grains);
+    p->timing = (flags & HSD_PLAN_TIMING) != 0;
+    plan_batch(c, n_cells, n_grains, p->ids.data(), p->b);
+    hipError_t e = hipSuccess;
+    auto al = [&](auto*& ptr, size_t count) {
+        if (e == hipSuccess) e = hipMalloc(&ptr, std::max<size_t>(count, 1) * sizeof(*ptr));
+    };
+    al(p->Pt, static_cast<size_t>(p->b.rows));
+    al(p->pscale, static_cast<size_t>(n_cells) * n_grains);
+    al(p->views, static_cast<size_t>(n_grains));
+    al(p->offs, static_cast<size_t>(n_grains));
+    al(p->items, p->b.items.size());
+    al(p->queue, static_cast<size_t>(hsd::kClasses));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->views, p->b.views.data(), sizeof(hsd::GrainView) * n_grains, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->offs, p->b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->b.items.empty())
+        e = hipMemcpy(p->items, p->b.items.data(), sizeof(int2) * p->b.items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->queue, 0, sizeof(unsigned) * hsd::kClasses);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    const bool conc = (flags & HSD_PLAN_CONCURRENT) != 0;
+    for (int i = 0; conc && i < hsd::kClasses && e == hipSuccess; ++i)
+        e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking);
+    for (int i = 0; conc && i <= hsd::kClasses && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&p->sev[i], hipEventDisableTiming);
+    for (int i = 0; p->timing && i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&p->ev[i]);
+    // persistent grid sizes come from occupancy queries: make them before the capture
+    for (int ci = 0; ci < hsd::kClasses && e == hipSuccess; ++ci)
+        if (c.cfg[ci].persistent && hsd::solve_capacity(c, ci) <= 0) e = hipErrorInvalidValue;
+    if (e != hipSuccess) {
+        hsd_plan_destroy(p);
+        return hip_fail(ctx, e, "hsd_plan_create");
+    }
+    Bufs d{p->Pt, p->pscale, p->views, p->offs, p->items, p->queue};
+    const Events none{{nullptr, nullptr, nullptr, nullptr}};
+    // Without timing the whole batch is one graph.  With timing, each phase
+    // is a graph of its own and the launch records the phase events between
+    // them on the caller's stream.
+    static const int whole[1] = {kPhaseAll};
+    static const int split[3] = {kPhaseSolve, kPhaseContract, kPhaseDiag};
+    p->n_graphs = p->timing ? 3 : 1;
+    for (int gi = 0; gi < p->n_graphs; ++gi) {
+        e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            hsd_plan_destroy(p);
+            return hip_fail(ctx, e, "hipStreamBeginCapture");
+        }
+        const int phases = p->timing ? split[gi] : whole[0];
+        const hsd_status st = enqueue(ctx, p->b, d, n_cells, u_dev, n_grains, p->ids.data(), j_dev, diag_dev,
+                                      nullptr, p->cap, none, conc ? p->side : nullptr, p->sev, phases);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->cap, &g);
+        p->graph[gi] = g;
+        if (st != HSD_OK) {
+            hsd_plan_destroy(p);
+            return st;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec[gi], p->graph[gi], nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hsd_plan_destroy(p);
+            return hip_fail(ctx, e, "graph capture");
+        }
+    }
+    *out = p;
+    return HSD_OK;
+}
+
+hsd_status hsd_plan_launch(hsd_plan* p, void* stream) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    if (p->timing) {
+        for (int gi = 0; gi < 3; ++gi) {
+            HSD_HIP(ctx, hipEventRecord(p->ev[gi], s));
+            HSD_HIP(ctx, hipGraphLaunch(p->exec[gi], s));
+        }
+        HSD_HIP(ctx, hipEventRecord(p->ev[3], s));
+    } else {
+        HSD_HIP(ctx, hipGraphLaunch(p->exec[0], s));
+    }
+    p->launched = true;
+    return HSD_OK;
+}
+
+hsd_status hsd_plan_phase_ms(hsd_plan* p, double* ms) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!ms) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    if (!p->timing || !p->launched) return fail(ctx, HSD_ERR_STATE, "plan made without timing, or never launched");
+    HSD_HIP(ctx, hipEventSynchronize(p->ev[3]));
+    for (int i = 0; i < 3; ++i) {
+        float t = 0.f;
+        HSD_HIP(ctx, hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
+        ms[i] = t;
+    }
     return HSD_OK;
 }
 

@@ -76,8 +76,19 @@ struct GrainView {
     int pad;
 };
 
+// Launch configuration of one bin-count class of the solver (defaults, or the
+// autotuner's choice).
+constexpr int kClasses = 4;
+constexpr int kClassHi[kClasses] = {1024, 512, 256, 128};   // class c holds kClassHi[c+1] < bins <= kClassHi[c]
+struct ClassCfg {
+    int kg = 2;          // row slots per straight-line group: 2 or 4
+    int wide = 0;        // > 512 bins: 0 = 32 lanes x 32 slots with Cum in LDS, 1 = 64 lanes x 16 slots
+    int persistent = 0;  // 1 = persistent grid fed by an atomic item counter
+};
+
 struct Ctx {
     int device = 0;
+    ClassCfg cfg[kClasses];
     int L = 0, Lp = 0;
     double lnlam0 = 0, dlnlam = 0;
     double* lam = nullptr;        // [L] device copy of the grid
@@ -91,6 +102,7 @@ struct Ctx {
     GrainView* views = nullptr;   size_t views_cap = 0;
     long long* offs = nullptr;    size_t offs_cap = 0;
     int2* items = nullptr;        size_t items_cap = 0;
+    unsigned* queue = nullptr;    // [kClasses] item counters of persistent launches
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded
@@ -120,10 +132,16 @@ struct SolveLaunch {
     unsigned* errword;
 };
 // Launch the fused rates -> B -> recursion kernel for every pair of the
-// listed (slot, cell block) items of one bin-count class.
-hipError_t launch_solve(const Ctx& c, const SolveLaunch& a, int nb_max, const int2* items_dev,
-                        int n_items, int cells_per_item_out_hint, hipStream_t s);
-int solve_cells_per_item(int nb_max);
+// listed (slot, first cell) items of bin-count class cls, with the class's
+// configuration in c.cfg.  A persistent configuration needs `queue`, one
+// device counter that this call clears (with a kernel) before the launch.
+hipError_t launch_solve(const Ctx& c, const SolveLaunch& a, int cls, const int2* items_dev, int n_items,
+                        unsigned* queue, hipStream_t s);
+int solve_cells_per_item(const ClassCfg& cfg, int cls);
+// Workgroups of class cls's kernel (in the context's configuration) that fit
+// on the device at once; the persistent grid size.  Queries the runtime on the
+// first call per kernel only.
+int solve_capacity(const Ctx& c, int cls);
 
 hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool,
                              double* P, hipStream_t s);

@@ -38,8 +38,8 @@
 // Rescaling.  When a new X_f exceeds 2^500 the pair's whole state (X_0..X_f and
 // every pending G) is multiplied by 2^-500, exactly (the appendix on precision
 // control rescales by 1e-30 above 1e30 in single precision).
+#include <atomic>
 #include <cmath>
-#include <cstdlib>
 #include <utility>
 
 #include "hsd_index.h"
@@ -364,6 +364,8 @@ struct KArgs {
     double* P64;
     unsigned* errword;
     const int2* items;
+    int n_items;               // work items (physical) or blocks of pairs (given rates)
+    unsigned* queue;           // persistent launch: next-item counter (zero at launch), else null
     // given-rates test hook
     const double* A;
     const double* cool;
@@ -375,229 +377,313 @@ struct KArgs {
 // continuous-heating and representable-power terms read it), instead of
 // being folded into per-row registers; chosen for the large bin counts, where
 // registers are scarcer than LDS.
-template <int P, int R, int KG, int WAVES, bool GIVEN, bool LDSCUM>
+//
+// One work item per workgroup (item = block index), or (PERSIST) a grid of
+// the workgroups that fit on the device at once in which every workgroup
+// takes the next item from an atomic counter until the list is exhausted, so
+// the items, ordered longest first, go to whichever workgroup frees up first.
+// Every workgroup leaves the loop once the counter has passed the last item.
+// (The body stays in the kernel itself: moved into a function that takes the
+// kernel arguments by reference, it costs 10-20 more VGPRs.)
+template <int P, int R, int KG, int WAVES, bool GIVEN, bool LDSCUM, bool PERSIST>
 __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
-    constexpr int PPW = 64 / P;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int q = lane & (P - 1);
-    const int seg = lane / P;
-
-    int gslot = 0, cell, nb;
-    GrainView gv{};
-    if constexpr (!GIVEN) {
-        const int2 it = a.items[blockIdx.x];
-        gslot = it.x;
-        cell = it.y + wave * PPW + seg;
-        gv = a.views[gslot];
-        nb = gv.nb;
-    } else {
-        cell = (blockIdx.x * WAVES + wave) * PPW + seg;
-        nb = a.nb_given;
-    }
-    const int n_live = GIVEN ? a.n_pairs : a.n_cells;
-    const bool live = cell < n_live;
-    const int cellc = live ? cell : 0;
-
-    Rec<R> st;
-    float rep[R];      // representable absorbed power from each row's bin, / total (register variant)
-    double total = 0.0;
-    double cf0 = 1.0;
-    bool bad = false;
-    DPar* dpar_s = reinterpret_cast<DPar*>(smem);
-    float* tab = nullptr;
-    float* cum = nullptr;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        st.intra[r] = 0.0f;
-        rep[r] = 0.0f;
-    }
-
-    if constexpr (!GIVEN) {
-        const int L = a.L;
-        // log2 table with sentinels: tab[-1], tab[L], tab[L+1] hold kNoField
-        float* base = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride;
-        tab = base + 1;
-        cum = LDSCUM ? base + (L + 3) : tab;   // else pass 2 overwrites Cum with the log2 table
-        for (int d = threadIdx.x; d < nb; d += 64 * WAVES) dpar_s[d] = gv.dpar[d];
-
-        // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
-        // (trapezoid), FP64, chunked over the segment's lanes; kept normalised by
-        // the total in FP32.
-        const double* uc = a.u + static_cast<size_t>(cellc) * L;
-        const int cs = (L + P - 1) / P;
-        const int j0 = q * cs;
-        const int j1 = min(j0 + cs, L);
-        double csum = 0.0;
-        if (j0 < j1) {
-            double rho_n = kLight * clean_field(uc[j0], bad) * gv.cabs[j0];
-            for (int j = j0; j < j1; ++j) {
-                const double rho = rho_n;
-                if (j + 1 < L) {
-                    rho_n = kLight * clean_field(uc[j + 1], bad) * gv.cabs[j + 1];
-                    csum += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
-                }
-            }
-        }
-        const double carry = seg_suffix_exclusive<P>(csum, q);
-        total = seg_sum<P>(csum);
-        const double inv_total = total > 0.0 ? 1.0 / total : 0.0;
-        if (j0 < j1) {
-            double c = carry;
-            double rho_n = (j1 < L) ? kLight * clean_field(uc[j1], bad) * gv.cabs[j1] : 0.0;
-            for (int j = j1 - 1; j >= j0; --j) {
-                const double rho = kLight * clean_field(uc[j], bad) * gv.cabs[j];
-                if (j + 1 < L) c += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
-                rho_n = rho;
-                cum[j] = static_cast<float>(c * inv_total);
-            }
-        }
+    __shared__ int s_next;
+    int item = blockIdx.x;
+    if constexpr (PERSIST) {
+        if (threadIdx.x == 0) s_next = static_cast<int>(atomicAdd(a.queue, 1u));
         __syncthreads();
-        if constexpr (!LDSCUM) {
-            // Continuous heating of row k from column k-1 (Draine & Li intrabin
-            // term): absorbed power of photons too soft for the step, per unit step.
+        item = s_next;
+    }
+    for (;;) {
+        if constexpr (PERSIST) {
+            if (item >= a.n_items) break;
+        }
+        constexpr int PPW = 64 / P;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int q = lane & (P - 1);
+        const int seg = lane / P;
+
+        int gslot = 0, cell, nb;
+        GrainView gv{};
+        if constexpr (!GIVEN) {
+            const int2 it = a.items[item];
+            gslot = it.x;
+            cell = it.y + wave * PPW + seg;
+            gv = a.views[gslot];
+            nb = gv.nb;
+        } else {
+            cell = (item * WAVES + wave) * PPW + seg;
+            nb = a.nb_given;
+        }
+        const int n_live = GIVEN ? a.n_pairs : a.n_cells;
+        const bool live = cell < n_live;
+        const int cellc = live ? cell : 0;
+
+        Rec<R> st;
+        float rep[R];      // representable absorbed power from each row's bin, / total (register variant)
+        double total = 0.0;
+        double cf0 = 1.0;
+        bool bad = false;
+        DPar* dpar_s = reinterpret_cast<DPar*>(smem);
+        float* tab = nullptr;
+        float* cum = nullptr;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int k = r * P + q - (R * P - nb);
-                if (k >= 1 && k < nb) {
-                    const int js = gv.jstar[k - 1];
-                    if (js < L && total > 0.0)
-                        st.intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
+        for (int r = 0; r < R; ++r) {
+            st.intra[r] = 0.0f;
+            rep[r] = 0.0f;
+        }
+
+        if constexpr (!GIVEN) {
+            const int L = a.L;
+            // log2 table with sentinels: tab[-1], tab[L], tab[L+1] hold kNoField
+            float* base = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride;
+            tab = base + 1;
+            cum = LDSCUM ? base + (L + 3) : tab;   // else pass 2 overwrites Cum with the log2 table
+            for (int d = threadIdx.x; d < nb; d += 64 * WAVES) dpar_s[d] = gv.dpar[d];
+
+            // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
+            // (trapezoid), FP64, chunked over the segment's lanes; kept normalised by
+            // the total in FP32.
+            const double* uc = a.u + static_cast<size_t>(cellc) * L;
+            const int cs = (L + P - 1) / P;
+            const int j0 = q * cs;
+            const int j1 = min(j0 + cs, L);
+            double csum = 0.0;
+            if (j0 < j1) {
+                double rho_n = kLight * clean_field(uc[j0], bad) * gv.cabs[j0];
+                for (int j = j0; j < j1; ++j) {
+                    const double rho = rho_n;
+                    if (j + 1 < L) {
+                        rho_n = kLight * clean_field(uc[j + 1], bad) * gv.cabs[j + 1];
+                        csum += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
+                    }
                 }
-                if (k >= 0 && k < nb) {
-                    const int jr = gv.jrep[k];
-                    if (jr < L) rep[r] = cum[jr];
+            }
+            const double carry = seg_suffix_exclusive<P>(csum, q);
+            total = seg_sum<P>(csum);
+            const double inv_total = total > 0.0 ? 1.0 / total : 0.0;
+            if (j0 < j1) {
+                double c = carry;
+                double rho_n = (j1 < L) ? kLight * clean_field(uc[j1], bad) * gv.cabs[j1] : 0.0;
+                for (int j = j1 - 1; j >= j0; --j) {
+                    const double rho = kLight * clean_field(uc[j], bad) * gv.cabs[j];
+                    if (j + 1 < L) c += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
+                    rho_n = rho;
+                    cum[j] = static_cast<float>(c * inv_total);
                 }
             }
             __syncthreads();
-        }
-        // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off, off = the
-        // pair's largest entry (restored through cf, so the exponent stays small).
-        float mx = -INFINITY;
-        for (int j = q; j < L; j += P) {
-            const double om = clean_field(uc[j], bad) * gv.cabs[j];
-            float v = kNoField;
-            if (om > 0.0) {
-                int e;
-                const double m = frexp(om, &e);
-                v = static_cast<float>(e) + __builtin_amdgcn_logf(static_cast<float>(m)) + 3.0f * a.dlam2 * j;
-                mx = fmaxf(mx, v);
-            }
-            tab[j] = v;
-        }
-        mx = seg_maxf<P>(mx);
-        const float off = (mx > -INFINITY) ? mx : 0.0f;
-        for (int j = q; j < L; j += P) {
-            const float v = tab[j];
-            tab[j] = (v > kNoField) ? v - off : kNoField;
-        }
-        if (q == 0) {
-            tab[-1] = kNoField;
-            tab[L] = kNoField;
-            tab[L + 1] = kNoField;
-        }
-        cf0 = exp2(gv.gam[0] + static_cast<double>(off));
-        __syncthreads();
-    }
-
-    // ---- recursion ----
+            if constexpr (!LDSCUM) {
+                // Continuous heating of row k from column k-1 (Draine & Li intrabin
+                // term): absorbed power of photons too soft for the step, per unit step.
 #pragma unroll
-    for (int r = 0; r < R; ++r) st.G[r] = 0.0;
-    st.part = 0.0;
-    st.nres = 0;
-    st.cf = cf0;
-    StepEnv env;
-    env.q = q;
-    env.nb = nb;
-    env.s0 = R * P - nb;
-    env.Lm1 = a.L - 1;
-    env.rbin = gv.rbin;
-    env.total = total;
-    env.colpar = gv.colpar;
-    env.dpar = dpar_s;
-    env.tab = tab;
-    env.cum = cum;
-    if constexpr (GIVEN) {
-        env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
-        env.cp = a.cool + static_cast<size_t>(cellc) * nb;
-    } else {
-        st.cnext = load_colpar(gv.colpar, 0);
-    }
-    all_columns<P, R, KG, GIVEN, LDSCUM>(st, env, std::make_integer_sequence<int, R>{});
-    double* G = st.G;
-    const int nres = st.nres;
-
-    // ---- normalisation (eq:renormalization) and outputs ----
-    const int s0 = R * P - nb;
-    double sx = 0.0, mxx = 0.0, srep = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int k = r * P + q - s0;
-        if (k >= 0) {
-            sx += G[r];
-            mxx = fmax(mxx, G[r]);
-            float rv = rep[r];
-            if constexpr (LDSCUM && !GIVEN) {
-                const int jr = gv.jrep[k];
-                rv = jr < a.L ? cum[jr] : 0.0f;
+                for (int r = 0; r < R; ++r) {
+                    const int k = r * P + q - (R * P - nb);
+                    if (k >= 1 && k < nb) {
+                        const int js = gv.jstar[k - 1];
+                        if (js < L && total > 0.0)
+                            st.intra[r] = static_cast<float>(static_cast<double>(cum[js]) * total * gv.invgap[k - 1]);
+                    }
+                    if (k >= 0 && k < nb) {
+                        const int jr = gv.jrep[k];
+                        if (jr < L) rep[r] = cum[jr];
+                    }
+                }
+                __syncthreads();
             }
-            srep += G[r] * static_cast<double>(rv);
+            // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off, off = the
+            // pair's largest entry (restored through cf, so the exponent stays small).
+            float mx = -INFINITY;
+            for (int j = q; j < L; j += P) {
+                const double om = clean_field(uc[j], bad) * gv.cabs[j];
+                float v = kNoField;
+                if (om > 0.0) {
+                    int e;
+                    const double m = frexp(om, &e);
+                    v = static_cast<float>(e) + __builtin_amdgcn_logf(static_cast<float>(m)) + 3.0f * a.dlam2 * j;
+                    mx = fmaxf(mx, v);
+                }
+                tab[j] = v;
+            }
+            mx = seg_maxf<P>(mx);
+            const float off = (mx > -INFINITY) ? mx : 0.0f;
+            for (int j = q; j < L; j += P) {
+                const float v = tab[j];
+                tab[j] = (v > kNoField) ? v - off : kNoField;
+            }
+            if (q == 0) {
+                tab[-1] = kNoField;
+                tab[L] = kNoField;
+                tab[L + 1] = kNoField;
+            }
+            cf0 = exp2(gv.gam[0] + static_cast<double>(off));
+            __syncthreads();
         }
-    }
-    sx = seg_sum<P>(sx);
-    mxx = seg_max<P>(mxx);
-    srep = seg_sum<P>(srep);
-    bad = seg_maxf<P>(bad ? 1.0f : 0.0f) > 0.0f;
-    if (!live) return;
-    if (a.P64) {
-        double* prow = a.P64 + static_cast<size_t>(cell) * nb;
+
+        // ---- recursion ----
+#pragma unroll
+        for (int r = 0; r < R; ++r) st.G[r] = 0.0;
+        st.part = 0.0;
+        st.nres = 0;
+        st.cf = cf0;
+        StepEnv env;
+        env.q = q;
+        env.nb = nb;
+        env.s0 = R * P - nb;
+        env.Lm1 = a.L - 1;
+        env.rbin = gv.rbin;
+        env.total = total;
+        env.colpar = gv.colpar;
+        env.dpar = dpar_s;
+        env.tab = tab;
+        env.cum = cum;
+        if constexpr (GIVEN) {
+            env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
+            env.cp = a.cool + static_cast<size_t>(cellc) * nb;
+        } else {
+            st.cnext = load_colpar(gv.colpar, 0);
+        }
+        all_columns<P, R, KG, GIVEN, LDSCUM>(st, env, std::make_integer_sequence<int, R>{});
+        double* G = st.G;
+        const int nres = st.nres;
+
+        // ---- normalisation (eq:renormalization) and outputs ----
+        const int s0 = R * P - nb;
+        double sx = 0.0, mxx = 0.0, srep = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int k = r * P + q - s0;
-            if (k >= 0) prow[k] = G[r] / sx;
+            if (k >= 0) {
+                sx += G[r];
+                mxx = fmax(mxx, G[r]);
+                float rv = rep[r];
+                if constexpr (LDSCUM && !GIVEN) {
+                    const int jr = gv.jrep[k];
+                    rv = jr < a.L ? cum[jr] : 0.0f;
+                }
+                srep += G[r] * static_cast<double>(rv);
+            }
         }
-    }
-    if constexpr (!GIVEN) {
-        if (a.Pt) {
-            float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(cell) * nb;
-            const double inv = 1.0 / mxx;
+        sx = seg_sum<P>(sx);
+        mxx = seg_max<P>(mxx);
+        srep = seg_sum<P>(srep);
+        bad = seg_maxf<P>(bad ? 1.0f : 0.0f) > 0.0f;
+        if (live) {
+            if (a.P64) {
+                double* prow = a.P64 + static_cast<size_t>(cell) * nb;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int k = r * P + q - s0;
-                if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
+                for (int r = 0; r < R; ++r) {
+                    const int k = r * P + q - s0;
+                    if (k >= 0) prow[k] = G[r] / sx;
+                }
+            }
+            if constexpr (!GIVEN) {
+                if (a.Pt) {
+                    float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(cell) * nb;
+                    const double inv = 1.0 / mxx;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int k = r * P + q - s0;
+                        if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
+                    }
+                }
+                const size_t pair = static_cast<size_t>(cell) * a.n_gslots + gslot;
+                if (q == 0) {
+                    if (a.pscale) a.pscale[pair] = static_cast<float>(mxx / sx);
+                    // no heating term anywhere leaves X = (1, 0, ..., 0): the sum is exactly 1
+                    const unsigned flags = (sx == 1.0 && nres == 0 ? 1u : 0u) | (nres > 0 ? 2u : 0u) | (bad ? 4u : 0u);
+                    if (a.diag) {
+                        a.diag[pair * 4 + 0] = static_cast<float>(total);
+                        a.diag[pair * 4 + 2] = static_cast<float>(total * (srep / sx));
+                        a.diag[pair * 4 + 3] = static_cast<float>(flags);
+                    }
+                    if (bad && a.errword) atomicOr(a.errword, 1u);
+                }
             }
         }
-        const size_t pair = static_cast<size_t>(cell) * a.n_gslots + gslot;
-        if (q == 0) {
-            if (a.pscale) a.pscale[pair] = static_cast<float>(mxx / sx);
-            // no heating term anywhere leaves X = (1, 0, ..., 0): the sum is exactly 1
-            const unsigned flags = (sx == 1.0 && nres == 0 ? 1u : 0u) | (nres > 0 ? 2u : 0u) | (bad ? 4u : 0u);
-            if (a.diag) {
-                a.diag[pair * 4 + 0] = static_cast<float>(total);
-                a.diag[pair * 4 + 2] = static_cast<float>(total * (srep / sx));
-                a.diag[pair * 4 + 3] = static_cast<float>(flags);
-            }
-            if (bad && a.errword) atomicOr(a.errword, 1u);
+        if constexpr (!PERSIST) {
+            break;
+        } else {
+            __syncthreads();     // the item's LDS tables are dead and every thread has read s_next
+            if (threadIdx.x == 0) s_next = static_cast<int>(atomicAdd(a.queue, 1u));
+            __syncthreads();
+            item = s_next;
         }
     }
 }
 
-template <int P, int R, int WAVES, bool LDSCUM>
-hipError_t launch_phys(const KArgs& ka, int n_items, int kg, hipStream_t s) {
-    const size_t lds = sizeof(DPar) * R * P + sizeof(float) * static_cast<size_t>(WAVES) * (64 / P) * ka.tabstride;
-    if (kg == 4)
-        hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, false, LDSCUM>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+__global__ void k_zero_u32(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Workgroups of one kernel that fit on the device at once (persistent grid).
+template <typename K>
+int resident_blocks(K kern, int threads, size_t lds) {
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess) return -1;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+    return (per_cu > 0 ? per_cu : 1) * ncu;
+}
+
+template <int P, int R, int KG, int WAVES, bool LDSCUM>
+size_t phys_lds(int tabstride) {
+    return sizeof(DPar) * R * P + sizeof(float) * static_cast<size_t>(WAVES) * (64 / P) * tabstride;
+}
+
+// Cached per kernel and LDS stride (the stride depends on the grid length).
+template <int P, int R, int KG, int WAVES, bool LDSCUM>
+int phys_cap(int tabstride) {
+    static std::atomic<long long> memo{-1};
+    const long long m = memo.load(std::memory_order_relaxed);
+    if (m >= 0 && static_cast<int>(m >> 32) == tabstride) return static_cast<int>(m & 0xffffffffLL);
+    const int cap = resident_blocks(k_solve<P, R, KG, WAVES, false, LDSCUM, true>, 64 * WAVES,
+                                    phys_lds<P, R, KG, WAVES, LDSCUM>(tabstride));
+    if (cap > 0) memo.store((static_cast<long long>(tabstride) << 32) | cap, std::memory_order_relaxed);
+    return cap;
+}
+
+template <int P, int R, int KG, int WAVES, bool LDSCUM>
+hipError_t launch_phys_kg(KArgs ka, int n_items, unsigned* queue, hipStream_t s) {
+    const size_t lds = phys_lds<P, R, KG, WAVES, LDSCUM>(ka.tabstride);
+    ka.n_items = n_items;
+    ka.queue = queue;
+    int grid = n_items;
+    if (queue) {
+        const int cap = phys_cap<P, R, KG, WAVES, LDSCUM>(ka.tabstride);
+        if (cap <= 0) return hipErrorInvalidValue;
+        grid = n_items < cap ? n_items : cap;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, queue, 1);
+    }
+    if (queue)
+        hipLaunchKernelGGL((k_solve<P, R, KG, WAVES, false, LDSCUM, true>), dim3(grid), dim3(64 * WAVES), lds, s, ka);
     else
-        hipLaunchKernelGGL((k_solve<P, R, 2, WAVES, false, LDSCUM>), dim3(n_items), dim3(64 * WAVES), lds, s, ka);
+        hipLaunchKernelGGL((k_solve<P, R, KG, WAVES, false, LDSCUM, false>), dim3(grid), dim3(64 * WAVES), lds, s, ka);
     return hipGetLastError();
 }
 
+template <int P, int R, int WAVES, bool LDSCUM>
+hipError_t launch_phys(const KArgs& ka, int n_items, int kg, unsigned* queue, hipStream_t s) {
+    if (kg == 4) return launch_phys_kg<P, R, 4, WAVES, LDSCUM>(ka, n_items, queue, s);
+    return launch_phys_kg<P, R, 2, WAVES, LDSCUM>(ka, n_items, queue, s);
+}
+
+template <int P, int R, int WAVES, bool LDSCUM>
+int cap_phys(int kg, int tabstride) {
+    if (kg == 4) return phys_cap<P, R, 4, WAVES, LDSCUM>(tabstride);
+    return phys_cap<P, R, 2, WAVES, LDSCUM>(tabstride);
+}
+
 template <int P, int R, int WAVES>
-hipError_t launch_given(const KArgs& ka, int n_pairs, hipStream_t s) {
+hipError_t launch_given(KArgs ka, int n_pairs, hipStream_t s) {
     const int per_block = WAVES * (64 / P);
     const int blocks = (n_pairs + per_block - 1) / per_block;
-    hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, true, false>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
+    ka.n_items = blocks;
+    ka.queue = nullptr;
+    hipLaunchKernelGGL((k_solve<P, R, 4, WAVES, true, false, false>), dim3(blocks), dim3(64 * WAVES), 0, s, ka);
     return hipGetLastError();
 }
 
@@ -607,19 +693,40 @@ constexpr int kWaves = 4;
 
 // Bin-count classes: lanes per pair P and row slots per lane R (P R >= bins).
 //   <= 128 bins: P 16, R 8;  <= 256: P 16, R 16;  <= 512: P 32, R 16;
-//   <= 1024: P 32, R 32 with the Cum table kept in LDS.
-int solve_cells_per_item(int nb_max) {
+//   <= 1024: P 32, R 32 with the Cum table kept in LDS, or (wide) P 64, R 16.
+int solve_cells_per_item(const ClassCfg& cfg, int cls) {
+    const int nb_max = kClassHi[cls];
     if (nb_max <= 256) return kWaves * 4;
-    if (nb_max > 512) {
-        const char* v = std::getenv("HSD_BIGCFG");
-        if (v && std::atoi(v) == 64) return kWaves;
-    }
+    if (nb_max > 512 && cfg.wide) return kWaves;
     return kWaves * 2;
 }
 
-hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const int2* items_dev, int n_items,
-                        int, hipStream_t s) {
+// LDS floats per pair: the log2 table with its sentinels, plus the Cum table
+// when it stays in LDS (> 512 bins, narrow layout).
+int tab_stride(const Ctx& c, int cls) {
+    if (kClassHi[cls] <= 512 || c.cfg[cls].wide) return (c.L + 3 + 3) & ~3;
+    return (2 * c.L + 3 + 3) & ~3;
+}
+
+int solve_capacity(const Ctx& c, int cls) {
+    if (cls < 0 || cls >= kClasses) return -1;
+    const ClassCfg& cfg = c.cfg[cls];
+    const int ts = tab_stride(c, cls);
+    switch (cls) {
+        case 3: return cap_phys<16, 8, kWaves, false>(cfg.kg, ts);
+        case 2: return cap_phys<16, 16, kWaves, false>(cfg.kg, ts);
+        case 1: return cap_phys<32, 16, kWaves, false>(cfg.kg, ts);
+        default:
+            if (cfg.wide) return cap_phys<64, 16, kWaves, false>(cfg.kg, ts);
+            return cap_phys<32, 32, kWaves, true>(cfg.kg, ts);
+    }
+}
+
+hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int cls, const int2* items_dev, int n_items,
+                        unsigned* queue, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (cls < 0 || cls >= kClasses) return hipErrorInvalidValue;
+    const ClassCfg& cfg = c.cfg[cls];
     KArgs ka{};
     ka.u = sl.u;
     ka.lam = c.lam;
@@ -635,26 +742,17 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int nb_max, const i
     ka.P64 = sl.P64;
     ka.errword = sl.errword;
     ka.items = items_dev;
-    static const int kg = [] {
-        const char* v = std::getenv("HSD_KGROUP");
-        return (v && std::atoi(v) == 4) ? 4 : 2;
-    }();
-    if (nb_max <= 512) {
-        ka.tabstride = (c.L + 3 + 3) & ~3;
-        if (nb_max <= 128) return launch_phys<16, 8, kWaves, false>(ka, n_items, kg, s);
-        if (nb_max <= 256) return launch_phys<16, 16, kWaves, false>(ka, n_items, kg, s);
-        return launch_phys<32, 16, kWaves, false>(ka, n_items, kg, s);
+    unsigned* q = cfg.persistent ? queue : nullptr;
+    if (cfg.persistent && !queue) return hipErrorInvalidValue;
+    ka.tabstride = tab_stride(c, cls);
+    switch (cls) {
+        case 3: return launch_phys<16, 8, kWaves, false>(ka, n_items, cfg.kg, q, s);
+        case 2: return launch_phys<16, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
+        case 1: return launch_phys<32, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
+        default:
+            if (cfg.wide) return launch_phys<64, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
+            return launch_phys<32, 32, kWaves, true>(ka, n_items, cfg.kg, q, s);
     }
-    static const bool wide = [] {
-        const char* v = std::getenv("HSD_BIGCFG");
-        return v && std::atoi(v) == 64;
-    }();
-    if (wide) {
-        ka.tabstride = (c.L + 3 + 3) & ~3;
-        return launch_phys<64, 16, kWaves, false>(ka, n_items, kg, s);
-    }
-    ka.tabstride = (2 * c.L + 3 + 3) & ~3;
-    return launch_phys<32, 32, kWaves, true>(ka, n_items, kg, s);
 }
 
 hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool, double* P,

@@ -28,7 +28,14 @@ STATUS_NAMES = {
 SYMBOLS = (
     "hsd_create", "hsd_destroy", "hsd_last_error", "hsd_add_grain", "hsd_grain_tables",
     "hsd_solve", "hsd_solve_P", "hsd_solve_from_rates", "hsd_sync", "hsd_set_timing", "hsd_phase_ms",
+    "hsd_get_class_cfg", "hsd_set_class_cfg", "hsd_plan_create", "hsd_plan_launch", "hsd_plan_phase_ms",
+    "hsd_plan_destroy", "hsd_autotune",
 )
+
+N_CLASSES = 4
+CLASS_BINS = ((513, 1024), (257, 512), (129, 256), (16, 128))   # bin-count range of each solver class
+PLAN_TIMING = 1
+PLAN_CONCURRENT = 2
 
 
 class HsdError(RuntimeError):
@@ -48,6 +55,15 @@ class hsd_grain_desc(ctypes.Structure):
         ("cabs_host", ctypes.POINTER(ctypes.c_double)),
         ("longwave_index", ctypes.c_double),
     ]
+
+
+class hsd_class_cfg(ctypes.Structure):
+    _fields_ = [("kg", ctypes.c_int32), ("wide", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+
+
+class hsd_tune_record(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("cfg", hsd_class_cfg), ("n_grains", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -77,6 +93,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_set_timing.restype = ctypes.c_int
     lib.hsd_phase_ms.argtypes = [vp, dp]
     lib.hsd_phase_ms.restype = ctypes.c_int
+    cp = ctypes.POINTER(hsd_class_cfg)
+    lib.hsd_get_class_cfg.argtypes = [vp, i32, cp]
+    lib.hsd_get_class_cfg.restype = ctypes.c_int
+    lib.hsd_set_class_cfg.argtypes = [vp, i32, cp]
+    lib.hsd_set_class_cfg.restype = ctypes.c_int
+    lib.hsd_plan_create.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, i32, ctypes.POINTER(vp)]
+    lib.hsd_plan_create.restype = ctypes.c_int
+    lib.hsd_plan_launch.argtypes = [vp, vp]
+    lib.hsd_plan_launch.restype = ctypes.c_int
+    lib.hsd_plan_phase_ms.argtypes = [vp, dp]
+    lib.hsd_plan_phase_ms.restype = ctypes.c_int
+    lib.hsd_plan_destroy.argtypes = [vp]
+    lib.hsd_plan_destroy.restype = None
+    lib.hsd_autotune.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(hsd_tune_record), i32,
+                                 ctypes.POINTER(i32)]
+    lib.hsd_autotune.restype = ctypes.c_int
     return lib
 
 
@@ -218,7 +250,86 @@ class Context:
             self._raise(st, "hsd_phase_ms")
         return ms
 
+    def hsd_get_class_cfg(self, cls: int) -> dict:
+        c = hsd_class_cfg()
+        st = self._lib.hsd_get_class_cfg(self._h, int(cls), ctypes.byref(c))
+        if st != HSD_OK:
+            self._raise(st, "hsd_get_class_cfg")
+        return {"kg": c.kg, "wide": c.wide, "persistent": c.persistent}
+
+    def hsd_set_class_cfg(self, cls: int, kg: int = 2, wide: int = 0, persistent: int = 0):
+        c = hsd_class_cfg(int(kg), int(wide), int(persistent))
+        st = self._lib.hsd_set_class_cfg(self._h, int(cls), ctypes.byref(c))
+        if st != HSD_OK:
+            self._raise(st, "hsd_set_class_cfg")
+
+    def hsd_autotune(self, u, grain_ids: Sequence[int], runs: int = 4):
+        """Time every class configuration on this batch; the context keeps the
+        fastest per class.  Returns one dict per configuration timed."""
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        cap = 64
+        recs = (hsd_tune_record * cap)()
+        n = ctypes.c_int32()
+        st = self._lib.hsd_autotune(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                    ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(runs), recs, cap,
+                                    ctypes.byref(n))
+        if st != HSD_OK:
+            self._raise(st, "hsd_autotune")
+        return [{"cls": r.cls, "kg": r.cfg.kg, "wide": r.cfg.wide, "persistent": r.cfg.persistent,
+                 "n_grains": r.n_grains, "ms": r.ms} for r in recs[:min(n.value, cap)]]
+
+    def hsd_plan_create(self, u, grain_ids: Sequence[int], j, diag=None, flags: int = 0) -> "Plan":
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(j, torch.float32, (n_cells, ids.shape[0], self.L), "j")
+        if diag is not None:
+            _check_dev(diag, torch.float32, (n_cells, ids.shape[0], 4), "diag")
+        h = ctypes.c_void_p()
+        st = self._lib.hsd_plan_create(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                       ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), j.data_ptr(),
+                                       diag.data_ptr() if diag is not None else None, int(flags), ctypes.byref(h))
+        if st != HSD_OK:
+            self._raise(st, "hsd_plan_create")
+        return Plan(self, h, (u, j, diag))
+
     def hsd_sync(self):
         st = self._lib.hsd_sync(self._h)
         if st != HSD_OK:
             self._raise(st, "hsd_sync")
+
+
+class Plan:
+    """Owns one hsd_plan; keeps the tensors it was built on alive."""
+
+    def __init__(self, ctx: Context, h, buffers):
+        self._ctx = ctx
+        self._h = h
+        self._buffers = buffers
+
+    def hsd_plan_launch(self, stream=None):
+        st = self._ctx._lib.hsd_plan_launch(self._h, _stream_ptr(stream))
+        if st != HSD_OK:
+            self._ctx._raise(st, "hsd_plan_launch")
+
+    def hsd_plan_phase_ms(self):
+        ms = np.zeros(3)
+        st = self._ctx._lib.hsd_plan_phase_ms(self._h, _dptr(ms))
+        if st != HSD_OK:
+            self._ctx._raise(st, "hsd_plan_phase_ms")
+        return ms
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._ctx._lib.hsd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

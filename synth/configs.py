@@ -28,7 +28,10 @@ inputs, shared verbatim by the oracle and the GPU path):
 * silicate mean atomic mass: MgFeSiO4 has 7 atoms and 172.23 amu, so 24.605
   amu per atom;
 * enthalpy-grid end points for c2..c5 (the workloads give none): the lower end
-  is the low-temperature Debye energy (3 pi^4 / 5) N k T^4 / theta^3 at 5 K,
+  is the low-temperature Debye energy (3 pi^4 / 5) N k T^4 / theta^3 at
+  T_lo = 5 K, or 2.5 K for c3, whose attenuated fields cool large silicate
+  grains to an equilibrium temperature of 4.7 K (the grid must reach below the
+  coldest equilibrium, else probability piles up in the lowest bin);
   the upper end is max(3 N k T_top, E_lo + 3 hc / lambda_min) with
   T_top = 511 K (carbonaceous) or 378 K (silicate), twice the equilibrium
   temperature of a large grain at U = 1e5, so that the top bin holds no
@@ -117,14 +120,13 @@ def _n_atoms(a_cm: float, rho: float, m_atom_amu: float) -> float:
 
 
 def make_grain(composition: str, a_cm: float, lam_cm: np.ndarray, n_bins: int | None = None,
-               E_range_erg: Tuple[float, float] | None = None) -> Grain:
+               E_range_erg: Tuple[float, float] | None = None, T_lo: float = 5.0) -> Grain:
     """Build a grain description; default bin count and enthalpy range follow
     the batched-workload conventions in the module docstring."""
     comp = COMPOSITIONS[composition]
     N = _n_atoms(a_cm, comp["rho"], comp["m_atom_amu"])
     k = CONSTANTS["k"]
     if E_range_erg is None:
-        T_lo = 5.0
         E_lo = (3.0 * math.pi ** 4 / 5.0) * N * k * T_lo ** 4 / comp["theta_K"] ** 3
         hc = CONSTANTS["h"] * CONSTANTS["c"]
         E_hi = max(3.0 * N * k * comp["T_top"], E_lo + 3.0 * hc / LAMBDA_MIN_CM)
@@ -193,7 +195,7 @@ def workload(name: str, n_cells: int | None = None) -> Workload:
         return Workload(name, 2, lam, gs, n_cells or 16384, rec)
     if name == "c3_uneven":
         lam = wavelength_grid_cm(500)
-        gs = [make_grain(c, a, lam) for c in ("carbonaceous", "silicate")
+        gs = [make_grain(c, a, lam, T_lo=2.5) for c in ("carbonaceous", "silicate")
               for a in radii_cm(3.5, 2500.0, 64)]
         rec = FieldRecipe(seed=4627000 + 3, U_range=(0.1, 1.0e3), jitter=0.0, tau_V_range=(0.01, 20.0))
         return Workload(name, 3, lam, gs, n_cells or 65536, rec)

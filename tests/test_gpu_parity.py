@@ -6,6 +6,7 @@ with j_ref >= 1e-10 max j_ref.  Inputs are the seeded synthetic workloads.
 """
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -14,6 +15,8 @@ import oracle
 import synth
 from oracle import model as om
 from synth.fields import make_fields
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -202,9 +205,27 @@ def test_c2_full_batch_sampled_pairs(hsd):
     ud = torch.tensor(u, device="cuda")
     j = torch.empty((w.n_cells, len(ids), w.n_lambda), dtype=torch.float32, device="cuda")
     diag = torch.empty((w.n_cells, len(ids), 4), dtype=torch.float32, device="cuda")
-    ctx.hsd_solve(ud, ids, j, diag)
+    # the benchmark's launch: autotuned class configurations (from its cache)
+    # and a plan replayed with phase timing and concurrent classes
+    from paper_1311_4627_amd import autotune
+    tuned = autotune.tune(ctx, ud, ids, cache_path=os.path.join(ROOT, "paper_1311_4627_amd", "tuned.json"))
+    print(f"c2 launch configuration: {tuned['cfg']} (cached: {tuned['cached']})", flush=True)
+    plan = ctx.hsd_plan_create(ud, ids, j, diag, flags=hsd.PLAN_TIMING | hsd.PLAN_CONCURRENT)
+    plan.hsd_plan_launch()
+    torch.cuda.synchronize()
     ctx.hsd_sync()
     print("c2 solved on the GPU", flush=True)
+    # the eager solve in the default configuration agrees (bit for bit unless
+    # the wide layout was chosen, which reorders FP64 sums)
+    for c in range(hsd.N_CLASSES):
+        ctx.hsd_set_class_cfg(c, kg=2, wide=0, persistent=0)
+    je = torch.empty_like(j)
+    ctx.hsd_solve(ud, ids, je, None)
+    ctx.hsd_sync()
+    rel = ((je - j).abs() / j.abs().clamp_min(1e-30 * float(j.abs().max()))).max().item()
+    print(f"c2 plan vs eager: max rel diff {rel:.2e}", flush=True)
+    assert rel < 1e-5
+    del je
     cells = [0, 4097, 16383]
     grains = [0, 7, 15, 23, 31]
     jj = j[cells].cpu().numpy().astype(np.float64)
@@ -229,6 +250,7 @@ def test_c2_full_batch_sampled_pairs(hsd):
     print(f"c2 emitted/A_rep over the batch: min {ratio.min():.4f} max {ratio.max():.4f}", flush=True)
     assert np.all(np.abs(ratio - 1.0) < 0.15)
     print(f"c2 worst sampled j rel err {worst:.2e}", flush=True)
+    plan.close()
 
 
 def test_tiny_grain_matches_dense_master_equation(hsd):

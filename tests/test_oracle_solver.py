@@ -199,3 +199,23 @@ def test_small_grain_is_stochastic():
     P, j, d = oracle.solve_pair(u, g, lam, with_diag=True)
     assert abs(d["emitted"] / d["A_rep"] - 1.0) < 0.01
     assert P.max() < 0.1 and np.count_nonzero(P > 1e-3) > 50
+
+
+def test_uneven_workload_grid_reaches_below_coldest_equilibrium():
+    # The uneven workload's weakest field (U = 0.1 under tau_V = 20) cools the
+    # largest grains further than any other workload's; the enthalpy grid must
+    # start below that equilibrium temperature, else probability piles up in
+    # the lowest bin and the grain emits more than it absorbs.
+    w = synth.workload("c3_uneven", n_cells=1)
+    rec = synth.FieldRecipe(seed=1, U_range=(0.1, 0.1 * (1 + 1e-9)), jitter=0.0,
+                            tau_V_range=(20.0, 20.0 * (1 + 1e-9)))
+    u = synth.fields.make_fields(w.lam_cm, rec, 1)[0]
+    for gi in (63, 127):
+        s = oracle.grain_setup(w.grains[gi], w.lam_cm)
+        T_eq = oracle.equilibrium_temperature(u, s)
+        assert T_eq > 1.5 * s.T[0], (gi, T_eq, s.T[0])
+        P, _, d = oracle.solve_pair(u, w.grains[gi], w.lam_cm, with_diag=True)
+        assert P[0] < 1e-3
+        # below 6 K a sizeable part of the emission falls beyond 1000 um, off
+        # the grid, so emitted-on-grid / absorbed sits below 1
+        assert 0.8 < d["emitted"] / d["A_rep"] < 1.01
