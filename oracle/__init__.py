@@ -24,7 +24,11 @@ approximation):
 * the grain emission spectrum (Sec. 2.3, eq:emission and eq:emission-lambda);
 * a dense solve of the steady-state master equation (eq:steady-state with
   eq:level-sum) as an independent check at small bin counts;
-* energy-balance diagnostics.
+* energy-balance diagnostics;
+* ``oracle.mlp``: the FP64 reference of the learned surrogate (features,
+  targets, the MLP's forward and backward passes, Adam, the band-error
+  metric), against which the GPU trainer's gradients and the inference
+  kernel's outputs are checked.
 
 Every floating-point step is IEEE double precision.  Each reading of a
 garbled or ambiguous passage carries a label (R1..R12) and is stated at the

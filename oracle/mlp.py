@@ -1,0 +1,181 @@
+"""FP64 reference of the emissivity surrogate (test infrastructure only).
+
+The surrogate is not part of the paper's method: it is the learned
+approximation the solver's users may swap in (the paper's introduction cites
+precomputed emissivity tables as the cheap alternative it improves on).
+This module fixes, in plain NumPy, what the GPU trainer and the fused
+inference kernel compute, so that their gradients and outputs can be checked:
+
+* features of a (field, grain) pair: log10 of the field's energy density in
+  32 bands of the wavelength grid plus log10 of the grain radius (cm);
+  band b spans grid nodes floor(b (L-1) / 32) .. floor((b+1) (L-1) / 32) and
+  its energy is the trapezoid integral of u over those nodes;
+* targets: y_lambda = log10(max(j_lambda, 1e-12 max j) / A), A the absorbed
+  power of the pair on the grid (trapezoid of c u C_abs);
+* the network: widths (33, 256, 256, 256, L), GELU (erf form) after every
+  hidden layer, inputs and targets z-scored per column;
+* loss: mean squared error over samples and outputs; Adam updates;
+* the accuracy metric: band-integrated j over the same 32 bands, relative
+  error over the bands holding at least 1e-3 of the pair's emitted power.
+
+``bf16=True`` rounds every matrix-product operand to bfloat16 (round to
+nearest even) and keeps everything else in FP64: the GPU's BF16 products with
+FP32 accumulation then differ from it only by accumulation order and by the
+rare operand whose FP32 value rounds the other way.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+from scipy import special
+
+N_BANDS = 32
+SQRT2 = math.sqrt(2.0)
+
+
+# ---- features, targets, metric -------------------------------------------------
+
+def band_edges(L: int) -> np.ndarray:
+    return (np.arange(N_BANDS + 1) * (L - 1)) // N_BANDS
+
+
+def band_integrals(f: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """Trapezoid integral of f (..., L) over each band: (..., 32)."""
+    e = band_edges(lam.shape[0])
+    seg = 0.5 * (f[..., 1:] + f[..., :-1]) * np.diff(lam)
+    csum = np.concatenate([np.zeros(f.shape[:-1] + (1,)), np.cumsum(seg, axis=-1)], axis=-1)
+    return csum[..., e[1:]] - csum[..., e[:-1]]
+
+
+def features(u: np.ndarray, lam: np.ndarray, radius_cm: float) -> np.ndarray:
+    """Raw (un-normalised) inputs of one or more fields for one grain: (..., 33)."""
+    E = band_integrals(np.asarray(u, dtype=np.float64), lam)
+    x = np.log10(np.maximum(E, 1e-300))
+    a = np.full(x.shape[:-1] + (1,), math.log10(radius_cm))
+    return np.concatenate([x, a], axis=-1)
+
+
+def targets(j: np.ndarray, absorbed) -> np.ndarray:
+    j = np.asarray(j, dtype=np.float64)
+    floor = 1e-12 * j.max(axis=-1, keepdims=True)
+    return np.log10(np.maximum(j, floor) / np.asarray(absorbed, dtype=np.float64)[..., None])
+
+
+def band_rel_error(j: np.ndarray, jref: np.ndarray, lam: np.ndarray, min_share: float = 1e-3) -> np.ndarray:
+    """Per pair: max over bands holding >= min_share of the reference's
+    emitted power of |J_b / J_b,ref - 1|."""
+    J = band_integrals(np.asarray(j, dtype=np.float64), lam)
+    Jr = band_integrals(np.asarray(jref, dtype=np.float64), lam)
+    tot = Jr.sum(axis=-1, keepdims=True)
+    m = Jr >= min_share * tot
+    err = np.where(m, np.abs(J / np.where(m, Jr, 1.0) - 1.0), 0.0)
+    return err.max(axis=-1)
+
+
+# ---- network ----------------------------------------------------------------------
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), via the FP32 value."""
+    f = np.asarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    r = np.where(np.isfinite(f), r, b)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _phi_cdf(z: np.ndarray) -> np.ndarray:
+    # Phi(z) = (1 + erf(z / sqrt 2)) / 2, written with erfc so that the left
+    # tail keeps its relative precision
+    return 0.5 * special.erfc(-z / SQRT2)
+
+
+def gelu(z: np.ndarray) -> np.ndarray:
+    """z Phi(z), Phi the standard normal CDF (the exact, erf form of GELU)."""
+    return z * _phi_cdf(z)
+
+
+def gelu_grad(z: np.ndarray) -> np.ndarray:
+    return _phi_cdf(z) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def unpack(flat: np.ndarray, widths: Sequence[int]) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """Flat parameter vector -> [(W [out, in], b [out])] per layer."""
+    flat = np.asarray(flat, dtype=np.float64)
+    out, o = [], 0
+    for i in range(len(widths) - 1):
+        n_in, n_out = widths[i], widths[i + 1]
+        W = flat[o:o + n_out * n_in].reshape(n_out, n_in)
+        o += n_out * n_in
+        b = flat[o:o + n_out]
+        o += n_out
+        out.append((W, b))
+    assert o == flat.shape[0]
+    return out
+
+
+def pack(layers: Sequence[Tuple[np.ndarray, np.ndarray]]) -> np.ndarray:
+    return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers])
+
+
+def _mm(a: np.ndarray, b: np.ndarray, bf16: bool) -> np.ndarray:
+    if bf16:
+        a, b = bf16_round(a), bf16_round(b)
+    return a @ b
+
+
+def forward(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, bf16: bool = False):
+    """Network output for normalised inputs X [n, 33]; also the
+    pre-activations and activations for the backward pass."""
+    layers = unpack(flat, widths)
+    h = np.asarray(X, dtype=np.float64)
+    hs, zs = [h], []
+    for i, (W, b) in enumerate(layers):
+        z = _mm(h, W.T, bf16) + b
+        zs.append(z)
+        h = gelu(z) if i + 1 < len(layers) else z
+        hs.append(h)
+    return h, (hs, zs)
+
+
+def loss_and_grad(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray, bf16: bool = False):
+    """L = mean over samples and outputs of (yhat - y)^2 and dL/dparams
+    (flat, same layout)."""
+    layers = unpack(flat, widths)
+    yhat, (hs, zs) = forward(flat, widths, X, bf16)
+    n, m = yhat.shape
+    r = yhat - Y
+    loss = float(np.mean(r * r))
+    dz = 2.0 * r / (n * m)
+    grads = [None] * len(layers)
+    for i in range(len(layers) - 1, -1, -1):
+        W, _ = layers[i]
+        dW = _mm(dz.T, hs[i], bf16)
+        db = dz.sum(axis=0)
+        grads[i] = (dW, db)
+        if i > 0:
+            dh = _mm(dz, W, bf16)
+            dz = dh * gelu_grad(zs[i - 1])
+    return loss, pack(grads)
+
+
+def adam_step(flat, grad, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma & Ba), step number t >= 1.  Returns new
+    (params, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return flat - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def zscore_stats(A: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Column means and standard deviations (population); a constant column
+    gets std 1."""
+    A = np.asarray(A, dtype=np.float64)
+    mu = A.mean(axis=0)
+    sd = A.std(axis=0)
+    return mu, np.where(sd > 0.0, sd, 1.0)

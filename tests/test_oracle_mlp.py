@@ -1,0 +1,142 @@
+"""Pins of the FP64 surrogate reference (oracle/mlp.py) against closed forms,
+finite differences and independent library routines."""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import synth
+from oracle import mlp
+from synth.fields import FieldRecipe, make_fields
+from synth import surrogate as ssur
+
+SMALL = (5, 7, 6, 3)
+
+
+def _small_problem(seed=3):
+    rng = np.random.default_rng(seed)
+    n_p = sum(SMALL[i + 1] * SMALL[i] + SMALL[i + 1] for i in range(len(SMALL) - 1))
+    flat = rng.normal(0.0, 0.7, n_p)
+    X = rng.normal(0.0, 1.0, (9, SMALL[0]))
+    Y = rng.normal(0.0, 1.0, (9, SMALL[-1]))
+    return flat, X, Y
+
+
+def test_gelu_matches_normal_cdf_definition_and_derivative():
+    z = np.linspace(-6.0, 6.0, 241)
+    assert np.allclose(mlp.gelu(z), z * stats.norm.cdf(z), rtol=1e-14, atol=1e-300)
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_grad(z), fd, rtol=1e-7, atol=1e-9)
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert np.allclose(mlp.gelu(-z), mlp.gelu(z) - z, atol=1e-14)       # z Phi(-z) = z - z Phi(z)
+
+
+def test_loss_gradient_against_central_differences():
+    flat, X, Y = _small_problem()
+    loss, g = mlp.loss_and_grad(flat, SMALL, X, Y)
+    h = 1e-6
+    fd = np.empty_like(flat)
+    for k in range(flat.shape[0]):
+        e = np.zeros_like(flat)
+        e[k] = h
+        fd[k] = (mlp.loss_and_grad(flat + e, SMALL, X, Y)[0] - mlp.loss_and_grad(flat - e, SMALL, X, Y)[0]) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-8 * max(1.0, np.max(np.abs(fd)))
+    # the loss itself is the mean squared residual of the forward pass
+    yhat, _ = mlp.forward(flat, SMALL, X)
+    assert loss == pytest.approx(np.mean((yhat - Y) ** 2), rel=1e-15)
+
+
+def test_full_size_gradient_spot_check():
+    w = ssur.widths(500)
+    flat = ssur.init_params(500, seed=11).astype(np.float64)
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(6, 33))
+    Y = rng.normal(size=(6, 500))
+    _, g = mlp.loss_and_grad(flat, w, X, Y)
+    h = 1e-5
+    for k in rng.choice(flat.shape[0], 12, replace=False):
+        e = np.zeros_like(flat)
+        e[k] = h
+        fd = (mlp.loss_and_grad(flat + e, w, X, Y)[0] - mlp.loss_and_grad(flat - e, w, X, Y)[0]) / (2 * h)
+        assert abs(g[k] - fd) < 1e-7 * max(1e-3, abs(fd))
+
+
+def test_pack_unpack_layout_and_parameter_count():
+    w = ssur.widths(500)
+    assert ssur.n_params(500) == 268788
+    flat = ssur.init_params(500)
+    layers = mlp.unpack(flat, w)
+    assert [l[0].shape for l in layers] == [(256, 33), (256, 256), (256, 256), (500, 256)]
+    assert np.array_equal(mlp.pack(layers), flat.astype(np.float64))
+    # W1 is the first block, row-major [out][in]
+    assert layers[0][0][1, 0] == flat[33]
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.normal(0, 1, 5000) * 10.0 ** rng.integers(-30, 30, 5000),
+                        [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 0.0, 65504.0]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mlp.bf16_round(x), ref)
+    assert mlp.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0                  # tie to even
+    assert mlp.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6    # tie to even, upward
+
+
+def test_bf16_mode_is_close_to_fp64():
+    flat, X, Y = _small_problem(9)
+    l64, g64 = mlp.loss_and_grad(flat, SMALL, X, Y)
+    l16, g16 = mlp.loss_and_grad(flat, SMALL, X, Y, bf16=True)
+    assert abs(l16 / l64 - 1) < 2e-2
+    assert np.linalg.norm(g16 - g64) < 2e-2 * np.linalg.norm(g64)
+
+
+def test_adam_first_step_and_quadratic():
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
+    # first step: bias-corrected m = g, v = g^2, so the move is lr * sign(g)
+    assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-4)
+    # minimises a quadratic
+    x = np.array([3.0, -4.0])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t in range(1, 3001):
+        x, m, v = mlp.adam_step(x, 2.0 * x, m, v, t, 0.05)
+    assert np.max(np.abs(x)) < 1e-2
+
+
+def test_band_integrals_partition_the_grid_and_features():
+    lam = synth.wavelength_grid_cm(500)
+    e = mlp.band_edges(500)
+    assert e[0] == 0 and e[-1] == 499 and np.all(np.diff(e) > 0)
+    u = make_fields(lam, FieldRecipe(2, (0.1, 1e3), 0.0, None), 4)
+    B = mlp.band_integrals(u, lam)
+    assert np.allclose(B.sum(axis=-1), np.trapezoid(u, lam, axis=-1), rtol=1e-12)
+    # one band against scipy's trapezoid on its own nodes
+    assert B[1, 5] == pytest.approx(integrate.trapezoid(u[1, e[5]:e[6] + 1], lam[e[5]:e[6] + 1]), rel=1e-12)
+    x = mlp.features(u, lam, 1e-7)
+    assert x.shape == (4, 33) and np.all(x[:, 32] == -7.0)
+    assert np.allclose(10 ** x[:, :32], B, rtol=1e-12)
+
+
+def test_targets_and_band_error():
+    lam = synth.wavelength_grid_cm(500)
+    rng = np.random.default_rng(1)
+    j = np.exp(rng.normal(size=(3, 500)))
+    A = np.array([2.0, 3.0, 4.0])
+    y = mlp.targets(j, A)
+    assert np.allclose(10 ** y * A[:, None], j, rtol=1e-12)
+    jz = j.copy()
+    jz[0, :10] = 0.0
+    assert np.all(np.isfinite(mlp.targets(jz, A)))
+    assert np.all(mlp.band_rel_error(j, j, lam) == 0.0)
+    assert np.allclose(mlp.band_rel_error(1.01 * j, j, lam), 0.01, rtol=1e-10)
+
+
+def test_zscore_stats():
+    A = np.array([[1.0, 5.0], [3.0, 5.0]])
+    mu, sd = mlp.zscore_stats(A)
+    assert np.allclose(mu, [2.0, 5.0]) and np.allclose(sd, [1.0, 1.0])
