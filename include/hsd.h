@@ -65,7 +65,8 @@ typedef struct hsd_plan hsd_plan;
 /* One grain size of one composition (the paper's GrainModel row plus the
  * engine's enthalpy grid, appendix on the library interface). */
 typedef struct {
-    double radius_cm;        /* grain radius (informational; C_abs carries the size) */
+    double radius_cm;        /* grain radius: an input of the surrogate (the plain solve
+                                takes the size from C_abs); > 0 for surrogate use */
     double n_atoms;          /* N: 3N Debye modes, real-valued                        */
     double theta_debye_K;    /* Debye temperature of the heat capacity               */
     int32_t n_bins;          /* M + 1 enthalpy bins; 16 <= n_bins <= 1024, multiple of 16 */
@@ -233,6 +234,84 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
 hsd_status hsd_plan_launch(hsd_plan* plan, void* stream);
 hsd_status hsd_plan_phase_ms(hsd_plan* plan, double* ms_host);
 void hsd_plan_destroy(hsd_plan* plan);
+
+/* ---- Learned surrogate ----
+ * Not part of the paper's method: a learned approximation of it (the paper's
+ * introduction names precomputed emissivity tables as the cheap alternative
+ * to the full solve), with the plain solve as its fallback and its judge.
+ * One network maps a (field, grain) pair to its spectrum:
+ *   inputs   x [33]: log10 of the field's energy int u dlambda in 32 bands of
+ *            the wavelength grid (band b spans the grid nodes
+ *            floor(b (L-1) / 32) .. floor((b+1) (L-1) / 32), trapezoid rule),
+ *            then log10 of the grain radius in cm;
+ *   outputs  y [L]: log10(j_lambda / A), A = int c u C_abs dlambda the pair's
+ *            absorbed power (trapezoid); training targets are
+ *            log10(max(j, 1e-6 max j) / A) from the plain solve;
+ *   network  33 -> 256 -> 256 -> 256 -> L, GELU (x Phi(x)) after each hidden
+ *            layer; inputs z-scored per column, targets centred per column
+ *            and divided by one pooled standard deviation (statistics of the
+ *            training set); every matrix product rounds its operands to
+ *            bfloat16 and accumulates in FP32; master weights FP32.
+ * Parameters are one FP32 vector, layer by layer: W_l row-major [out][in],
+ * then b_l (268,788 values for L = 500).  Rows of X_dev / Y_dev / A_dev are
+ * pairs in the order r = cell * n_grains + g. */
+typedef struct hsd_sur hsd_sur;
+hsd_status hsd_sur_create(hsd_ctx* ctx, hsd_sur** out);   /* weights uninitialised: set them */
+void hsd_sur_destroy(hsd_sur* sur);                       /* NULL is ignored; before the context */
+hsd_status hsd_sur_n_params(hsd_sur* sur, int64_t* n_params_host);
+/* Set (and reset the optimiser state) / read the FP32 parameter vector.  Synchronous. */
+hsd_status hsd_sur_set_params(hsd_sur* sur, const float* params_host);
+hsd_status hsd_sur_get_params(hsd_sur* sur, float* params_host);
+/* Column means and standard deviations (> 0) of raw inputs [33] and targets
+ * [L].  Synchronous. */
+hsd_status hsd_sur_set_norm(hsd_sur* sur, const double* x_mean_host, const double* x_std_host,
+                            const double* y_mean_host, const double* y_std_host);
+hsd_status hsd_sur_get_norm(hsd_sur* sur, double* x_mean_host, double* x_std_host, double* y_mean_host,
+                            double* y_std_host);
+/* Raw inputs X_dev [n_cells * n_grains][33] (float) and absorbed powers
+ * A_dev [n_cells * n_grains] (double) of every pair; either may be NULL.
+ * Grains need radius_cm > 0.  Asynchronous on `stream`. */
+hsd_status hsd_sur_features(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                            const int32_t* grain_ids_host, float* X_dev, double* A_dev, void* stream);
+/* Raw targets Y_dev [n][L] from spectra j_dev [n][L] and absorbed powers
+ * A_dev [n].  Asynchronous on `stream`. */
+hsd_status hsd_sur_targets(hsd_ctx* ctx, int64_t n, const float* j_dev, const double* A_dev, float* Y_dev,
+                           void* stream);
+/* Statistics of a training set (FP64 column sums on the device): input
+ * column means and standard deviations, target column means and the pooled
+ * target standard deviation (sqrt of the mean column variance, repeated),
+ * stored as by hsd_sur_set_norm.  Synchronous. */
+hsd_status hsd_sur_fit_norm(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev);
+/* Test hook: mean squared error over the n rows (normalised targets) and
+ * its gradient with respect to the parameter vector (grad_host may be NULL),
+ * without an update.  n <= 65536.  Synchronous. */
+hsd_status hsd_sur_loss_grad(hsd_sur* sur, int32_t n, const float* X_dev, const float* Y_dev, double* loss_host,
+                             float* grad_host);
+/* Train: `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8) on minibatches of
+ * `batch` rows drawn with replacement by a counter-based generator from
+ * `seed`; learning rate warms up linearly over the first 2% of steps, then
+ * decays as a cosine to 5% of `lr`.  loss_host (optional) receives each
+ * step's minibatch loss.  Optimiser state carries over between calls until
+ * hsd_sur_set_params.  Synchronous. */
+hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps,
+                         int32_t batch, float lr, uint64_t seed, float* loss_host);
+/* Surrogate spectra of every (cell, grain) pair: j_dev as in hsd_solve;
+ * diag_dev (optional) = (A, 4 pi int j dlambda, A, flags) with flags bit 3
+ * set (value from the surrogate) and bit 4 set where |emitted / A - 1| >
+ * 0.01.  Asynchronous on `stream` (grows workspace). */
+hsd_status hsd_sur_predict(hsd_sur* sur, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                           const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream);
+/* The surrogate with the plain solve as fallback: every pair is first
+ * evaluated by the network surs_host[g] of its grain (one network may serve
+ * several grains); a pair whose emitted power misses its absorbed power by
+ * more than tol (relative; the energy balance of eq:steady-state) is
+ * re-solved by the plain path, in place.  j_dev and diag_dev as in
+ * hsd_solve; surrogate pairs carry diag flag bit 3, re-solved pairs carry the
+ * plain solve's flags.  *n_fallback_host receives the number of re-solved
+ * pairs.  Waits for the stream once (to size the fallback). */
+hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, float* j_dev,
+                               float* diag_dev, int64_t* n_fallback_host, void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,10 +10,11 @@ inference kernel compute, so that their gradients and outputs can be checked:
   32 bands of the wavelength grid plus log10 of the grain radius (cm);
   band b spans grid nodes floor(b (L-1) / 32) .. floor((b+1) (L-1) / 32) and
   its energy is the trapezoid integral of u over those nodes;
-* targets: y_lambda = log10(max(j_lambda, 1e-12 max j) / A), A the absorbed
+* targets: y_lambda = log10(max(j_lambda, 1e-6 max j) / A), A the absorbed
   power of the pair on the grid (trapezoid of c u C_abs);
 * the network: widths (33, 256, 256, 256, L), GELU (erf form) after every
-  hidden layer, inputs and targets z-scored per column;
+  hidden layer; inputs z-scored per column, targets centred per column and
+  scaled by one pooled standard deviation;
 * loss: mean squared error over samples and outputs; Adam updates;
 * the accuracy metric: band-integrated j over the same 32 bands, relative
   error over the bands holding at least 1e-3 of the pair's emitted power.
@@ -60,7 +61,7 @@ def features(u: np.ndarray, lam: np.ndarray, radius_cm: float) -> np.ndarray:
 
 def targets(j: np.ndarray, absorbed) -> np.ndarray:
     j = np.asarray(j, dtype=np.float64)
-    floor = 1e-12 * j.max(axis=-1, keepdims=True)
+    floor = 1e-6 * j.max(axis=-1, keepdims=True)
     return np.log10(np.maximum(j, floor) / np.asarray(absorbed, dtype=np.float64)[..., None])
 
 

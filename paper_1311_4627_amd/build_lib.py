@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhsd.so")
 
-SOURCES = ["hsd_api.hip", "hsd_precompute.hip", "hsd_solve.hip", "hsd_contract.hip"]
+SOURCES = ["hsd_api.hip", "hsd_precompute.hip", "hsd_solve.hip", "hsd_contract.hip", "hsd_surrogate.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

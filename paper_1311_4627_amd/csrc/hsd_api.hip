@@ -23,9 +23,34 @@ struct Batch {
     long long rows = 0;
 };
 
+// Workspace of surrogate solves (grown on demand, kept with the context).
+struct SurWork {
+    float* bands = nullptr;       size_t bands_cap = 0;
+    float* X = nullptr;           size_t X_cap = 0;       // raw inputs of a chunk
+    float* Xn = nullptr;          size_t Xn_cap = 0;      // normalised inputs
+    double* A = nullptr;          size_t A_cap = 0;
+    float* emit = nullptr;        size_t emit_cap = 0;
+    float* h0 = nullptr;          size_t h0_cap = 0;
+    float* h1 = nullptr;          size_t h1_cap = 0;
+    int* sel = nullptr;           size_t sel_cap = 0;
+    const double** cabs = nullptr; size_t cabs_cap = 0;
+    float* loga = nullptr;        size_t loga_cap = 0;
+    unsigned* cnt = nullptr;      size_t cnt_cap = 0;     // [n_grains + 1]: per-slot flagged, then total
+    int* seg_off = nullptr;       size_t seg_off_cap = 0;
+    int* seg_cnt = nullptr;       size_t seg_cnt_cap = 0;
+    int* cellmap = nullptr;       size_t cellmap_cap = 0;
+    long long* pairs = nullptr;   size_t pairs_cap = 0;
+};
+
 struct hsd_ctx {
     Ctx c;
     Batch batch;     // host description of the last eager solve
+    SurWork sw;
+};
+
+struct hsd_sur {
+    hsd_ctx* ctx = nullptr;
+    hsd::Sur s;
 };
 
 // A batch bound to fixed buffers, captured once as a HIP graph.
@@ -143,6 +168,33 @@ void plan_batch(const Ctx& c, int32_t n_cells, int32_t n_grains, const int32_t* 
                 if (cb >= ncb) continue;
                 b.items.push_back(make_int2(slots[m % nsl], cb * cpi));
             }
+        }
+    }
+    b.cls_begin[hsd::kClasses] = static_cast<int>(b.items.size());
+}
+
+// Batch of per-slot pair lists (counts[g] pairs of slot g, in list order).
+void plan_batch_lists(const Ctx& c, const std::vector<int>& counts, int32_t n_grains, const int32_t* ids, Batch& b) {
+    b.views.resize(n_grains);
+    b.offs.resize(n_grains);
+    b.items.clear();
+    b.rows = 0;
+    for (int g = 0; g < n_grains; ++g) {
+        const Grain& gr = c.grains[ids[g]];
+        b.views[g] = hsd::GrainView{gr.colpar, gr.dpar, gr.gam, gr.invgap, gr.jstar, gr.jrep, gr.cabs,
+                                    std::pow(gr.E_hi / gr.E_lo, 1.0 / (gr.n_bins - 1)), gr.n_bins, 0};
+        b.offs[g] = b.rows;
+        b.rows += static_cast<long long>(counts[g]) * gr.n_bins;
+    }
+    for (int ci = 0; ci < hsd::kClasses; ++ci) {
+        b.cls_begin[ci] = static_cast<int>(b.items.size());
+        const int hi = hsd::kClassHi[ci];
+        const int lo = ci + 1 < hsd::kClasses ? hsd::kClassHi[ci + 1] : 0;
+        const int cpi = hsd::solve_cells_per_item(c.cfg[ci], ci);
+        for (int g = 0; g < n_grains; ++g) {
+            const int nb = c.grains[ids[g]].n_bins;
+            if (nb <= lo || nb > hi) continue;
+            for (int k0 = 0; k0 < counts[g]; k0 += cpi) b.items.push_back(make_int2(g, k0));
         }
     }
     b.cls_begin[hsd::kClasses] = static_cast<int>(b.items.size());
@@ -313,6 +365,10 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.lam);
     hipFree(c.errword);
     hipFree(c.queue);
+    SurWork& w = ctx->sw;
+    hipFree(w.bands); hipFree(w.X); hipFree(w.Xn); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
+    hipFree(w.cellmap); hipFree(w.pairs);
     hipFree(c.Pt);
     hipFree(c.pscale);
     hipFree(c.diag_tmp);
@@ -352,6 +408,7 @@ hsd_status hsd_add_grain(hsd_ctx* ctx, const hsd_grain_desc* d, int32_t* grain_i
     g.n_atoms = d->n_atoms;
     g.theta = d->theta_debye_K;
     g.longwave = d->longwave_index;
+    g.radius = d->radius_cm;
     const size_t Lp = c.Lp;
     hipError_t e = hipSuccess;
     auto al = [&](auto*& p, size_t count) {
@@ -699,6 +756,418 @@ hsd_status hsd_sync(hsd_ctx* ctx) {
         HSD_HIP(ctx, hipMemset(ctx->c.errword, 0, sizeof(unsigned)));
         return fail(ctx, HSD_ERR_NONFINITE_INPUT, "a field value was NaN, infinite or negative");
     }
+    return HSD_OK;
+}
+
+// ---- learned surrogate ----
+
+hsd_status hsd_sur_create(hsd_ctx* ctx, hsd_sur** out) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    hsd_sur* p = new (std::nothrow) hsd_sur();
+    if (!p) return fail(ctx, HSD_ERR_OOM, "host allocation");
+    p->ctx = ctx;
+    p->s.c = &ctx->c;
+    p->s.L = ctx->c.L;
+    p->s.widths[4] = ctx->c.L;
+    const hipError_t e = hsd::sur_alloc(p->s);
+    if (e != hipSuccess) {
+        hsd::sur_free(p->s);
+        delete p;
+        return hip_fail(ctx, e, "hsd_sur_create");
+    }
+    *out = p;
+    return HSD_OK;
+}
+
+void hsd_sur_destroy(hsd_sur* p) {
+    if (!p) return;
+    hipSetDevice(p->ctx->c.device);
+    hipDeviceSynchronize();
+    hsd::sur_free(p->s);
+    delete p;
+}
+
+hsd_status hsd_sur_n_params(hsd_sur* p, int64_t* n) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    if (!n) return fail(p->ctx, HSD_ERR_INVALID_ARG, "null output");
+    *n = p->s.n_params;
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_set_params(hsd_sur* p, const float* params_host) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!params_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null parameters");
+    for (long long i = 0; i < p->s.n_params; ++i)
+        if (!std::isfinite(params_host[i])) return fail(ctx, HSD_ERR_INVALID_ARG, "non-finite parameter");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipMemcpy(p->s.w, params_host, sizeof(float) * p->s.n_params, hipMemcpyHostToDevice));
+    HSD_HIP(ctx, hipMemset(p->s.m, 0, sizeof(float) * p->s.n_params));
+    HSD_HIP(ctx, hipMemset(p->s.v, 0, sizeof(float) * p->s.n_params));
+    p->s.t = 0;
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_get_params(hsd_sur* p, float* params_host) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!params_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipDeviceSynchronize());
+    HSD_HIP(ctx, hipMemcpy(params_host, p->s.w, sizeof(float) * p->s.n_params, hipMemcpyDeviceToHost));
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_set_norm(hsd_sur* p, const double* x_mean, const double* x_std, const double* y_mean,
+                            const double* y_std) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!x_mean || !x_std || !y_mean || !y_std) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    const int L = p->s.L;
+    std::vector<float> a(33), b(33), c(L), d(L);
+    for (int k = 0; k < 33; ++k) {
+        if (!(x_std[k] > 0.0) || !std::isfinite(x_mean[k])) return fail(ctx, HSD_ERR_INVALID_ARG, "bad input statistics");
+        a[k] = static_cast<float>(x_mean[k]);
+        b[k] = static_cast<float>(x_std[k]);
+    }
+    for (int k = 0; k < L; ++k) {
+        if (!(y_std[k] > 0.0) || !std::isfinite(y_mean[k])) return fail(ctx, HSD_ERR_INVALID_ARG, "bad target statistics");
+        c[k] = static_cast<float>(y_mean[k]);
+        d[k] = static_cast<float>(y_std[k]);
+    }
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipMemcpy(p->s.xm, a.data(), sizeof(float) * 33, hipMemcpyHostToDevice));
+    HSD_HIP(ctx, hipMemcpy(p->s.xs, b.data(), sizeof(float) * 33, hipMemcpyHostToDevice));
+    HSD_HIP(ctx, hipMemcpy(p->s.ym, c.data(), sizeof(float) * L, hipMemcpyHostToDevice));
+    HSD_HIP(ctx, hipMemcpy(p->s.ys, d.data(), sizeof(float) * L, hipMemcpyHostToDevice));
+    p->s.have_norm = true;
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_get_norm(hsd_sur* p, double* x_mean, double* x_std, double* y_mean, double* y_std) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!x_mean || !x_std || !y_mean || !y_std) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    if (!p->s.have_norm) return fail(ctx, HSD_ERR_STATE, "no statistics set");
+    const int L = p->s.L;
+    std::vector<float> a(33), b(33), c(L), d(L);
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipMemcpy(a.data(), p->s.xm, sizeof(float) * 33, hipMemcpyDeviceToHost));
+    HSD_HIP(ctx, hipMemcpy(b.data(), p->s.xs, sizeof(float) * 33, hipMemcpyDeviceToHost));
+    HSD_HIP(ctx, hipMemcpy(c.data(), p->s.ym, sizeof(float) * L, hipMemcpyDeviceToHost));
+    HSD_HIP(ctx, hipMemcpy(d.data(), p->s.ys, sizeof(float) * L, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 33; ++k) {
+        x_mean[k] = a[k];
+        x_std[k] = b[k];
+    }
+    for (int k = 0; k < L; ++k) {
+        y_mean[k] = c[k];
+        y_std[k] = d[k];
+    }
+    return HSD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Per-slot tables of the selected grains for the feature kernels.
+hsd_status sur_select(hsd_ctx* ctx, const std::vector<int>& slots, const int32_t* ids, hipStream_t s) {
+    Ctx& c = ctx->c;
+    SurWork& w = ctx->sw;
+    const size_t n = slots.size();
+    std::vector<const double*> cabs(n);
+    std::vector<float> loga(n);
+    for (size_t k = 0; k < n; ++k) {
+        const Grain& g = c.grains[ids[slots[k]]];
+        if (!(g.radius > 0.0)) return fail(ctx, HSD_ERR_INVALID_ARG, "the surrogate needs grains with radius_cm > 0");
+        cabs[k] = g.cabs;
+        loga[k] = static_cast<float>(std::log10(g.radius));
+    }
+    HSD_HIP(ctx, grow(w.sel, w.sel_cap, n));
+    HSD_HIP(ctx, grow(w.cabs, w.cabs_cap, n));
+    HSD_HIP(ctx, grow(w.loga, w.loga_cap, n));
+    HSD_HIP(ctx, hipMemcpyAsync(w.sel, slots.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(w.cabs, cabs.data(), sizeof(double*) * n, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(w.loga, loga.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipStreamSynchronize(s));      // host vectors go out of scope
+    return HSD_OK;
+}
+
+constexpr long long kSurChunk = 131072;   // pair rows per inference chunk
+
+// Surrogate spectra of every (cell, slot) pair of `slots` into j, with diag
+// entries and the energy-balance flags (bit 4) counted in sw.cnt.
+hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u, int32_t n_grains,
+                   const int32_t* ids, const std::vector<int>& slots, float tol, float* j, float* diag, hipStream_t s) {
+    Ctx& c = ctx->c;
+    SurWork& w = ctx->sw;
+    if (!sur.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
+    const hsd_status st = sur_select(ctx, slots, ids, s);
+    if (st != HSD_OK) return st;
+    const int n_sel = static_cast<int>(slots.size());
+    const long long rows = static_cast<long long>(n_cells) * n_sel;
+    const size_t ch = static_cast<size_t>(std::min(rows, kSurChunk));
+    HSD_HIP(ctx, grow(w.X, w.X_cap, ch * 33));
+    HSD_HIP(ctx, grow(w.Xn, w.Xn_cap, ch * 33));
+    HSD_HIP(ctx, grow(w.A, w.A_cap, ch));
+    HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch));
+    HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 256));
+    HSD_HIP(ctx, grow(w.h1, w.h1_cap, ch * 256));
+    for (long long r0 = 0; r0 < rows; r0 += kSurChunk) {
+        const long long n = std::min(kSurChunk, rows - r0);
+        HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.cabs, w.loga, r0, n, n_sel, w.X, w.A, s));
+        HSD_HIP(ctx, hsd::sur_norm_rows(w.X, n, 33, sur.xm, sur.xs, w.Xn, s));
+        HSD_HIP(ctx, hipMemsetAsync(w.emit, 0, sizeof(float) * n, s));
+        HSD_HIP(ctx, hsd::sur_predict_rows(sur, static_cast<int>(n), w.Xn, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
+                                           w.h0, w.h1, s));
+        if (diag)
+            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, r0, n, n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
+    }
+    return HSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hsd_status hsd_sur_features(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                            const int32_t* grain_ids_host, float* X_dev, double* A_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0 || n_grains == 0) return HSD_OK;
+    if (!u_dev || !grain_ids_host || (!X_dev && !A_dev)) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    std::vector<int> slots(n_grains);
+    for (int g = 0; g < n_grains; ++g) slots[g] = g;
+    const hsd_status st = sur_select(ctx, slots, grain_ids_host, s);
+    if (st != HSD_OK) return st;
+    SurWork& w = ctx->sw;
+    HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
+    HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
+    HSD_HIP(ctx, hsd::sur_pairs(c, u_dev, w.bands, w.cabs, w.loga, 0, static_cast<long long>(n_cells) * n_grains,
+                                n_grains, X_dev, A_dev, s));
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_targets(hsd_ctx* ctx, int64_t n, const float* j_dev, const double* A_dev, float* Y_dev,
+                           void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (n == 0) return HSD_OK;
+    if (!j_dev || !A_dev || !Y_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hsd::sur_targets(j_dev, A_dev, n, ctx->c.L, Y_dev, static_cast<hipStream_t>(stream)));
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_fit_norm(hsd_sur* p, int64_t n, const float* X_dev, const float* Y_dev) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (n <= 0 || !X_dev || !Y_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "need n > 0 and both arrays");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipDeviceSynchronize());
+    std::vector<double> xm, xs, ym, ys;
+    HSD_HIP(ctx, hsd::sur_colstats(X_dev, n, 33, xm, xs));
+    HSD_HIP(ctx, hsd::sur_colstats(Y_dev, n, p->s.L, ym, ys));
+    // targets: one pooled standard deviation for every wavelength
+    double pooled = 0.0;
+    for (double v : ys) pooled += v * v;
+    pooled = std::sqrt(pooled / ys.size());
+    if (!(pooled > 0.0)) pooled = 1.0;
+    std::fill(ys.begin(), ys.end(), pooled);
+    return hsd_sur_set_norm(p, xm.data(), xs.data(), ym.data(), ys.data());
+}
+
+hsd_status hsd_sur_loss_grad(hsd_sur* p, int32_t n, const float* X_dev, const float* Y_dev, double* loss_host,
+                             float* grad_host) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (n <= 0 || n > 65536 || !X_dev || !Y_dev || !loss_host)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "need 0 < n <= 65536 and non-null arrays");
+    if (!p->s.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
+    hsd::Sur& s = p->s;
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    const hipStream_t st = nullptr;
+    HSD_HIP(ctx, hsd::sur_grow(s, n));
+    HSD_HIP(ctx, hsd::sur_seq_idx(s, 0, n, st));
+    HSD_HIP(ctx, hsd::sur_gather(s, X_dev, Y_dev, n, st));
+    HSD_HIP(ctx, hsd::sur_forward(s, n, s.Xb, st, true));
+    HSD_HIP(ctx, hsd::sur_loss(s, n, st));
+    HSD_HIP(ctx, hsd::sur_backward(s, n, s.Xb, st));
+    HSD_HIP(ctx, hipDeviceSynchronize());
+    double l = 0.0;
+    HSD_HIP(ctx, hipMemcpy(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost));
+    *loss_host = l / (static_cast<double>(n) * s.L);
+    if (grad_host) HSD_HIP(ctx, hipMemcpy(grad_host, s.g, sizeof(float) * s.n_params, hipMemcpyDeviceToHost));
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_train(hsd_sur* p, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps, int32_t batch,
+                         float lr, uint64_t seed, float* loss_host) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (n <= 0 || !X_dev || !Y_dev || steps < 0 || batch <= 0 || batch > 65536 || !(lr > 0.f))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "need n > 0, steps >= 0, 0 < batch <= 65536, lr > 0");
+    if (!p->s.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
+    hsd::Sur& s = p->s;
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    const hipStream_t st = nullptr;
+    HSD_HIP(ctx, hsd::sur_grow(s, batch));
+    double* trace = nullptr;
+    if (loss_host && steps > 0) HSD_HIP(ctx, hipMalloc(&trace, sizeof(double) * steps));
+    hipError_t e = hipSuccess;
+    const int warm = std::max(1, steps / 50);
+    for (int k = 0; k < steps && e == hipSuccess; ++k) {
+        // linear warm-up, then cosine decay to 5% of lr
+        double f = 1.0;
+        if (k < warm) f = static_cast<double>(k + 1) / warm;
+        else f = 0.05 + 0.95 * 0.5 * (1.0 + std::cos(hsd::kPi * (k - warm) / std::max(1, steps - warm)));
+        e = hsd::sur_batch_idx(s, seed, s.t, batch, n, st);
+        if (e == hipSuccess) e = hsd::sur_gather(s, X_dev, Y_dev, batch, st);
+        if (e == hipSuccess) e = hsd::sur_forward(s, batch, s.Xb, st, true);
+        if (e == hipSuccess) e = hsd::sur_loss(s, batch, st);
+        if (e == hipSuccess && trace)
+            e = hipMemcpyAsync(trace + k, s.loss, sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hsd::sur_backward(s, batch, s.Xb, st);
+        if (e == hipSuccess) e = hsd::sur_adam(s, static_cast<float>(lr * f), st);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess && trace) {
+        std::vector<double> h(steps);
+        e = hipMemcpy(h.data(), trace, sizeof(double) * steps, hipMemcpyDeviceToHost);
+        for (int k = 0; k < steps; ++k) loss_host[k] = static_cast<float>(h[k] / (static_cast<double>(batch) * s.L));
+    }
+    if (trace) (void)hipFree(trace);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hsd_sur_train");
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_predict(hsd_sur* p, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                           const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0 || n_grains == 0) return HSD_OK;
+    if (!u_dev || !grain_ids_host || !j_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    SurWork& w = ctx->sw;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
+    HSD_HIP(ctx, grow(w.cnt, w.cnt_cap, static_cast<size_t>(n_grains) + 1));
+    HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * (n_grains + 1), s));
+    HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
+    std::vector<int> slots(n_grains);
+    for (int g = 0; g < n_grains; ++g) slots[g] = g;
+    return sur_run(ctx, p->s, n_cells, u_dev, n_grains, grain_ids_host, slots, 0.01f, j_dev, diag_dev, s);
+}
+
+hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, float* j_dev,
+                               float* diag_dev, int64_t* n_fallback_host, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (!n_fallback_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null fallback count");
+    *n_fallback_host = 0;
+    if (n_cells == 0 || n_grains == 0) return HSD_OK;
+    if (!u_dev || !grain_ids_host || !surs_host || !j_dev || !diag_dev)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    if (!(tol >= 0.f)) return fail(ctx, HSD_ERR_INVALID_ARG, "tol must be >= 0");
+    for (int g = 0; g < n_grains; ++g) {
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+        if (!surs_host[g] || surs_host[g]->ctx != ctx) return fail(ctx, HSD_ERR_INVALID_ARG, "missing or foreign surrogate");
+    }
+    Ctx& c = ctx->c;
+    SurWork& w = ctx->sw;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
+    HSD_HIP(ctx, grow(w.cnt, w.cnt_cap, static_cast<size_t>(n_grains) + 1));
+    HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * (n_grains + 1), s));
+    HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
+    // one pass per network over the grains it serves
+    std::vector<hsd_sur*> nets;
+    for (int g = 0; g < n_grains; ++g)
+        if (std::find(nets.begin(), nets.end(), surs_host[g]) == nets.end()) nets.push_back(surs_host[g]);
+    for (hsd_sur* net : nets) {
+        std::vector<int> slots;
+        for (int g = 0; g < n_grains; ++g)
+            if (surs_host[g] == net) slots.push_back(g);
+        const hsd_status st = sur_run(ctx, net->s, n_cells, u_dev, n_grains, grain_ids_host, slots, tol, j_dev,
+                                      diag_dev, s);
+        if (st != HSD_OK) return st;
+    }
+    // flagged pairs per slot
+    std::vector<unsigned> cnt(n_grains + 1);
+    HSD_HIP(ctx, hipMemcpyAsync(cnt.data(), w.cnt, sizeof(unsigned) * (n_grains + 1), hipMemcpyDeviceToHost, s));
+    HSD_HIP(ctx, hipStreamSynchronize(s));
+    const long long nfb = cnt[n_grains];
+    *n_fallback_host = nfb;
+    if (nfb == 0) return HSD_OK;
+    // fallback: the plain solve on the flagged pairs, written in place
+    std::vector<int> counts(n_grains), off(n_grains);
+    long long acc = 0;
+    for (int g = 0; g < n_grains; ++g) {
+        counts[g] = static_cast<int>(cnt[g]);
+        off[g] = static_cast<int>(acc);
+        acc += cnt[g];
+    }
+    HSD_HIP(ctx, grow(w.seg_off, w.seg_off_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(w.seg_cnt, w.seg_cnt_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(w.cellmap, w.cellmap_cap, static_cast<size_t>(nfb)));
+    HSD_HIP(ctx, grow(w.pairs, w.pairs_cap, static_cast<size_t>(nfb)));
+    HSD_HIP(ctx, hipMemcpyAsync(w.seg_off, off.data(), sizeof(int) * n_grains, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(w.seg_cnt, counts.data(), sizeof(int) * n_grains, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * n_grains, s));        // reused as cursors
+    HSD_HIP(ctx, hsd::sur_fb_scatter(diag_dev, static_cast<long long>(n_cells) * n_grains, n_grains, w.seg_off, w.cnt,
+                                     w.cellmap, w.pairs, s));
+    Batch& b = ctx->batch;
+    plan_batch_lists(c, counts, n_grains, grain_ids_host, b);
+    HSD_HIP(ctx, grow(c.Pt, c.Pt_cap, static_cast<size_t>(std::max(b.rows, 1LL))));
+    HSD_HIP(ctx, grow(c.pscale, c.pscale_cap, static_cast<size_t>(n_cells) * n_grains));
+    HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
+    HSD_HIP(ctx, hipMemcpyAsync(c.views, b.views.data(), sizeof(hsd::GrainView) * n_grains, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(c.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(c.items, b.items.data(), sizeof(int2) * b.items.size(), hipMemcpyHostToDevice, s));
+    hsd::SolveLaunch sl{};
+    sl.u = u_dev;
+    sl.n_cells = n_cells;
+    sl.n_gslots = n_grains;
+    sl.views = c.views;
+    sl.offs = c.offs;
+    sl.Pt = c.Pt;
+    sl.pscale = c.pscale;
+    sl.diag = diag_dev;
+    sl.errword = c.errword;
+    sl.cellmap = w.cellmap;
+    sl.seg_off = w.seg_off;
+    sl.seg_cnt = w.seg_cnt;
+    for (int ci = 0; ci < hsd::kClasses; ++ci) {
+        const int n_it = b.cls_begin[ci + 1] - b.cls_begin[ci];
+        if (n_it == 0) continue;
+        HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, c.items + b.cls_begin[ci], n_it, c.queue + ci, s));
+    }
+    for (int g = 0; g < n_grains; ++g) {
+        if (counts[g] == 0) continue;
+        const Grain& gr = c.grains[grain_ids_host[g]];
+        hsd::ContractLaunch cl{c.Pt + b.offs[g], c.pscale, gr.Bt, gr.bscale, j_dev, counts[g], gr.n_bins,
+                               c.L, c.Lp, n_grains, g, w.cellmap + off[g]};
+        HSD_HIP(ctx, hsd::launch_contract(cl, s));
+    }
+    hsd::DiagLaunch dl{c.lam, j_dev, diag_dev, n_cells, c.L, n_grains, w.pairs, nfb};
+    HSD_HIP(ctx, hsd::launch_diag(dl, s));
     return HSD_OK;
 }
 

@@ -83,8 +83,9 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
         for (int i = 0; i < 4; ++i) {
             const int row = row0 + wr + bi * 16 + 4 * (lane >> 4) + i;
             if (row >= a.n_cells) continue;
-            const float ps = a.pscale[static_cast<size_t>(row) * a.n_gslots + a.gslot];
-            float* jrow = a.j + (static_cast<size_t>(row) * a.n_gslots + a.gslot) * a.L;
+            const size_t cell = a.rowmap ? static_cast<size_t>(a.rowmap[row]) : static_cast<size_t>(row);
+            const float ps = a.pscale[cell * a.n_gslots + a.gslot];
+            float* jrow = a.j + (cell * a.n_gslots + a.gslot) * a.L;
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
                 const int col = col0 + wc + bj * 16 + (lane & 15);
@@ -98,9 +99,10 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
 // 16-lane segment per pair; the other diagnostics come from the solver.
 __global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
     const int lane = threadIdx.x & 15;
-    const size_t pair = static_cast<size_t>(blockIdx.x) * 16 + (threadIdx.x >> 4);
-    const size_t n_pairs = static_cast<size_t>(a.n_cells) * a.n_gslots;
-    const bool valid = pair < n_pairs;
+    const size_t k = static_cast<size_t>(blockIdx.x) * 16 + (threadIdx.x >> 4);
+    const size_t n_k = a.pairs ? static_cast<size_t>(a.n_list) : static_cast<size_t>(a.n_cells) * a.n_gslots;
+    const bool valid = k < n_k;
+    const size_t pair = !valid ? 0 : (a.pairs ? static_cast<size_t>(a.pairs[k]) : k);
     const float* jr = a.j + (valid ? pair : 0) * a.L;
     double em = 0.0;
     for (int j = lane; j + 1 < a.L; j += 16)
@@ -120,7 +122,7 @@ hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s) {
-    const size_t n_pairs = static_cast<size_t>(a.n_cells) * a.n_gslots;
+    const size_t n_pairs = a.pairs ? static_cast<size_t>(a.n_list) : static_cast<size_t>(a.n_cells) * a.n_gslots;
     if (n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_diag, dim3(static_cast<unsigned>((n_pairs + 15) / 16)), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -46,7 +46,7 @@ struct alignas(16) DPar {
 // Device tables of one registered grain (all owned by the context).
 struct Grain {
     int n_bins = 0;
-    double E_lo = 0, E_hi = 0, n_atoms = 0, theta = 0, longwave = 0;
+    double E_lo = 0, E_hi = 0, n_atoms = 0, theta = 0, longwave = 0, radius = 0;
     double* E = nullptr;       // [n]
     double* dE = nullptr;      // [n]
     double* T = nullptr;       // [n]
@@ -130,6 +130,11 @@ struct SolveLaunch {
     float* diag;              // [n_cells * n_gslots * 4] or null
     double* P64;              // [n_cells * nb] (single-slot P output) or null
     unsigned* errword;
+    // optional pair lists: slot s solves the cells cellmap[seg_off[s] .. + seg_cnt[s]]
+    // (its P~ rows in that order); null = every cell for every slot
+    const int* cellmap = nullptr;
+    const int* seg_off = nullptr;
+    const int* seg_cnt = nullptr;
 };
 // Launch the fused rates -> B -> recursion kernel for every pair of the
 // listed (slot, first cell) items of bin-count class cls, with the class's
@@ -152,7 +157,8 @@ struct ContractLaunch {
     const float* Bt;          // [nb][Lp]
     const float* bscale;      // [Lp]
     float* j;                 // [n_cells][n_gslots][L]
-    int n_cells, nb, L, Lp, n_gslots, gslot;
+    int n_cells, nb, L, Lp, n_gslots, gslot;   // n_cells: rows of the slot's P~ block
+    const int* rowmap = nullptr;              // optional: cell of each row (pair lists)
 };
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
 
@@ -161,7 +167,64 @@ struct DiagLaunch {
     const float* j;           // [n_cells][n_gslots][L]
     float* diag;              // [n_cells][n_gslots][4]; writes entry 1
     int n_cells, L, n_gslots;
+    const long long* pairs = nullptr;   // optional: only these pair indices (cell * n_gslots + slot)
+    long long n_list = 0;
 };
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
+
+// ---- learned surrogate (hsd_surrogate.hip) ----
+struct Sur {
+    Ctx* c = nullptr;
+    int L = 0;
+    int widths[5] = {33, 256, 256, 256, 0};
+    long long n_params = 0;
+    long long off_W[4] = {}, off_b[4] = {};
+    float* w = nullptr;        // master weights
+    float* g = nullptr;        // gradients
+    float* m = nullptr;        // Adam moments
+    float* v = nullptr;
+    long long t = 0;           // Adam steps taken
+    float* xm = nullptr;       // [33] input means / stds
+    float* xs = nullptr;
+    float* ym = nullptr;       // [L] target means / stds
+    float* ys = nullptr;
+    float* wq = nullptr;       // [L] 4 pi x trapezoid weights
+    bool have_norm = false;
+    // training workspace (grown on demand)
+    int cap_B = 0;
+    float *Xb = nullptr, *Yb = nullptr, *Z[3] = {}, *H[3] = {}, *Yh = nullptr, *dY = nullptr, *dZ[2] = {};
+    long long* idx = nullptr;
+    double* loss = nullptr;
+    int splits = 1;            // K splits of the weight-gradient products
+    float* split_work = nullptr;
+    std::vector<float> loss_trace;
+};
+
+hipError_t sur_alloc(Sur& s);
+void sur_free(Sur& s);
+hipError_t sur_grow(Sur& s, int B);
+hipError_t sur_bands(const Ctx& c, const double* u, int n_cells, float* bands, hipStream_t st);
+hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* const* cabs, const float* loga,
+                     long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st);
+hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st);
+hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd);
+hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep_z);
+hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st);
+hipError_t sur_loss(Sur& s, int B, hipStream_t st);
+hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st);
+hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st);
+hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
+hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
+hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,
+                         hipStream_t st);
+hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, long long row0, int n_sel,
+                            int n_slots, const int* sel, float* j, float* emit, float* h0, float* h1,
+                            hipStream_t st);
+hipError_t sur_flag(const float* emit, const double* A, long long n, float tol, unsigned char* flag, unsigned* count,
+                    hipStream_t st);
+hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
+                    const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
+hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,
+                          int* cellmap, long long* pairs, hipStream_t st);
 
 }  // namespace hsd

@@ -366,6 +366,9 @@ struct KArgs {
     const int2* items;
     int n_items;               // work items (physical) or blocks of pairs (given rates)
     unsigned* queue;           // persistent launch: next-item counter (zero at launch), else null
+    const int* cellmap;        // optional: cells of each slot's pairs, slot s at seg_off[s] .. + seg_cnt[s]
+    const int* seg_off;
+    const int* seg_cnt;
     // given-rates test hook
     const double* A;
     const double* cool;
@@ -405,20 +408,29 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         const int q = lane & (P - 1);
         const int seg = lane / P;
 
-        int gslot = 0, cell, nb;
+        int gslot = 0, cell, nb, rowk;   // rowk: the pair's row in its slot's P~ block
+        bool live;
         GrainView gv{};
         if constexpr (!GIVEN) {
             const int2 it = a.items[item];
             gslot = it.x;
-            cell = it.y + wave * PPW + seg;
+            rowk = it.y + wave * PPW + seg;
             gv = a.views[gslot];
             nb = gv.nb;
+            if (a.cellmap) {
+                // a list of cells per slot (the surrogate's fallback pairs)
+                live = rowk < a.seg_cnt[gslot];
+                cell = live ? a.cellmap[a.seg_off[gslot] + rowk] : 0;
+            } else {
+                live = rowk < a.n_cells;
+                cell = rowk;
+            }
         } else {
             cell = (item * WAVES + wave) * PPW + seg;
+            rowk = cell;
             nb = a.nb_given;
+            live = cell < a.n_pairs;
         }
-        const int n_live = GIVEN ? a.n_pairs : a.n_cells;
-        const bool live = cell < n_live;
         const int cellc = live ? cell : 0;
 
         Rec<R> st;
@@ -581,7 +593,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             }
             if constexpr (!GIVEN) {
                 if (a.Pt) {
-                    float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(cell) * nb;
+                    float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(rowk) * nb;
                     const double inv = 1.0 / mxx;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -742,6 +754,9 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int cls, const int2
     ka.P64 = sl.P64;
     ka.errword = sl.errword;
     ka.items = items_dev;
+    ka.cellmap = sl.cellmap;
+    ka.seg_off = sl.seg_off;
+    ka.seg_cnt = sl.seg_cnt;
     unsigned* q = cfg.persistent ? queue : nullptr;
     if (cfg.persistent && !queue) return hipErrorInvalidValue;
     ka.tabstride = tab_stride(c, cls);

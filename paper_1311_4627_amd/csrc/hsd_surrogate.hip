@@ -1,0 +1,773 @@
+// Learned surrogate of the emissivity solve: an MLP 33 -> 256 -> 256 -> 256 -> L
+// (GELU after the hidden layers) mapping the field's energy in 32 wavelength
+// bands and the grain radius to log10(j_lambda / A), A the absorbed power.  It
+// is trained here on spectra of the plain solve, on the GPU (BF16 matrix-core
+// products with FP32 accumulation, FP32 master weights, Adam), and evaluated
+// with its energy balance checked per pair.  The paper's introduction names
+// precomputed emissivity tables as the cheap alternative to the full solve;
+// this is a learned table of that kind with the plain solve as its fallback.
+//
+// Layouts.  Parameters are one FP32 vector, layer by layer: W_l row-major
+// [out][in], then b_l.  Raw inputs X are [n][33]: log10 of the band energies
+// int u dlambda (trapezoid over grid nodes floor(b (L-1) / 32) ..
+// floor((b+1) (L-1) / 32)), then log10 of the radius in cm.  Raw targets Y are
+// [n][L]: log10(max(j, 1e-6 max j) / A) (the floor keeps wavelengths that carry
+// no power from dominating the fit).  Inputs are z-scored per column; targets
+// have their column means removed and are divided by one pooled standard
+// deviation, so the loss weighs an error in dex the same at every wavelength.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "hsd_internal.h"
+
+namespace hsd {
+namespace {
+
+constexpr int kBands = 32;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> bfloat16, round to nearest even (finite values).
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(u >> 16);
+}
+
+__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return phi_cdf(z) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ---- per-cell band energies --------------------------------------------------
+// One 64-lane wave per cell; lane b < 32 integrates band b in FP64.
+__global__ void __launch_bounds__(256) k_bands(const double* u, const double* lam, int n_cells, int L,
+                                               float* bands) {
+    const int lane = threadIdx.x & 63;
+    const int cell = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (cell >= n_cells || lane >= kBands) return;
+    const int e0 = (lane * (L - 1)) / kBands, e1 = ((lane + 1) * (L - 1)) / kBands;
+    const double* uc = u + static_cast<size_t>(cell) * L;
+    double s = 0.0;
+    for (int j = e0; j < e1; ++j) s += 0.5 * (uc[j] + uc[j + 1]) * (lam[j + 1] - lam[j]);
+    bands[static_cast<size_t>(cell) * kBands + lane] = static_cast<float>(log10(fmax(s, 1e-300)));
+}
+
+// Pair rows R = cell * n_sel + s (s indexes the selected grains): raw inputs
+// (33 floats) and the absorbed power A = int c u C_abs dlambda (trapezoid,
+// FP64) of rows R = row0 .. row0 + n_rows - 1, written at R - row0.  One wave
+// per pair.
+struct PairArgs {
+    const double* u;
+    const double* lam;
+    const float* bands;        // [n_cells][32]
+    const double* const* cabs; // [n_sel] device pointers to C_abs tables
+    const float* loga;         // [n_sel] log10 radius (cm)
+    long long row0, n_rows;
+    int n_sel, L;
+    float* X;                  // [n_rows][33] or null
+    double* A;                 // [n_rows] or null
+};
+
+__global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
+    const int lane = threadIdx.x & 63;
+    const long long r = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= a.n_rows) return;
+    const long long rg = a.row0 + r;
+    const long long cell = rg / a.n_sel;
+    const int s = static_cast<int>(rg - cell * a.n_sel);
+    if (a.X) {
+        float* xr = a.X + r * 33;
+        if (lane < kBands) xr[lane] = a.bands[cell * kBands + lane];
+        if (lane == kBands) xr[kBands] = a.loga[s];
+    }
+    if (a.A) {
+        const double* uc = a.u + cell * a.L;
+        const double* cb = a.cabs[s];
+        double acc = 0.0;
+        for (int j = lane; j + 1 < a.L; j += 64)
+            acc += 0.5 * (uc[j] * cb[j] + uc[j + 1] * cb[j + 1]) * (a.lam[j + 1] - a.lam[j]);
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+        if (lane == 0) a.A[r] = kLight * acc;
+    }
+}
+
+// Raw targets from spectra: one wave per row.
+__global__ void __launch_bounds__(256) k_targets(const float* j, const double* A, long long n, int L, float* Y) {
+    const int lane = threadIdx.x & 63;
+    const long long r = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const float* jr = j + r * L;
+    float mx = 0.f;
+    for (int k = lane; k < L; k += 64) mx = fmaxf(mx, jr[k]);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+    const double fl = 1e-6 * static_cast<double>(mx);
+    const double a = A[r];
+    for (int k = lane; k < L; k += 64)
+        Y[r * L + k] = static_cast<float>(log10(fmax(static_cast<double>(jr[k]), fl) / a));
+}
+
+// Column sums and sums of squares in FP64 (one thread per column, blocks of
+// rows accumulated with double atomics).
+__global__ void __launch_bounds__(256) k_colstats(const float* Xm, long long n, int w, long long rows_per_block,
+                                                  double* sum, double* sq) {
+    const int col = blockIdx.y * 256 + threadIdx.x;
+    if (col >= w) return;
+    const long long r0 = static_cast<long long>(blockIdx.x) * rows_per_block;
+    const long long r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
+    double s = 0.0, q = 0.0;
+    for (long long r = r0; r < r1; ++r) {
+        const double v = Xm[r * w + col];
+        s += v;
+        q += v * v;
+    }
+    atomicAdd(sum + col, s);
+    atomicAdd(sq + col, q);
+}
+
+// Gather a minibatch and z-score it: rows idx[b] of X (33 wide) and Y (L wide).
+__global__ void __launch_bounds__(256) k_gather(const float* X, const float* Y, const long long* idx, int B, int L,
+                                                const float* xm, const float* xs, const float* ym, const float* ys,
+                                                float* Xb, float* Yb) {
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const long long r = idx[b];
+    for (int k = threadIdx.x; k < 33; k += blockDim.x) Xb[b * 33 + k] = (X[r * 33 + k] - xm[k]) / xs[k];
+    if (Y)
+        for (int k = threadIdx.x; k < L; k += blockDim.x)
+            Yb[static_cast<long long>(b) * L + k] = (Y[r * L + k] - ym[k]) / ys[k];
+}
+
+// z-score rows in place order: out[r] = (X[r] - m) / s for all rows (inference inputs).
+__global__ void __launch_bounds__(256) k_norm_rows(const float* X, long long n, int w, const float* m, const float* s,
+                                                   float* out) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n * w) return;
+    const int k = static_cast<int>(i % w);
+    out[i] = (X[i] - m[k]) / s[k];
+}
+
+// Minibatch indices from a counter-based generator (SplitMix64 of seed and
+// position; uniform enough for sampling with replacement).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ void k_batch_idx(unsigned long long seed, long long step, int B, long long n, long long* idx) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const unsigned long long h = splitmix64(seed ^ splitmix64(static_cast<unsigned long long>(step) * B + b));
+    idx[b] = static_cast<long long>(h % static_cast<unsigned long long>(n));
+}
+
+// Loss and its gradient with respect to the network output:
+// L = mean (yhat - y)^2, dL/dyhat = 2 (yhat - y) / (B L).  A fixed grid walks
+// the elements; each block adds its FP64 partial sum of squares once.
+__global__ void __launch_bounds__(256) k_loss(const float* yhat, const float* y, long long n, float scale,
+                                              float* dy, double* loss) {
+    __shared__ double red[4];
+    double l = 0.0;
+    for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * 256) {
+        const float r = yhat[i] - y[i];
+        dy[i] = scale * r;
+        l += static_cast<double>(r) * r;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) l += __shfl_xor(l, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
+}
+
+// Bias gradient, first stage: column sums of dZ [B][N] over chunks of 32
+// rows (blockIdx.y), written per chunk; k_split_sum adds the chunks in order.
+__global__ void __launch_bounds__(256) k_colsum(const float* dz, int B, int N, float* part) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const int b0 = blockIdx.y * 32, b1 = min(B, b0 + 32);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) s += dz[static_cast<long long>(b) * N + j];
+    part[static_cast<long long>(blockIdx.y) * N + j] = s;
+}
+
+// Adam (Kingma & Ba) with bias correction folded into the step size.
+__global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m, float* v, long long n, float lr_t,
+                                              float b1, float b2, float eps_t) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+}
+
+// ---- BF16 matrix-core GEMM ----------------------------------------------------------
+// C[i][j] = epilogue(sum_k A[i][k] B[k][j]) with arbitrary strides: A[i][k] at
+// A[i*sai + k*sak], B[k][j] at B[k*sbk + j*sbj].  Operands are FP32 in memory
+// and rounded to BF16 as they are staged in LDS; the v_mfma_f32_16x16x16_bf16
+// products accumulate in FP32.  Operand layout of that instruction: lane l
+// supplies A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16];
+// accumulator register i of lane l is D[4 (l / 16) + i][l % 16].  One
+// 256-thread block computes a 64 x 64 tile, each wave a 32 x 32 quarter.
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3, EPI_SPECTRUM = 4 };
+
+struct GemmArgs {
+    const float* A; long long sai, sak;
+    const float* B; long long sbk, sbj;
+    float* C; long long ldc;           // EPI_BIAS_GELU: pre-activations (may be null)
+    float* C2; long long ldc2;         // EPI_BIAS_GELU: activations
+    const float* bias;                 // [N]
+    const float* aux; long long ldaux; // EPI_GELU_BWD: pre-activations
+    int M, N, K;
+    int kchunk;                        // split K: block z sums k in [z kchunk, (z+1) kchunk) (EPI_STORE only)
+    long long split_stride;            //   and writes its partial at C + z split_stride
+    // EPI_SPECTRUM: j = A_row 10^(y s_j + m_j), scattered to pair rows, and
+    // 4 pi int j dlambda accumulated per row
+    const float* ym; const float* ys;
+    const double* Arow;               // absorbed power per row
+    const float* wq;                  // [N] trapezoid weights times 4 pi
+    float* emit;                      // [M] accumulated emitted power
+    long long row0;                   // global row of the tile's row 0 (for the pair map)
+    int n_sel, n_slots;
+    const int* sel;                   // [n_sel] slot of each selected grain
+};
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    constexpr int BM = 64, BN = 64, BK = 32, LK = BK + 8;
+    __shared__ __align__(16) unsigned short As[BM][LK];
+    __shared__ __align__(16) unsigned short Bs[BN][LK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long m0 = static_cast<long long>(blockIdx.y) * BM;
+    const int n0 = blockIdx.x * BN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool a_kfast = g.sak == 1;
+    const bool b_kfast = g.sbk == 1;
+    int kbeg = 0, kend = g.K;
+    float* Cz = g.C;
+    if constexpr (EPI == EPI_STORE) {
+        if (g.kchunk > 0) {
+            kbeg = blockIdx.z * g.kchunk;
+            kend = min(g.K, kbeg + g.kchunk);
+            Cz = g.C + blockIdx.z * g.split_stride;
+        }
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int e = 0; e < (BM * BK) / 256; ++e) {
+            const int idx = tid + 256 * e;
+            const int i = a_kfast ? idx / BK : idx % BM;
+            const int k = a_kfast ? idx % BK : idx / BM;
+            const long long gi = m0 + i;
+            const int gk = k0 + k;
+            float v = 0.f;
+            if (gi < g.M && gk < kend) v = g.A[gi * g.sai + gk * g.sak];
+            As[i][k] = to_bf16(v);
+        }
+#pragma unroll
+        for (int e = 0; e < (BN * BK) / 256; ++e) {
+            const int idx = tid + 256 * e;
+            const int j = b_kfast ? idx / BK : idx % BN;
+            const int k = b_kfast ? idx % BK : idx / BN;
+            const int gj = n0 + j, gk = k0 + k;
+            float v = 0.f;
+            if (gj < g.N && gk < kend) v = g.B[static_cast<long long>(gk) * g.sbk + static_cast<long long>(gj) * g.sbj];
+            Bs[j][k] = to_bf16(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            bf16x4 af[2], bf[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                af[t] = *reinterpret_cast<const bf16x4*>(&As[wm + t * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+                bf[t] = *reinterpret_cast<const bf16x4*>(&Bs[wn + t * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long long i = m0 + wm + a * 16 + 4 * (lane >> 4) + r;
+            float part = 0.f;
+            float* jrow = nullptr;
+            double Ai = 0.0;
+            if constexpr (EPI == EPI_SPECTRUM) {
+                if (i < g.M) {
+                    const long long gr = g.row0 + i;
+                    const long long cell = gr / g.n_sel;
+                    const int s = static_cast<int>(gr - cell * g.n_sel);
+                    jrow = g.C + (cell * g.n_slots + g.sel[s]) * g.ldc;
+                    Ai = g.Arow[i];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int j = n0 + wn + b * 16 + (lane & 15);
+                if (i >= g.M || j >= g.N) continue;
+                const float v = acc[a][b][r];
+                if constexpr (EPI == EPI_STORE) {
+                    Cz[i * g.ldc + j] = v;
+                } else if constexpr (EPI == EPI_BIAS) {
+                    g.C[i * g.ldc + j] = v + g.bias[j];
+                } else if constexpr (EPI == EPI_BIAS_GELU) {
+                    const float z = v + g.bias[j];
+                    if (g.C) g.C[i * g.ldc + j] = z;
+                    g.C2[i * g.ldc2 + j] = gelu(z);
+                } else if constexpr (EPI == EPI_GELU_BWD) {
+                    g.C[i * g.ldc + j] = v * gelu_grad(g.aux[i * g.ldaux + j]);
+                } else {
+                    const float y = (v + g.bias[j]) * g.ys[j] + g.ym[j];
+                    const float jv = static_cast<float>(Ai) * exp2f(y * 3.32192809488736235f);
+                    jrow[j] = jv;
+                    part += jv * g.wq[j];
+                }
+            }
+            if constexpr (EPI == EPI_SPECTRUM) {
+                // the 16 lanes of a row group hold this row's columns
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 16);
+                if ((lane & 15) == 0 && i < g.M) atomicAdd(g.emit + i, part);
+            }
+        }
+    }
+}
+
+template <int EPI>
+hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    const dim3 grid((g.N + 63) / 64, static_cast<unsigned>((g.M + 63) / 64));
+    hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// Sum of the split-K partials: out[e] = sum_z part[z * stride + e], z in order.
+__global__ void __launch_bounds__(256) k_split_sum(const float* part, int nz, long long stride, long long n,
+                                                   float* out) {
+    const long long e = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= n) return;
+    float acc = 0.f;
+    for (int z = 0; z < nz; ++z) acc += part[z * stride + e];
+    out[e] = acc;
+}
+
+// C[M][N] = A . B with K split over `nz` blocks along z into a workspace of
+// nz * M * N floats, then summed in a fixed order (deterministic).
+hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    float* out = g.C;
+    const long long mn = static_cast<long long>(g.M) * g.N;
+    g.kchunk = ((g.K + nz - 1) / nz + 31) / 32 * 32;
+    nz = (g.K + g.kchunk - 1) / g.kchunk;
+    g.C = work;
+    g.ldc = g.N;
+    g.split_stride = mn;
+    const dim3 grid((g.N + 63) / 64, static_cast<unsigned>((g.M + 63) / 64), static_cast<unsigned>(nz));
+    hipLaunchKernelGGL((k_gemm<EPI_STORE>), grid, dim3(256), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_sum, dim3(static_cast<unsigned>((mn + 255) / 256)), dim3(256), 0, s, work, nz, mn, mn,
+                       out);
+    return hipGetLastError();
+}
+
+// Flag rows whose emitted power misses the absorbed power by more than tol.
+__global__ void __launch_bounds__(256) k_flag(const float* emit, const double* A, long long n, float tol,
+                                              unsigned char* flag, unsigned* count) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    bool f = false;
+    if (i < n) {
+        const double r = static_cast<double>(emit[i]) / A[i];
+        f = !(fabs(r - 1.0) <= tol);
+        flag[i] = f ? 1 : 0;
+    }
+    const unsigned long long b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, static_cast<unsigned>(__popcll(b)));
+}
+
+// Per-pair diagnostics of surrogate rows and the energy-balance check: diag =
+// (A, 4 pi int j dlambda, A, flags) with flags bit 3 (value from the surrogate)
+// and bit 4 (|emitted / A - 1| > tol: the pair goes to the plain solve);
+// cnt[slot] and cnt[n_slots] count the flagged pairs.
+__global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, long long row0, long long n,
+                                                  int n_sel, int n_slots, const int* sel, float tol, float* diag,
+                                                  unsigned* cnt) {
+    const long long r = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= n) return;
+    const long long rg = row0 + r;
+    const long long cell = rg / n_sel;
+    const int slot = sel[static_cast<int>(rg - cell * n_sel)];
+    const double a = A[r];
+    const float e = emit[r];
+    const bool bad = !(fabs(static_cast<double>(e) / a - 1.0) <= tol);
+    float* d = diag + (cell * n_slots + slot) * 4;
+    d[0] = static_cast<float>(a);
+    d[1] = e;
+    d[2] = static_cast<float>(a);
+    d[3] = bad ? 24.f : 8.f;
+    if (bad) {
+        atomicAdd(cnt + slot, 1u);
+        atomicAdd(cnt + n_slots, 1u);
+    }
+}
+
+// Lists of the flagged pairs per slot (order within a slot is arbitrary; each
+// pair's result does not depend on it).
+__global__ void __launch_bounds__(256) k_fb_scatter(const float* diag, long long n_pairs, int n_slots,
+                                                    const int* seg_off, unsigned* cursor, int* cellmap,
+                                                    long long* pairs) {
+    const long long p = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (p >= n_pairs) return;
+    if (!(static_cast<int>(diag[p * 4 + 3]) & 16)) return;
+    const int slot = static_cast<int>(p % n_slots);
+    const unsigned pos = atomicAdd(cursor + slot, 1u);
+    const long long k = seg_off[slot] + static_cast<long long>(pos);
+    cellmap[k] = static_cast<int>(p / n_slots);
+    pairs[k] = p;
+}
+
+}  // namespace
+
+// ---- host side ------------------------------------------------------------------------
+
+namespace {
+
+void sur_layout(Sur& s) {
+    long long o = 0;
+    for (int l = 0; l < 4; ++l) {
+        s.off_W[l] = o;
+        o += static_cast<long long>(s.widths[l + 1]) * s.widths[l];
+        s.off_b[l] = o;
+        o += s.widths[l + 1];
+    }
+    s.n_params = o;
+}
+
+}  // namespace
+
+hipError_t sur_alloc(Sur& s) {
+    sur_layout(s);
+    hipError_t e = hipSuccess;
+    auto al = [&](auto*& p, size_t n) {
+        if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
+    };
+    al(s.w, s.n_params); al(s.g, s.n_params); al(s.m, s.n_params); al(s.v, s.n_params);
+    al(s.xm, 33); al(s.xs, 33); al(s.ym, s.L); al(s.ys, s.L); al(s.wq, s.L); al(s.loss, 1);
+    if (e == hipSuccess) e = hipMemset(s.m, 0, sizeof(float) * s.n_params);
+    if (e == hipSuccess) e = hipMemset(s.v, 0, sizeof(float) * s.n_params);
+    if (e == hipSuccess) {
+        std::vector<float> wq(s.L, 0.f);
+        const std::vector<double>& lam = s.c->lam_host;
+        for (int j = 0; j + 1 < s.L; ++j) {
+            const double h = 0.5 * (lam[j + 1] - lam[j]) * 4.0 * kPi;
+            wq[j] += static_cast<float>(h);
+            wq[j + 1] += static_cast<float>(h);
+        }
+        e = hipMemcpy(s.wq, wq.data(), sizeof(float) * s.L, hipMemcpyHostToDevice);
+    }
+    return e;
+}
+
+void sur_free(Sur& s) {
+    for (float* p : {s.w, s.g, s.m, s.v, s.xm, s.xs, s.ym, s.ys, s.wq, s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
+    for (int i = 0; i < 3; ++i) {
+        (void)hipFree(s.Z[i]);
+        (void)hipFree(s.H[i]);
+    }
+    for (int i = 0; i < 2; ++i) (void)hipFree(s.dZ[i]);
+    (void)hipFree(s.idx);
+    (void)hipFree(s.loss);
+    (void)hipFree(s.split_work);
+}
+
+hipError_t sur_grow(Sur& s, int B) {
+    if (B <= s.cap_B) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    for (float* p : {s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
+    for (int i = 0; i < 3; ++i) {
+        (void)hipFree(s.Z[i]);
+        (void)hipFree(s.H[i]);
+        s.Z[i] = s.H[i] = nullptr;
+    }
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(s.dZ[i]);
+        s.dZ[i] = nullptr;
+    }
+    (void)hipFree(s.idx);
+    s.Xb = s.Yb = s.Yh = s.dY = nullptr;
+    s.idx = nullptr;
+    s.cap_B = 0;
+    auto al = [&](auto*& p, size_t n) {
+        if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
+    };
+    const size_t b = static_cast<size_t>(B);
+    al(s.Xb, b * 33); al(s.Yb, b * s.L); al(s.Yh, b * s.L); al(s.dY, b * s.L);
+    for (int i = 0; i < 3; ++i) {
+        al(s.Z[i], b * 256);
+        al(s.H[i], b * 256);
+    }
+    al(s.dZ[0], b * 256); al(s.dZ[1], b * 256);
+    al(s.idx, b);
+    // split K so that the weight-gradient products (at most 500 x 256 outputs,
+    // K = batch) spread over a few hundred blocks
+    s.splits = std::max(1, std::min(32, B / 256));
+    (void)hipFree(s.split_work);
+    s.split_work = nullptr;
+    al(s.split_work, static_cast<size_t>(s.splits) * std::max(s.L, 256) * 256 +
+                         static_cast<size_t>((B + 31) / 32) * std::max(s.L, 256));
+    if (e == hipSuccess) s.cap_B = B;
+    return e;
+}
+
+hipError_t sur_bands(const Ctx& c, const double* u, int n_cells, float* bands, hipStream_t st) {
+    if (n_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bands, dim3((n_cells + 3) / 4), dim3(256), 0, st, u, c.lam, n_cells, c.L, bands);
+    return hipGetLastError();
+}
+
+hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* const* cabs, const float* loga,
+                     long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st) {
+    if (n_rows <= 0) return hipSuccess;
+    PairArgs p{u, c.lam, bands, cabs, loga, row0, n_rows, n_sel, c.L, X, A};
+    hipLaunchKernelGGL(k_pairs, dim3(static_cast<unsigned>((n_rows + 3) / 4)), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_targets, dim3(static_cast<unsigned>((n + 3) / 4)), dim3(256), 0, st, j, A, n, L, Y);
+    return hipGetLastError();
+}
+
+// Column means and standard deviations of a [n][w] FP32 matrix (FP64 sums).
+hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd) {
+    double* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(double) * 2 * w);
+    if (e == hipSuccess) e = hipMemset(d, 0, sizeof(double) * 2 * w);
+    const long long rpb = 1024;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_colstats, dim3(static_cast<unsigned>((n + rpb - 1) / rpb), (w + 255) / 256), dim3(256),
+                           0, nullptr, Xm, n, w, rpb, d, d + w);
+        e = hipGetLastError();
+    }
+    std::vector<double> h(2 * w);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d, sizeof(double) * 2 * w, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return e;
+    mean.resize(w);
+    sd.resize(w);
+    for (int k = 0; k < w; ++k) {
+        mean[k] = h[k] / n;
+        const double var = h[w + k] / n - mean[k] * mean[k];
+        sd[k] = var > 0.0 ? std::sqrt(var) : 1.0;
+    }
+    return hipSuccess;
+}
+
+namespace {
+
+GemmArgs nt(const float* A, int lda, const float* W, int ldw, float* C, int ldc, int M, int N, int K) {
+    // C[M][N] = A[M][K] . W[N][K]^T
+    GemmArgs g{};
+    g.A = A; g.sai = lda; g.sak = 1;
+    g.B = W; g.sbk = 1; g.sbj = ldw;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    return g;
+}
+
+}  // namespace
+
+// Forward pass of a batch of B normalised rows Xb [B][33]; keeps the
+// pre-activations Z and activations H (training) and writes the output Yh.
+hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep_z) {
+    hipError_t e = hipSuccess;
+    const float* h = Xb;
+    int in = 33;
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+        GemmArgs g = nt(h, in, s.w + s.off_W[l], in, keep_z ? s.Z[l] : nullptr, 256, B, 256, in);
+        g.C2 = s.H[l];
+        g.ldc2 = 256;
+        g.bias = s.w + s.off_b[l];
+        e = gemm<EPI_BIAS_GELU>(g, st);
+        h = s.H[l];
+        in = 256;
+    }
+    if (e != hipSuccess) return e;
+    GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, s.Yh, s.L, B, s.L, 256);
+    g.bias = s.w + s.off_b[3];
+    return gemm<EPI_BIAS>(g, st);
+}
+
+// Backward pass from dY (= dL/dYh) into s.g (weights and biases).
+hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    const float* dz = s.dY;
+    int nout = s.L;
+    for (int l = 3; l >= 0 && e == hipSuccess; --l) {
+        const int nin = s.widths[l];
+        const float* hin = l > 0 ? s.H[l - 1] : Xb;
+        // dW[nout][nin] = dz^T [nout][B] . hin [B][nin]
+        GemmArgs g{};
+        g.A = dz; g.sai = 1; g.sak = nout;
+        g.B = hin; g.sbk = nin; g.sbj = 1;
+        g.C = s.g + s.off_W[l]; g.ldc = nin;
+        g.M = nout; g.N = nin; g.K = B;
+        e = gemm_splitk(g, s.splits, s.split_work, st);
+        if (e != hipSuccess) break;
+        const int nchunk = (B + 31) / 32;
+        hipLaunchKernelGGL(k_colsum, dim3((nout + 255) / 256, nchunk), dim3(256), 0, st, dz, B, nout, s.split_work);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_split_sum, dim3((nout + 255) / 256), dim3(256), 0, st, s.split_work, nchunk,
+                               static_cast<long long>(nout), static_cast<long long>(nout), s.g + s.off_b[l]);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess || l == 0) break;
+        // dz_prev[B][nin] = (dz [B][nout] . W [nout][nin]) * gelu'(Z[l-1])
+        float* dzp = s.dZ[l % 2];
+        GemmArgs h{};
+        h.A = dz; h.sai = nout; h.sak = 1;
+        h.B = s.w + s.off_W[l]; h.sbk = nin; h.sbj = 1;
+        h.C = dzp; h.ldc = nin;
+        h.aux = s.Z[l - 1]; h.ldaux = 256;
+        h.M = B; h.N = nin; h.K = nout;
+        e = gemm<EPI_GELU_BWD>(h, st);
+        dz = dzp;
+        nout = nin;
+    }
+    return e;
+}
+
+hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
+    const long long n = static_cast<long long>(B) * s.L;
+    hipError_t e = hipMemsetAsync(s.loss, 0, sizeof(double), st);
+    if (e != hipSuccess) return e;
+    const long long blocks = std::min<long long>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_loss, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, s.Yh, s.Yb, n,
+                       2.0f / static_cast<float>(n), s.dY, s.loss);
+    return hipGetLastError();
+}
+
+hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, st, X, Y, s.idx, B, s.L, s.xm, s.xs, s.ym, s.ys, s.Xb, s.Yb);
+    return hipGetLastError();
+}
+
+hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_idx, dim3((B + 255) / 256), dim3(256), 0, st, seed, step, B, n, s.idx);
+    return hipGetLastError();
+}
+
+hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st) {
+    std::vector<long long> h(B);
+    for (int b = 0; b < B; ++b) h[b] = first + b;
+    hipError_t e = hipMemcpyAsync(s.idx, h.data(), sizeof(long long) * B, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
+    ++s.t;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - std::pow(b1, static_cast<double>(s.t));
+    const double c2 = 1.0 - std::pow(b2, static_cast<double>(s.t));
+    // w -= lr (m / c1) / (sqrt(v / c2) + eps) = lr sqrt(c2) / c1 * m / (sqrt(v) + eps sqrt(c2))
+    const float lr_t = static_cast<float>(lr * std::sqrt(c2) / c1);
+    const float eps_t = static_cast<float>(eps * std::sqrt(c2));
+    hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((s.n_params + 255) / 256)), dim3(256), 0, st, s.w, s.g,
+                       s.m, s.v, s.n_params, lr_t, 0.9f, 0.999f, eps_t);
+    return hipGetLastError();
+}
+
+// Inference for rows [row0, row0 + M) of a selection: normalised inputs Xn
+// [M][33] -> spectra scattered to j (pair rows), emitted power per row.
+hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, long long row0, int n_sel,
+                            int n_slots, const int* sel, float* j, float* emit, float* h0, float* h1,
+                            hipStream_t st) {
+    hipError_t e = hipSuccess;
+    const float* h = Xn;
+    int in = 33;
+    float* bufs[2] = {h0, h1};
+    for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+        GemmArgs g = nt(h, in, s.w + s.off_W[l], in, nullptr, 256, M, 256, in);
+        g.C2 = bufs[l % 2];
+        g.ldc2 = 256;
+        g.bias = s.w + s.off_b[l];
+        e = gemm<EPI_BIAS_GELU>(g, st);
+        h = bufs[l % 2];
+        in = 256;
+    }
+    if (e != hipSuccess) return e;
+    GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, j, s.L, M, s.L, 256);
+    g.bias = s.w + s.off_b[3];
+    g.ym = s.ym;
+    g.ys = s.ys;
+    g.Arow = A;
+    g.wq = s.wq;
+    g.emit = emit;
+    g.row0 = row0;
+    g.n_sel = n_sel;
+    g.n_slots = n_slots;
+    g.sel = sel;
+    return gemm<EPI_SPECTRUM>(g, st);
+}
+
+hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm_rows, dim3(static_cast<unsigned>((n * w + 255) / 256)), dim3(256), 0, st, X, n, w, m,
+                       sd, out);
+    return hipGetLastError();
+}
+
+hipError_t sur_flag(const float* emit, const double* A, long long n, float tol, unsigned char* flag, unsigned* count,
+                    hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, emit, A, n, tol, flag,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
+                    const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, row0, n,
+                       n_sel, n_slots, sel, tol, diag, cnt);
+    return hipGetLastError();
+}
+
+hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,
+                          int* cellmap, long long* pairs, hipStream_t st) {
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fb_scatter, dim3(static_cast<unsigned>((n_pairs + 255) / 256)), dim3(256), 0, st, diag,
+                       n_pairs, n_slots, seg_off, cursor, cellmap, pairs);
+    return hipGetLastError();
+}
+
+}  // namespace hsd

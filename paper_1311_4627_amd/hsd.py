@@ -30,6 +30,9 @@ SYMBOLS = (
     "hsd_solve", "hsd_solve_P", "hsd_solve_from_rates", "hsd_sync", "hsd_set_timing", "hsd_phase_ms",
     "hsd_get_class_cfg", "hsd_set_class_cfg", "hsd_plan_create", "hsd_plan_launch", "hsd_plan_phase_ms",
     "hsd_plan_destroy", "hsd_autotune",
+    "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
+    "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
+    "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate",
 )
 
 N_CLASSES = 4
@@ -109,6 +112,27 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_autotune.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(hsd_tune_record), i32,
                                  ctypes.POINTER(i32)]
     lib.hsd_autotune.restype = ctypes.c_int
+    i64, fp = ctypes.c_int64, ctypes.POINTER(ctypes.c_float)
+    lib.hsd_sur_create.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.hsd_sur_destroy.argtypes = [vp]
+    lib.hsd_sur_destroy.restype = None
+    lib.hsd_sur_n_params.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.hsd_sur_set_params.argtypes = [vp, fp]
+    lib.hsd_sur_get_params.argtypes = [vp, fp]
+    lib.hsd_sur_set_norm.argtypes = [vp, dp, dp, dp, dp]
+    lib.hsd_sur_get_norm.argtypes = [vp, dp, dp, dp, dp]
+    lib.hsd_sur_features.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
+    lib.hsd_sur_targets.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.hsd_sur_fit_norm.argtypes = [vp, i64, vp, vp]
+    lib.hsd_sur_loss_grad.argtypes = [vp, i32, vp, vp, dp, fp]
+    lib.hsd_sur_train.argtypes = [vp, i64, vp, vp, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
+    lib.hsd_sur_predict.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
+    lib.hsd_solve_surrogate.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.c_float,
+                                        vp, vp, ctypes.POINTER(i64), vp]
+    for name in ("hsd_sur_create", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
+                 "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
+                 "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate"):
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
@@ -297,6 +321,53 @@ class Context:
             self._raise(st, "hsd_plan_create")
         return Plan(self, h, (u, j, diag))
 
+    def hsd_sur_features(self, u, grain_ids: Sequence[int], X=None, A=None, stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        n = n_cells * int(ids.shape[0])
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        if X is not None:
+            _check_dev(X, torch.float32, (n, 33), "X")
+        if A is not None:
+            _check_dev(A, torch.float64, (n,), "A")
+        st = self._lib.hsd_sur_features(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                        ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        X.data_ptr() if X is not None else None,
+                                        A.data_ptr() if A is not None else None, _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_sur_features")
+
+    def hsd_sur_targets(self, j, A, Y, stream=None):
+        import torch
+        n = int(A.shape[0])
+        _check_dev(j, torch.float32, (n, self.L), "j")
+        _check_dev(A, torch.float64, (n,), "A")
+        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        st = self._lib.hsd_sur_targets(self._h, n, j.data_ptr(), A.data_ptr(), Y.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_sur_targets")
+
+    def hsd_solve_surrogate(self, u, grain_ids: Sequence[int], surs: Sequence["Surrogate"], j, diag, tol=0.01,
+                            stream=None) -> int:
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        G = int(ids.shape[0])
+        if len(surs) != G:
+            raise ValueError("one surrogate per grain")
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(j, torch.float32, (n_cells, G, self.L), "j")
+        _check_dev(diag, torch.float32, (n_cells, G, 4), "diag")
+        hs = (ctypes.c_void_p * G)(*[s._h.value for s in surs])
+        nfb = ctypes.c_int64()
+        st = self._lib.hsd_solve_surrogate(self._h, n_cells, u.data_ptr(), G,
+                                           ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), hs, float(tol),
+                                           j.data_ptr(), diag.data_ptr(), ctypes.byref(nfb), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_solve_surrogate")
+        return int(nfb.value)
+
     def hsd_sync(self):
         st = self._lib.hsd_sync(self._h)
         if st != HSD_OK:
@@ -333,3 +404,103 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Surrogate:
+    """Owns one hsd_sur (a network on the context's device)."""
+
+    def __init__(self, ctx: Context):
+        self._ctx = ctx
+        self._lib = ctx._lib
+        h = ctypes.c_void_p()
+        st = self._lib.hsd_sur_create(ctx._h, ctypes.byref(h))
+        if st != HSD_OK:
+            ctx._raise(st, "hsd_sur_create")
+        self._h = h
+        n = ctypes.c_int64()
+        self._check(self._lib.hsd_sur_n_params(h, ctypes.byref(n)), "hsd_sur_n_params")
+        self.n_params = int(n.value)
+        self.L = ctx.L
+
+    def _check(self, st, what):
+        if st != HSD_OK:
+            self._ctx._raise(st, what)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hsd_sur_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hsd_sur_set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.n_params,):
+            raise ValueError(f"need {self.n_params} parameters")
+        self._check(self._lib.hsd_sur_set_params(self._h, _fptr(p)), "hsd_sur_set_params")
+
+    def hsd_sur_get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.hsd_sur_get_params(self._h, _fptr(p)), "hsd_sur_get_params")
+        return p
+
+    def hsd_sur_set_norm(self, x_mean, x_std, y_mean, y_std):
+        a, b = (np.ascontiguousarray(v, dtype=np.float64) for v in (x_mean, x_std))
+        c, d = (np.ascontiguousarray(v, dtype=np.float64) for v in (y_mean, y_std))
+        if a.shape != (33,) or b.shape != (33,) or c.shape != (self.L,) or d.shape != (self.L,):
+            raise ValueError("statistics have the wrong shape")
+        self._check(self._lib.hsd_sur_set_norm(self._h, _dptr(a), _dptr(b), _dptr(c), _dptr(d)), "hsd_sur_set_norm")
+
+    def hsd_sur_get_norm(self):
+        a, b, c, d = np.empty(33), np.empty(33), np.empty(self.L), np.empty(self.L)
+        self._check(self._lib.hsd_sur_get_norm(self._h, _dptr(a), _dptr(b), _dptr(c), _dptr(d)), "hsd_sur_get_norm")
+        return a, b, c, d
+
+    def hsd_sur_fit_norm(self, X, Y):
+        import torch
+        n = int(X.shape[0])
+        _check_dev(X, torch.float32, (n, 33), "X")
+        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        self._check(self._lib.hsd_sur_fit_norm(self._h, n, X.data_ptr(), Y.data_ptr()), "hsd_sur_fit_norm")
+
+    def hsd_sur_loss_grad(self, X, Y):
+        import torch
+        n = int(X.shape[0])
+        _check_dev(X, torch.float32, (n, 33), "X")
+        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        self._check(self._lib.hsd_sur_loss_grad(self._h, n, X.data_ptr(), Y.data_ptr(), ctypes.byref(loss), _fptr(g)),
+                    "hsd_sur_loss_grad")
+        return float(loss.value), g
+
+    def hsd_sur_train(self, X, Y, steps: int, batch: int, lr: float, seed: int = 4627):
+        import torch
+        n = int(X.shape[0])
+        _check_dev(X, torch.float32, (n, 33), "X")
+        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        trace = np.zeros(max(int(steps), 1), dtype=np.float32)
+        self._check(self._lib.hsd_sur_train(self._h, n, X.data_ptr(), Y.data_ptr(), int(steps), int(batch),
+                                            float(lr), int(seed), _fptr(trace)), "hsd_sur_train")
+        return trace[:int(steps)]
+
+    def hsd_sur_predict(self, u, grain_ids: Sequence[int], j, diag=None, stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(j, torch.float32, (n_cells, ids.shape[0], self.L), "j")
+        if diag is not None:
+            _check_dev(diag, torch.float32, (n_cells, ids.shape[0], 4), "diag")
+        self._check(self._lib.hsd_sur_predict(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                              ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), j.data_ptr(),
+                                              diag.data_ptr() if diag is not None else None, _stream_ptr(stream)),
+                    "hsd_sur_predict")
