@@ -128,6 +128,167 @@ def count_rates(ctx_tables, lam, grain) -> int:
     return tot
 
 
+def _band_error(jp, jr, lam):
+    """Per pair: max over bands holding >= 1e-3 of the reference's emitted
+    power of |J_b / J_b,ref - 1| (the bands and rule of the surrogate's
+    accuracy metric; the same definition as the reference MLP's)."""
+    L = lam.shape[0]
+    e = (np.arange(33) * (L - 1)) // 32
+    def bands(f):
+        seg = 0.5 * (f[:, 1:] + f[:, :-1]) * np.diff(lam)
+        cs = np.concatenate([np.zeros((f.shape[0], 1)), np.cumsum(seg, axis=1)], axis=1)
+        return cs[:, e[1:]] - cs[:, e[:-1]]
+    J, Jr = bands(jp.astype(np.float64)), bands(jr.astype(np.float64))
+    m = Jr >= 1e-3 * Jr.sum(axis=1, keepdims=True)
+    return np.where(m, np.abs(J / np.where(m, Jr, 1.0) - 1.0), 0.0).max(axis=1)
+
+
+def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
+    """Per composition: plain-solve the training cells, build inputs and
+    targets, fit the statistics and train; then the held-out band errors."""
+    from synth import surrogate as ssur
+    nets, report = {}, {}
+    for comp in ("carbonaceous", "silicate"):
+        sel = [i for i, g in zip(ids, w4.grains) if g.composition == comp]
+        G = len(sel)
+        t0 = time.perf_counter()
+        u = torch.tensor(make_fields(w4.lam_cm, w4.field_recipe, w4.n_cells), device="cuda:0")
+        n = w4.n_cells * G
+        j = torch.empty((w4.n_cells, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+        ctx.hsd_solve(u, sel, j, None)
+        X = torch.empty((n, 33), dtype=torch.float32, device="cuda:0")
+        A = torch.empty((n,), dtype=torch.float64, device="cuda:0")
+        ctx.hsd_sur_features(u, sel, X, A)
+        Y = torch.empty((n, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+        ctx.hsd_sur_targets(j.view(n, w4.n_lambda), A, Y)
+        ctx.hsd_sync()
+        del j, u
+        gen_s = time.perf_counter() - t0
+        sur = hsd.Surrogate(ctx)
+        sur.hsd_sur_set_params(ssur.init_params(w4.n_lambda))
+        sur.hsd_sur_fit_norm(X, Y)
+        t0 = time.perf_counter()
+        trace = sur.hsd_sur_train(X, Y, steps=steps, batch=batch, lr=lr)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del X, Y, A
+        # held-out cells: plain vs surrogate
+        nh = w4.notes["heldout_cells"]
+        uh = torch.tensor(make_fields(w4.lam_cm, w4.notes["heldout_recipe"], nh), device="cuda:0")
+        jr = torch.empty((nh, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+        jp = torch.empty_like(jr)
+        ctx.hsd_solve(uh, sel, jr, None)
+        sur.hsd_sur_predict(uh, sel, jp, None)
+        ctx.hsd_sync()
+        err = _band_error(jp.cpu().numpy().reshape(-1, w4.n_lambda), jr.cpu().numpy().reshape(-1, w4.n_lambda),
+                          w4.lam_cm)
+        report[comp] = {"train_pairs": n, "heldout_pairs": nh * G, "steps": steps, "batch": batch,
+                        "data_s": round(gen_s, 2), "train_s": round(train_s, 2),
+                        "loss_first": float(np.mean(trace[:20])), "loss_last": float(np.mean(trace[-100:])),
+                        "heldout_band_err": {"median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
+                                             "p99": float(np.quantile(err, 0.99)), "max": float(err.max())}}
+        log(f"{comp}: trained {steps} steps in {train_s:.1f} s; held-out band error median "
+            f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}")
+        nets[comp] = sur
+    return nets, report
+
+
+def bench_surrogate(args):
+    import torch
+    from paper_1311_4627_amd import autotune, hsd
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    w4 = synth.workload("c4_train")
+    ctx = hsd.Context(w4.lam_cm, device=0)
+    ids = [ctx.add_grain(g) for g in w4.grains]
+    nets, report = train_surrogates(torch, hsd, ctx, w4, ids, args.train_steps, 4096, 4e-3, log)
+    if args.workload == "c4_train":
+        tot_pairs = sum(r["train_pairs"] for r in report.values())
+        tot_s = sum(r["train_s"] for r in report.values())
+        line = {"metric": "surrogate training: samples per second (held-out band errors reported)",
+                "value": args.train_steps * 4096 * len(report) / tot_s, "unit": "samples/s", "n_gpus": 1,
+                "steps": args.train_steps, "warmup": 0, "ms_per_step": 1e3 * tot_s / (args.train_steps * len(report)),
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 matmul, f32 master",
+                "data": "synthetic", "config": {"workload": "c4_train", "train_pairs": tot_pairs,
+                                                "net": "33-256-256-256-500 GELU"},
+                "per_composition": report}
+        print(json.dumps(line))
+        return
+    # c5: 262144 cells x 64 radii x 2 compositions, plain vs surrogate + fallback
+    w5 = synth.workload("c5_surrogate")
+    assert [g.radius_cm for g in w5.grains] == [g.radius_cm for g in w4.grains]
+    surs = [nets[g.composition] for g in w5.grains]
+    u = torch.tensor(make_fields(w5.lam_cm, w5.field_recipe, w5.n_cells), device="cuda:0")
+    G = len(ids)
+    jpl = torch.empty((w5.n_cells, G, w5.n_lambda), dtype=torch.float32, device="cuda:0")
+    dpl = torch.empty((w5.n_cells, G, 4), dtype=torch.float32, device="cuda:0")
+    tuned = autotune.tune(ctx, u, ids, cache_path=TUNE_CACHE)
+    log(f"c5 launch configuration: {tuned['cfg']} (cached: {tuned['cached']})")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, out
+
+    t_plain, _ = timed(lambda: ctx.hsd_solve(u, ids, jpl, dpl, stream), args.steps)
+    log(f"plain: {t_plain * 1e3:.1f} ms per step")
+    jsu = torch.empty_like(jpl)
+    dsu = torch.empty_like(dpl)
+    t_sur, nfb = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=0.01, stream=stream), args.steps)
+    log(f"surrogate + fallback: {t_sur * 1e3:.1f} ms per step, {nfb} fallback pairs")
+    # the network alone (every pair), timed with HIP events around its kernels
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    carb = [i for i, g in zip(ids, w5.grains) if g.composition == "carbonaceous"]
+    jn = torch.empty((w5.n_cells, len(carb), w5.n_lambda), dtype=torch.float32, device="cuda:0")
+    nets["carbonaceous"].hsd_sur_predict(u, carb, jn, None)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    nets["carbonaceous"].hsd_sur_predict(u, carb, jn, None, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_net = ev0.elapsed_time(ev1) * 1e-3
+    del jn
+    # accuracy on a seeded 1% sample of the pairs, against the plain GPU solve
+    n_pairs = w5.n_cells * G
+    rng = np.random.default_rng(4627005)
+    samp = np.sort(rng.choice(n_pairs, n_pairs // 100, replace=False))
+    idx = torch.tensor(samp, device="cuda:0")
+    jp = jsu.view(n_pairs, -1).index_select(0, idx).cpu().numpy()
+    jr = jpl.view(n_pairs, -1).index_select(0, idx).cpu().numpy()
+    err = _band_error(jp, jr, w5.lam_cm)
+    flags = dsu.view(n_pairs, 4)[:, 3].index_select(0, idx).cpu().numpy().astype(np.int64)
+    by_sur = (flags & 8) != 0
+    log(f"1% sample: band error max {err.max():.4f} (surrogate pairs {err[by_sur].max() if by_sur.any() else 0:.4f}), "
+        f"median {np.median(err):.5f}")
+    half_pairs = w5.n_cells * len(carb)
+    out_bytes = half_pairs * w5.n_lambda * 4
+    line = {"metric": METRIC, "value": n_pairs / t_sur, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": t_sur * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16 matmul + f32/f64 fallback", "data": "synthetic",
+            "config": {"workload": "c5_surrogate", "cells": w5.n_cells, "grains": G, "n_lambda": w5.n_lambda,
+                       "tol": 0.01},
+            "plain_solves_per_s": n_pairs / t_plain, "speedup_vs_plain": t_plain / t_sur,
+            "fallback_fraction": nfb / n_pairs,
+            "sample_band_error": {"pairs": int(samp.shape[0]), "max": float(err.max()),
+                                  "p99": float(np.quantile(err, 0.99)), "median": float(np.median(err)),
+                                  "max_surrogate_pairs": float(err[by_sur].max()) if by_sur.any() else 0.0,
+                                  "reference": "plain GPU solve (matches the FP64 oracle to 1e-4)"},
+            "roofline": {"bound": "hbm", "kernel": "surrogate inference, one composition (network alone)",
+                         "achieved": out_bytes / t_net / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": out_bytes / t_net / 8e12, "traffic": None, "kernel_ms": t_net * 1e3,
+                         "bytes_per_launch": out_bytes},
+            "training": report}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +299,7 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=48)
     ap.add_argument("--eager", action="store_true", help="time hsd_solve calls instead of plan replays")
     ap.add_argument("--retune", action="store_true", help="time the launch configurations again")
+    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate training steps per composition")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -154,6 +316,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design note, "
               f"not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload in ("c4_train", "c5_surrogate"):
+        bench_surrogate(args)
+        return
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -33,11 +33,19 @@ def _load(path: str) -> Dict[str, dict]:
     return {}
 
 
+MAX_TUNE_CELLS = 16384
+
+
 def tune(ctx: "hsd.Context", u, grain_ids: Sequence[int], cache_path: Optional[str] = None,
          runs: int = 4, force: bool = False) -> dict:
     """Apply the cached configuration of this batch's key, or time and cache
-    it.  Returns {"key", "cached", "cfg": [per class], "records": [...]}."""
+    it.  Batches larger than MAX_TUNE_CELLS cells are timed (and keyed) on
+    their first MAX_TUNE_CELLS cells: by then every class has thousands of
+    work items and the ranking of configurations no longer changes.
+    Returns {"key", "cached", "cfg": [per class], "records": [...]}."""
     import torch
+    if int(u.shape[0]) > MAX_TUNE_CELLS:
+        u = u[:MAX_TUNE_CELLS]
     key = batch_key(ctx, grain_ids, int(u.shape[0]), torch.cuda.get_device_name(u.device))
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:

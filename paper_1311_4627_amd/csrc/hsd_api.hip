@@ -30,11 +30,13 @@ struct SurWork {
     float* Xn = nullptr;          size_t Xn_cap = 0;      // normalised inputs
     double* A = nullptr;          size_t A_cap = 0;
     float* emit = nullptr;        size_t emit_cap = 0;
-    float* h0 = nullptr;          size_t h0_cap = 0;
-    float* h1 = nullptr;          size_t h1_cap = 0;
+    unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs [chunk][64]
+    unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][256]
+    unsigned short* h1 = nullptr; size_t h1_cap = 0;
     int* sel = nullptr;           size_t sel_cap = 0;
     const double** cabs = nullptr; size_t cabs_cap = 0;
     float* loga = nullptr;        size_t loga_cap = 0;
+    double* wcT = nullptr;        size_t wcT_cap = 0;     // [L][n_sel] absorption weights
     unsigned* cnt = nullptr;      size_t cnt_cap = 0;     // [n_grains + 1]: per-slot flagged, then total
     int* seg_off = nullptr;       size_t seg_off_cap = 0;
     int* seg_cnt = nullptr;       size_t seg_cnt_cap = 0;
@@ -367,6 +369,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.queue);
     SurWork& w = ctx->sw;
     hipFree(w.bands); hipFree(w.X); hipFree(w.Xn); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);
     hipFree(c.Pt);
@@ -808,6 +811,7 @@ hsd_status hsd_sur_set_params(hsd_sur* p, const float* params_host) {
     HSD_HIP(ctx, hipMemset(p->s.m, 0, sizeof(float) * p->s.n_params));
     HSD_HIP(ctx, hipMemset(p->s.v, 0, sizeof(float) * p->s.n_params));
     p->s.t = 0;
+    p->s.wb_fresh = false;
     return HSD_OK;
 }
 
@@ -893,11 +897,13 @@ hsd_status sur_select(hsd_ctx* ctx, const std::vector<int>& slots, const int32_t
     HSD_HIP(ctx, hipMemcpyAsync(w.sel, slots.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(w.cabs, cabs.data(), sizeof(double*) * n, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(w.loga, loga.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, grow(w.wcT, w.wcT_cap, n * c.L));
+    HSD_HIP(ctx, hsd::sur_wc(c, w.cabs, static_cast<int>(n), w.wcT, s));
     HSD_HIP(ctx, hipStreamSynchronize(s));      // host vectors go out of scope
     return HSD_OK;
 }
 
-constexpr long long kSurChunk = 131072;   // pair rows per inference chunk
+constexpr long long kSurChunk = 262144;   // pair rows per inference chunk
 
 // Surrogate spectra of every (cell, slot) pair of `slots` into j, with diag
 // entries and the energy-balance flags (bit 4) counted in sw.cnt.
@@ -912,18 +918,17 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
     const long long rows = static_cast<long long>(n_cells) * n_sel;
     const size_t ch = static_cast<size_t>(std::min(rows, kSurChunk));
     HSD_HIP(ctx, grow(w.X, w.X_cap, ch * 33));
-    HSD_HIP(ctx, grow(w.Xn, w.Xn_cap, ch * 33));
     HSD_HIP(ctx, grow(w.A, w.A_cap, ch));
     HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch));
+    HSD_HIP(ctx, grow(w.xb, w.xb_cap, ch * 64));
     HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 256));
     HSD_HIP(ctx, grow(w.h1, w.h1_cap, ch * 256));
     for (long long r0 = 0; r0 < rows; r0 += kSurChunk) {
         const long long n = std::min(kSurChunk, rows - r0);
-        HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.cabs, w.loga, r0, n, n_sel, w.X, w.A, s));
-        HSD_HIP(ctx, hsd::sur_norm_rows(w.X, n, 33, sur.xm, sur.xs, w.Xn, s));
+        HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.wcT, w.loga, r0, n, n_sel, w.X, w.A, s));
         HSD_HIP(ctx, hipMemsetAsync(w.emit, 0, sizeof(float) * n, s));
-        HSD_HIP(ctx, hsd::sur_predict_rows(sur, static_cast<int>(n), w.Xn, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
-                                           w.h0, w.h1, s));
+        HSD_HIP(ctx, hsd::sur_infer_rows(sur, static_cast<int>(n), w.X, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
+                                         w.xb, w.h0, w.h1, s));
         if (diag)
             HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, r0, n, n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
     }
@@ -952,7 +957,7 @@ hsd_status hsd_sur_features(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, 
     SurWork& w = ctx->sw;
     HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
     HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
-    HSD_HIP(ctx, hsd::sur_pairs(c, u_dev, w.bands, w.cabs, w.loga, 0, static_cast<long long>(n_cells) * n_grains,
+    HSD_HIP(ctx, hsd::sur_pairs(c, u_dev, w.bands, w.wcT, w.loga, 0, static_cast<long long>(n_cells) * n_grains,
                                 n_grains, X_dev, A_dev, s));
     return HSD_OK;
 }

@@ -197,6 +197,8 @@ struct Sur {
     double* loss = nullptr;
     int splits = 1;            // K splits of the weight-gradient products
     float* split_work = nullptr;
+    unsigned short* wb = nullptr;   // BF16 weights for inference (W1 padded to 64 inputs)
+    bool wb_fresh = false;
     std::vector<float> loss_trace;
 };
 
@@ -204,7 +206,8 @@ hipError_t sur_alloc(Sur& s);
 void sur_free(Sur& s);
 hipError_t sur_grow(Sur& s, int B);
 hipError_t sur_bands(const Ctx& c, const double* u, int n_cells, float* bands, hipStream_t st);
-hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* const* cabs, const float* loga,
+hipError_t sur_wc(const Ctx& c, const double* const* cabs, int n_sel, double* wcT, hipStream_t st);
+hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* wcT, const float* loga,
                      long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st);
 hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st);
 hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd);
@@ -217,6 +220,10 @@ hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
 hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,
                          hipStream_t st);
+hipError_t sur_pack(Sur& s, hipStream_t st);
+hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
+                          const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
+                          unsigned short* h1, hipStream_t st);
 hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, long long row0, int n_sel,
                             int n_slots, const int* sel, float* j, float* emit, float* h0, float* h1,
                             hipStream_t st);

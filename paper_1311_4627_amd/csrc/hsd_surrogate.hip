@@ -57,43 +57,72 @@ __global__ void __launch_bounds__(256) k_bands(const double* u, const double* la
     bands[static_cast<size_t>(cell) * kBands + lane] = static_cast<float>(log10(fmax(s, 1e-300)));
 }
 
-// Pair rows R = cell * n_sel + s (s indexes the selected grains): raw inputs
-// (33 floats) and the absorbed power A = int c u C_abs dlambda (trapezoid,
-// FP64) of rows R = row0 .. row0 + n_rows - 1, written at R - row0.  One wave
-// per pair.
+// Absorption weights of the selected grains, transposed: wcT[j][s] =
+// c C_abs,s(lambda_j) w_j with w_j the trapezoid weight of node j, so the
+// absorbed power of a pair is A = sum_j u_j wcT[j][s].
+__global__ void __launch_bounds__(256) k_wc(const double* const* cabs, const double* lam, int n_sel, int L,
+                                            double* wcT) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_sel * L) return;
+    const int j = i / n_sel, s = i - j * n_sel;
+    const double lo = j > 0 ? lam[j - 1] : lam[0];
+    const double hi = j + 1 < L ? lam[j + 1] : lam[L - 1];
+    wcT[i] = kLight * cabs[s][j] * 0.5 * (hi - lo);
+}
+
+// Pair rows R = cell * n_sel + s (s indexes the selected grains) in
+// [row0, row0 + n_rows): raw inputs (33 floats) and the absorbed power A, both
+// written at R - row0.  One wave per cell, one lane per selected grain: the
+// field value u_j is the same for every lane (a scalar load) and lane s reads
+// its own column of wcT, so the dot products need no reductions.
 struct PairArgs {
     const double* u;
-    const double* lam;
     const float* bands;        // [n_cells][32]
-    const double* const* cabs; // [n_sel] device pointers to C_abs tables
+    const double* wcT;         // [L][n_sel]
     const float* loga;         // [n_sel] log10 radius (cm)
     long long row0, n_rows;
+    long long cell0, n_cells;  // cells touched by the rows
     int n_sel, L;
     float* X;                  // [n_rows][33] or null
     double* A;                 // [n_rows] or null
 };
 
 __global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
-    const int lane = threadIdx.x & 63;
-    const long long r = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (r >= a.n_rows) return;
-    const long long rg = a.row0 + r;
-    const long long cell = rg / a.n_sel;
-    const int s = static_cast<int>(rg - cell * a.n_sel);
-    if (a.X) {
-        float* xr = a.X + r * 33;
-        if (lane < kBands) xr[lane] = a.bands[cell * kBands + lane];
-        if (lane == kBands) xr[kBands] = a.loga[s];
-    }
-    if (a.A) {
+    __shared__ double us[4][1024];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long cell = a.cell0 + static_cast<long long>(blockIdx.x) * 4 + wave;
+    const bool live = cell < a.cell0 + a.n_cells;
+    if (live) {
         const double* uc = a.u + cell * a.L;
-        const double* cb = a.cabs[s];
-        double acc = 0.0;
-        for (int j = lane; j + 1 < a.L; j += 64)
-            acc += 0.5 * (uc[j] * cb[j] + uc[j + 1] * cb[j + 1]) * (a.lam[j + 1] - a.lam[j]);
-#pragma unroll
-        for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
-        if (lane == 0) a.A[r] = kLight * acc;
+        for (int j = lane; j < a.L; j += 64) us[wave][j] = uc[j];
+    }
+    __syncthreads();
+    if (!live) return;
+    for (int s0 = 0; s0 < a.n_sel; s0 += 64) {
+        const int s = s0 + lane;
+        const long long rr = cell * a.n_sel + s - a.row0;      // output row
+        const bool mine = s < a.n_sel && rr >= 0 && rr < a.n_rows;
+        if (a.A) {
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            const double* wc = a.wcT + (s < a.n_sel ? s : 0);
+            const long long st = a.n_sel;
+            int j = 0;
+            for (; j + 4 <= a.L; j += 4) {
+                p0 = fma(us[wave][j], wc[j * st], p0);
+                p1 = fma(us[wave][j + 1], wc[(j + 1) * st], p1);
+                p2 = fma(us[wave][j + 2], wc[(j + 2) * st], p2);
+                p3 = fma(us[wave][j + 3], wc[(j + 3) * st], p3);
+            }
+            for (; j < a.L; ++j) p0 = fma(us[wave][j], wc[j * st], p0);
+            if (mine) a.A[rr] = (p0 + p1) + (p2 + p3);
+        }
+        if (a.X && mine) {
+            float* xr = a.X + rr * 33;
+            const float* bc = a.bands + cell * kBands;
+#pragma unroll 8
+            for (int k = 0; k < kBands; ++k) xr[k] = bc[k];
+            xr[kBands] = a.loga[s];
+        }
     }
 }
 
@@ -451,6 +480,198 @@ __global__ void __launch_bounds__(256) k_fb_scatter(const float* diag, long long
     pairs[k] = p;
 }
 
+
+// ---- inference: weight-stationary dense layers on BF16 activations --------------
+// A layer out[r][n] = epi(sum_k in[r][k] W[n][k] + b[n]) over many rows r.  A
+// block keeps a slice of 128 output columns of W (BF16, all K) in LDS and runs
+// row tiles of 64 through it, so the weights are read from memory once per
+// block instead of once per row tile.  Each wave owns 16 rows; lane l holds
+// row l % 16 and the K/4 contiguous inputs starting at (K/4)(l / 16), which is
+// how it feeds v_mfma_f32_16x16x16_bf16: in step s its 4 inputs are
+// k = (K/4) q + 4 s + 0..3 (q = l / 16), and the weight fragment it reads
+// from LDS uses the same k, so each product still sums over every k once.
+
+// Weights for inference, BF16: W1 padded to K = 64, then W2, W3, W4.
+__global__ void __launch_bounds__(256) k_pack_bf16(const float* w, long long oW1, long long oW2, long long oW3,
+                                                   long long oW4, int L, unsigned short* wb) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    const long long n1 = 256 * 64, n2 = 256 * 256, n4 = static_cast<long long>(L) * 256;
+    if (i < n1) {
+        const int r = static_cast<int>(i / 64), k = static_cast<int>(i % 64);
+        wb[i] = k < 33 ? to_bf16(w[oW1 + r * 33 + k]) : 0;
+    } else if (i < n1 + n2) {
+        wb[i] = to_bf16(w[oW2 + (i - n1)]);
+    } else if (i < n1 + 2 * n2) {
+        wb[i] = to_bf16(w[oW3 + (i - n1 - n2)]);
+    } else if (i < n1 + 2 * n2 + n4) {
+        wb[i] = to_bf16(w[oW4 + (i - n1 - 2 * n2)]);
+    }
+}
+
+// Normalised BF16 inputs, zero padded to 64: xb[r][k] = (X[r][k] - m_k) / s_k.
+__global__ void __launch_bounds__(256) k_norm_bf16(const float* X, long long n, const float* m, const float* sd,
+                                                   unsigned short* xb) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n * 64) return;
+    const long long r = i >> 6;
+    const int k = static_cast<int>(i & 63);
+    xb[i] = k < 33 ? to_bf16((X[r * 33 + k] - m[k]) / sd[k]) : 0;
+}
+
+struct DenseArgs {
+    const unsigned short* in;   // [M][K] bf16
+    const unsigned short* W;    // [N][K] bf16
+    const float* bias;          // [N]
+    int M, N;
+    unsigned short* out;        // hidden: [M][N] bf16
+    // spectrum epilogue
+    float* j; int L;
+    const float* ym; const float* ys;
+    const double* Arow; const float* wq; float* emit;
+    long long row0; int n_sel, n_slots; const int* sel;
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// 128 output columns per block (LDS slice), 128 rows per tile: each wave owns
+// 32 rows as two groups of 16, so every weight fragment read from LDS feeds
+// two matrix-core products.  v_mfma_f32_16x16x32_bf16 takes 8 inputs per lane;
+// step s uses k = (K/4) q + 8 s + 0..7 for lane l (q = l / 16) in both operands.
+template <int K, bool SPECTRUM>
+__global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
+    // rows per wave: 2 groups of 16 (hidden layers), 1 group (output layer,
+    // whose epilogue needs the registers)
+    constexpr int G = SPECTRUM ? 1 : 2;
+    constexpr int NB = 128, TM = 64 * G, LDK = K + 8, S = K / 32;
+    __shared__ __align__(16) unsigned short Ws[NB][LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n0 = blockIdx.x * NB;
+    // LDS row 16 c + m holds output column 8 m + c of the slice, so that the
+    // accumulators of lane l (MFMA column l % 16 of subtiles c = 0..7) are the
+    // 8 consecutive output columns 8 (l % 16) .. + 7: one vector store per row
+    for (int e = tid; e < NB * (K / 8); e += 256) {
+        const int rr = e / (K / 8), k8 = (e % (K / 8)) * 8;
+        const int col = 8 * (rr & 15) + (rr >> 4);
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (n0 + col < a.N) v = *reinterpret_cast<const u32x4*>(a.W + static_cast<long long>(n0 + col) * K + k8);
+        *reinterpret_cast<u32x4*>(&Ws[rr][k8]) = v;
+    }
+    __syncthreads();
+    const int q = lane >> 4, rl = lane & 15;
+    const int nc = n0 + 8 * rl;                    // first of this lane's 8 output columns
+    const int n_tiles = (a.M + TM - 1) / TM;
+    auto load = [&](int t, auto& f) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const long long row = static_cast<long long>(t) * TM + wave * 16 * G + g * 16 + rl;
+            if (t < n_tiles && row < a.M) {
+                const u32x4* src = reinterpret_cast<const u32x4*>(a.in + row * K + (K / 4) * q);
+#pragma unroll
+                for (int v = 0; v < S; ++v) f[g][v] = src[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < S; ++v) f[g][v] = u32x4{0u, 0u, 0u, 0u};
+            }
+        }
+    };
+    // epilogue constants of this lane's 8 columns (output layer):
+    // j = A 2^(acc e_c + f_c), e_c = s_c log2(10), f_c = (b_c s_c + m_c) log2(10)
+    float e8[SPECTRUM ? 8 : 1], f8[SPECTRUM ? 8 : 1], w8[SPECTRUM ? 8 : 1];
+    if constexpr (SPECTRUM) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int n = nc + c < a.N ? nc + c : a.N - 1;
+            e8[c] = a.ys[n] * 3.32192809488736235f;
+            f8[c] = (a.bias[n] * a.ys[n] + a.ym[n]) * 3.32192809488736235f;
+            w8[c] = nc + c < a.N ? a.wq[n] : 0.f;
+        }
+    }
+    // the next tile's inputs are loaded while this tile computes
+    u32x4 cur[G][S], nxt[G][S];
+    int t = blockIdx.y;
+    load(t, cur);
+    for (; t < n_tiles; t += gridDim.y) {
+        load(t + gridDim.y, nxt);
+        f32x4 acc[G][8];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[g][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const bf16x8 b = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4*>(&Ws[16 * c + rl][(K / 4) * q + 8 * st]));
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    acc[g][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[g][st]), b,
+                                                                        acc[g][c], 0, 0, 0);
+            }
+            // keep each step's weight fragments within the step (bounds register use)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // accumulator register i of lane l, subtile c: row 4 q + i of its group
+        // of 16, output column nc + c
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long r = static_cast<long long>(t) * TM + wave * 16 * G + g * 16 + 4 * q + i;
+                if constexpr (!SPECTRUM) {
+                    if (r < a.M) {
+                        if (nc + 8 <= a.N) {
+                            unsigned pk[4];
+#pragma unroll
+                            for (int c = 0; c < 8; c += 2) {
+                                const unsigned lo = to_bf16(gelu(acc[g][c][i] + a.bias[nc + c]));
+                                const unsigned hi = to_bf16(gelu(acc[g][c + 1][i] + a.bias[nc + c + 1]));
+                                pk[c / 2] = lo | (hi << 16);
+                            }
+                            *reinterpret_cast<u32x4*>(a.out + r * a.N + nc) = u32x4{pk[0], pk[1], pk[2], pk[3]};
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 8; ++c)
+                                if (nc + c < a.N) a.out[r * a.N + nc + c] = to_bf16(gelu(acc[g][c][i] + a.bias[nc + c]));
+                        }
+                    }
+                } else {
+                    float part = 0.f;
+                    if (r < a.M) {
+                        const long long gr = a.row0 + r;
+                        const long long cell = gr / a.n_sel;
+                        const int slot = a.sel[static_cast<int>(gr - cell * a.n_sel)];
+                        float* jrow = a.j + (cell * a.n_slots + slot) * a.L;
+                        const float Ar = static_cast<float>(a.Arow[r]);
+                        float jv[8];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            jv[c] = Ar * exp2f(fmaf(acc[g][c][i], e8[c], f8[c]));
+                            part += jv[c] * w8[c];
+                        }
+                        if (nc + 8 <= a.N) {
+                            *reinterpret_cast<float4*>(jrow + nc) = make_float4(jv[0], jv[1], jv[2], jv[3]);
+                            *reinterpret_cast<float4*>(jrow + nc + 4) = make_float4(jv[4], jv[5], jv[6], jv[7]);
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 8; ++c)
+                                if (nc + c < a.N) jrow[nc + c] = jv[c];
+                        }
+                    }
+#pragma unroll
+                    for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 16);
+                    if (rl == 0 && r < a.M) atomicAdd(a.emit + r, part);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < S; ++v) cur[g][v] = nxt[g][v];
+    }
+}
+
 }  // namespace
 
 // ---- host side ------------------------------------------------------------------------
@@ -503,6 +724,7 @@ void sur_free(Sur& s) {
     (void)hipFree(s.idx);
     (void)hipFree(s.loss);
     (void)hipFree(s.split_work);
+    (void)hipFree(s.wb);
 }
 
 hipError_t sur_grow(Sur& s, int B) {
@@ -550,11 +772,20 @@ hipError_t sur_bands(const Ctx& c, const double* u, int n_cells, float* bands, h
     return hipGetLastError();
 }
 
-hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* const* cabs, const float* loga,
+hipError_t sur_wc(const Ctx& c, const double* const* cabs, int n_sel, double* wcT, hipStream_t st) {
+    const int n = n_sel * c.L;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wc, dim3((n + 255) / 256), dim3(256), 0, st, cabs, c.lam, n_sel, c.L, wcT);
+    return hipGetLastError();
+}
+
+hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* wcT, const float* loga,
                      long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
-    PairArgs p{u, c.lam, bands, cabs, loga, row0, n_rows, n_sel, c.L, X, A};
-    hipLaunchKernelGGL(k_pairs, dim3(static_cast<unsigned>((n_rows + 3) / 4)), dim3(256), 0, st, p);
+    const long long cell0 = row0 / n_sel;
+    const long long cell1 = (row0 + n_rows - 1) / n_sel;
+    PairArgs p{u, bands, wcT, loga, row0, n_rows, cell0, cell1 - cell0 + 1, n_sel, c.L, X, A};
+    hipLaunchKernelGGL(k_pairs, dim3(static_cast<unsigned>((p.n_cells + 3) / 4)), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
@@ -694,6 +925,7 @@ hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st) {
 
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
     ++s.t;
+    s.wb_fresh = false;
     const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
     const double c1 = 1.0 - std::pow(b1, static_cast<double>(s.t));
     const double c2 = 1.0 - std::pow(b2, static_cast<double>(s.t));
@@ -736,6 +968,70 @@ hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, lon
     g.n_slots = n_slots;
     g.sel = sel;
     return gemm<EPI_SPECTRUM>(g, st);
+}
+
+// Weights in BF16 for inference (packed once per parameter change).
+hipError_t sur_pack(Sur& s, hipStream_t st) {
+    if (s.wb_fresh) return hipSuccess;
+    const long long n = 256LL * 64 + 2LL * 256 * 256 + static_cast<long long>(s.L) * 256;
+    if (!s.wb) {
+        const hipError_t e = hipMalloc(&s.wb, sizeof(unsigned short) * n);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_pack_bf16, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, s.w, s.off_W[0],
+                       s.off_W[1], s.off_W[2], s.off_W[3], s.L, s.wb);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) s.wb_fresh = true;
+    return e;
+}
+
+namespace {
+
+template <int K, bool SPEC>
+hipError_t dense(const DenseArgs& a, hipStream_t st) {
+    const int nsplit = (a.N + 127) / 128;
+    const int n_tiles = (a.M + (SPEC ? 63 : 127)) / (SPEC ? 64 : 128);
+    // two blocks per CU fit (LDS): spread them over the column slices
+    const int per_split = std::max(1, std::min(n_tiles, 512 / nsplit));
+    hipLaunchKernelGGL((k_dense<K, SPEC>), dim3(nsplit, per_split), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Inference of rows [row0, row0 + M) of a selection from raw inputs X [M][33]:
+// spectra scattered to j (pair rows) and 4 pi int j dlambda added to emit.
+hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
+                          const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
+                          unsigned short* h1, hipStream_t st) {
+    if (M <= 0) return hipSuccess;
+    hipError_t e = sur_pack(s, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_norm_bf16, dim3(static_cast<unsigned>((static_cast<long long>(M) * 64 + 255) / 256)),
+                       dim3(256), 0, st, X, static_cast<long long>(M), s.xm, s.xs, xb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned short* W1 = s.wb;
+    const unsigned short* W2 = W1 + 256 * 64;
+    const unsigned short* W3 = W2 + 256 * 256;
+    const unsigned short* W4 = W3 + 256 * 256;
+    DenseArgs d{};
+    d.M = M;
+    d.N = 256;
+    d.in = xb; d.W = W1; d.bias = s.w + s.off_b[0]; d.out = h0;
+    e = dense<64, false>(d, st);
+    if (e != hipSuccess) return e;
+    d.in = h0; d.W = W2; d.bias = s.w + s.off_b[1]; d.out = h1;
+    e = dense<256, false>(d, st);
+    if (e != hipSuccess) return e;
+    d.in = h1; d.W = W3; d.bias = s.w + s.off_b[2]; d.out = h0;
+    e = dense<256, false>(d, st);
+    if (e != hipSuccess) return e;
+    DenseArgs o{};
+    o.in = h0; o.W = W4; o.bias = s.w + s.off_b[3]; o.M = M; o.N = s.L;
+    o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit;
+    o.row0 = row0; o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
+    return dense<256, true>(o, st);
 }
 
 hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,

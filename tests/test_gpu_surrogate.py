@@ -190,3 +190,35 @@ def test_fallback_is_the_plain_solve(hsd, small):
     assert nfb0 == n_cells * G
     assert torch.equal(j, je) and torch.equal(diag, de)
     sur.close()
+
+
+def test_inference_matches_bf16_reference(hsd, small):
+    # the inference kernels (BF16 activations between weight-stationary
+    # layers, spectrum epilogue) against the reference forward pass with
+    # BF16-rounded operands, on the same raw inputs and statistics
+    d = small
+    w, G = d["w"], len(d["ids"])
+    sur = hsd.Surrogate(d["ctx"])
+    flat = ssur.init_params(w.n_lambda, seed=17)
+    sur.hsd_sur_set_params(flat)
+    sur.hsd_sur_fit_norm(d["X"], d["Y"])
+    sur.hsd_sur_train(d["X"], d["Y"], steps=200, batch=512, lr=2e-3)     # weights away from their init
+    flat = sur.hsd_sur_get_params().astype(np.float64)
+    xm, xs, ym, ys = sur.hsd_sur_get_norm()
+    n_cells = 24
+    jp = torch.empty((n_cells, G, w.n_lambda), dtype=torch.float32, device="cuda")
+    dp = torch.empty((n_cells, G, 4), dtype=torch.float32, device="cuda")
+    sur.hsd_sur_predict(d["ud"][:n_cells].contiguous(), d["ids"], jp, dp)
+    torch.cuda.synchronize()
+    X = d["X"].cpu().numpy()[: n_cells * G].astype(np.float64)
+    A = d["A"].cpu().numpy()[: n_cells * G]
+    yhat, _ = mlp.forward(flat, ssur.widths(w.n_lambda), (X - xm) / xs, bf16=True)
+    jref = A[:, None] * 10.0 ** (yhat * ys + ym)
+    jg = jp.cpu().numpy().reshape(-1, w.n_lambda).astype(np.float64)
+    rel = np.abs(jg / jref - 1)
+    print(f"inference vs reference: median {np.median(rel):.2e} max {rel.max():.2e}", flush=True)
+    assert np.median(rel) < 2e-4 and rel.max() < 2e-2
+    # emitted power of each pair: 4 pi trapezoid of its spectrum
+    em = 4 * math.pi * np.trapezoid(jg, w.lam_cm, axis=1)
+    assert np.allclose(dp.cpu().numpy().reshape(-1, 4)[:, 1], em, rtol=1e-5)
+    sur.close()
