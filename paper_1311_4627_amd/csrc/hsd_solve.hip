@@ -167,6 +167,14 @@ __device__ __forceinline__ double clean_field(double u, bool& bad) {
     return u;
 }
 
+// Integer clamp in one instruction (the compiler keeps max + min when the
+// bounds are not constants).
+__device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 template <int R>
 struct Rec {
     double G[R];       // inflow G(k) of the lane's rows, then X_k once row k is passed
@@ -185,6 +193,7 @@ struct StepEnv {
     const ColPar* colpar;
     const DPar* dpar;  // LDS
     const float* tab;  // LDS, this pair's log2 table
+    int tlo, thi;      // LDS byte addresses of table entries -1 and L
     const float* cum;  // LDS, this pair's Cum / total (LDS-table variant)
     const double* Ap;  // given-rates hook: this pair's rate matrix
     const double* cp;  // given-rates hook: this pair's cooling rates
@@ -194,7 +203,7 @@ struct StepEnv {
 struct StepState {
     int pf, l, kb, ke;     // column position pf = f + s0, lane of the diagonal, grid-resident rows (positions)
     double Xg;         // X_f times the column's rate factor
-    int ia;
+    int cb;            // LDS byte address of table entry ia1 of the column
     float fa;
 };
 
@@ -226,14 +235,21 @@ __device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const S
                 const int d = (R0 + s) * P + q - ss.pf;
                 dp[s] = e.dpar[R0 + s == RO ? max(d, 0) : d];
             }
+            // the grid interval of transition_index (hsd_index.h) as an LDS byte
+            // address: cb + 4 nib + 4 fl = address of entry jlo, with the column's
+            // and the distance's parts pre-scaled by 4 (cb, dpar.nib), clamped to
+            // entries -1 .. L
             float t0[NS], t1[NS], w[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                int jlo;
-                transition_index(ss.ia, ss.fa, dp[s].nib, dp[s].fb, jlo, w[s]);
-                jlo = min(max(jlo, -1), e.Lm1 + 1);
-                t0[s] = e.tab[jlo];
-                t1[s] = e.tab[jlo + 1];
+                const float fd = ss.fa - dp[s].fb;
+                const int fl = static_cast<int>(fd);
+                w[s] = __builtin_amdgcn_fractf(fd);
+                const int off = med3_i32(ss.cb + dp[s].nib + (fl << 2), e.tlo, e.thi);
+                typedef const __attribute__((address_space(3))) float* LdsF;
+                const LdsF p = (LdsF)static_cast<size_t>(static_cast<unsigned>(off));
+                t0[s] = p[0];
+                t1[s] = p[1];
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s)
@@ -309,7 +325,7 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
             st.cf *= e.rbin;
         }
         double part = 0.0;
-        StepState ss{pf, l, kb, ke, Xg, cc.ia, cc.fa};
+        StepState ss{pf, l, kb, ke, Xg, 4 * cc.ia + e.tlo + 4, cc.fa};
         all_groups<P, R, KG, GIVEN, RO>(st, e, ss, part, std::make_integer_sequence<int, (R - RO + KG - 1) / KG>{});
         if constexpr (!GIVEN) {
             // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1)
@@ -453,7 +469,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             float* base = reinterpret_cast<float*>(smem + sizeof(DPar) * R * P) + (wave * PPW + seg) * a.tabstride;
             tab = base + 1;
             cum = LDSCUM ? base + (L + 3) : tab;   // else pass 2 overwrites Cum with the log2 table
-            for (int d = threadIdx.x; d < nb; d += 64 * WAVES) dpar_s[d] = gv.dpar[d];
+            for (int d = threadIdx.x; d < nb; d += 64 * WAVES) {
+                DPar v = gv.dpar[d];
+                v.nib *= 4;              // table entries are 4 bytes
+                dpar_s[d] = v;
+            }
 
             // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
             // (trapezoid), FP64, chunked over the segment's lanes; kept normalised by
@@ -550,6 +570,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         env.colpar = gv.colpar;
         env.dpar = dpar_s;
         env.tab = tab;
+        if constexpr (!GIVEN) {
+            typedef __attribute__((address_space(3))) float* LdsF;
+            env.tlo = static_cast<int>(reinterpret_cast<size_t>((LdsF)tab)) - 4;
+            env.thi = env.tlo + 4 * (a.L + 1);
+        }
         env.cum = cum;
         if constexpr (GIVEN) {
             env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
