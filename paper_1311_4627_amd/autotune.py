@@ -36,6 +36,15 @@ def _load(path: str) -> Dict[str, dict]:
 MAX_TUNE_CELLS = 16384
 
 
+def device_id(dev) -> str:
+    """Architecture and compute-unit count of the device (the marketing name
+    is not always reported, e.g. under a profiler)."""
+    import torch
+    p = torch.cuda.get_device_properties(dev)
+    arch = getattr(p, "gcnArchName", "") or "unknown"
+    return f"{arch.split(':')[0]}/{p.multi_processor_count}cu"
+
+
 def tune(ctx: "hsd.Context", u, grain_ids: Sequence[int], cache_path: Optional[str] = None,
          runs: int = 4, force: bool = False) -> dict:
     """Apply the cached configuration of this batch's key, or time and cache
@@ -46,7 +55,7 @@ def tune(ctx: "hsd.Context", u, grain_ids: Sequence[int], cache_path: Optional[s
     import torch
     if int(u.shape[0]) > MAX_TUNE_CELLS:
         u = u[:MAX_TUNE_CELLS]
-    key = batch_key(ctx, grain_ids, int(u.shape[0]), torch.cuda.get_device_name(u.device))
+    key = batch_key(ctx, grain_ids, int(u.shape[0]), device_id(u.device))
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         entry = cache[key]
