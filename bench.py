@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=48)
     ap.add_argument("--eager", action="store_true", help="time hsd_solve calls instead of plan replays")
     ap.add_argument("--retune", action="store_true", help="time the launch configurations again")
-    ap.add_argument("--train-steps", type=int, default=20000, help="surrogate training steps per composition")
+    ap.add_argument("--train-steps", type=int, default=60000, help="surrogate training steps per composition")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM byte counters)")
     args = ap.parse_args()

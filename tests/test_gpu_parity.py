@@ -268,3 +268,35 @@ def test_tiny_grain_matches_dense_master_equation(hsd):
         Pdense = oracle.dense_steady_state(om.heating_matrix(u[c], s), s.cool)
         m = Pdense >= 1e-6 * Pdense.max()
         assert np.max(np.abs(P[c][m] / Pdense[m] - 1)) < J_TOL
+
+
+def test_empty_batches_are_no_ops(hsd, c1):
+    w, ctx, gid, u = c1
+    u0 = torch.empty((0, w.n_lambda), dtype=torch.float64, device="cuda")
+    j0 = torch.empty((0, 1, w.n_lambda), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(u0, [gid], j0, None)
+    ud = torch.tensor(u[:2], device="cuda")
+    jz = torch.empty((2, 0, w.n_lambda), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(ud, [], jz, None)
+    ctx.hsd_sync()
+
+
+def test_maximum_sizes_match_oracle(hsd):
+    # the largest grid and grain the library takes: 1024 wavelengths, 1024 bins
+    lam = synth.wavelength_grid_cm(1024)
+    g = synth.make_grain("carbonaceous", 3.5e-8, lam, n_bins=1024)
+    ctx = hsd.Context(lam)
+    gid = ctx.add_grain(g)
+    rec = synth.FieldRecipe(seed=77, U_range=(0.1, 1e5), jitter=0.3, tau_V_range=None)
+    u = make_fields(lam, rec, 5)
+    ud = torch.tensor(u, device="cuda")
+    j = torch.empty((5, 1, 1024), dtype=torch.float32, device="cuda")
+    diag = torch.empty((5, 1, 4), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(ud, [gid], j, diag)
+    ctx.hsd_sync()
+    jj = j.cpu().numpy()[:, 0].astype(np.float64)
+    for c in (0, 2, 4):
+        _, jr = oracle.solve_pair(u[c], g, lam)
+        e = j_rel_err(jj[c], jr)
+        print(f"max sizes cell {c}: j rel err {e:.2e}", flush=True)
+        assert e < J_TOL
