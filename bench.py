@@ -51,8 +51,8 @@ METRIC = "emissivity solves/s (cell×grain) at 1e-4 rel err; surrogate vs plain 
 EXP2_PEAK = 157.3e12 / 2 / 4                 # v_exp_f32 per second: a quarter of the FP32 FMA rate
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_c2_hbm_traffic.md")
 TUNE_CACHE = os.path.join(ROOT, "paper_1311_4627_amd", "tuned.json")
-SOLVER_SOURCES = ["paper_1311_4627_amd/csrc/hsd_solve.hip", "paper_1311_4627_amd/csrc/hsd_index.h",
-                  "paper_1311_4627_amd/csrc/hsd_internal.h"]
+# the solver kernel's own sources (the traffic summary is valid while they are unchanged)
+SOLVER_SOURCES = ["paper_1311_4627_amd/csrc/hsd_solve.hip", "paper_1311_4627_amd/csrc/hsd_index.h"]
 
 
 def solver_hash() -> str:
@@ -374,6 +374,23 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     phase /= args.steps
 
+    # the size-distribution convolution (a post-processing pass over j, not
+    # part of the step): HBM-bound, reads j once and writes one spectrum per cell
+    sizedist = None
+    if args.workload == "c2_batched":
+        radii = np.array([g.radius_cm for g in w.grains])
+        out = torch.empty((w.n_cells, w.n_lambda), dtype=torch.float64, device="cuda:0")
+        ctx.hsd_size_convolve(j, synth.size_weights(radii), out, stream=stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        ctx.hsd_size_convolve(j, synth.size_weights(radii), out, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) * 1e-3
+        nbytes = j.numel() * 4 + out.numel() * 8
+        sizedist = {"ms": t * 1e3, "GB_per_s": nbytes / t / 1e9, "frac_of_hbm_peak": nbytes / t / 8e12}
+        del out
+
     rates_per_step = 0
     for gi, g in zip(ids, w.grains):
         rates_per_step += count_rates(ctx.hsd_grain_tables(gi), w.lam_cm, g) * w.n_cells
@@ -403,6 +420,7 @@ def main():
         "phases_ms": {"solve": phase[0], "contract": phase[1], "diag": phase[2]},
         "setup_s": setup_s,
         "tune_s": tune_s,
+        "size_convolution": sizedist,
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu

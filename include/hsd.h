@@ -158,6 +158,20 @@ hsd_status hsd_sync(hsd_ctx* ctx);
 hsd_status hsd_set_timing(hsd_ctx* ctx, int32_t enable);
 hsd_status hsd_phase_ms(hsd_ctx* ctx, double* ms_host);
 
+/* The emissivity of a whole size distribution (Sec. 2.3, eq:convolution on
+ * the discrete size grid): out[c][l] = sum_g w_g j[c][g][l], multiplied by
+ * lambda_l when lambda_weighted != 0 (lambda j_lambda = nu j_nu, the form the
+ * paper's library returns).  The weights w_g are the caller's quadrature of
+ * the size distribution, per H atom for the paper's units (then out is
+ * erg s^-1 sr^-1 per H; divide by 1 eV in erg for the paper's eV).
+ *   j_dev        [n_cells][n_grains][n_lambda] float (as from hsd_solve)
+ *   weights_host [n_grains] double, finite
+ *   out_dev      [n_cells][n_lambda] double
+ * FP64 sums.  Waits for `stream` once (to reuse the weight buffer), then
+ * enqueues on it. */
+hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, const float* j_dev,
+                             const double* weights_host, int32_t lambda_weighted, double* out_dev, void* stream);
+
 /* ---- Launch configuration (read and set by the autotuner) ----
  * The solver groups grains into four bin-count classes, each served by its
  * own kernel shape: class 0 holds 513..1024 bins, class 1 257..512, class 2

@@ -57,5 +57,6 @@ from .model import (  # noqa: F401
     diagnostics,
     solve_pair,
     equilibrium_temperature,
+    size_convolution,
 )
 from .dense import dense_steady_state  # noqa: F401

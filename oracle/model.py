@@ -319,3 +319,13 @@ def equilibrium_temperature(u: np.ndarray, setup: GrainSetup) -> float:
     absorbed = float(np.trapezoid(C * u * setup.cabs, lam))
     g = lambda lt: 4.0 * math.pi * float(np.trapezoid(setup.cabs * planck_lambda(lam, math.exp(lt)), lam)) - absorbed
     return math.exp(optimize.brentq(g, math.log(1.0), math.log(1.0e5), xtol=1e-14, rtol=1e-14))
+
+
+def size_convolution(j: np.ndarray, weights: np.ndarray, lam: np.ndarray, lambda_weighted: bool = True) -> np.ndarray:
+    """Sec. 2.3, eq:convolution on a discrete size grid: the emissivity of the
+    whole size distribution, sum_g w_g j_lambda(a_g), with w_g the quadrature
+    weights of the distribution (per H atom); times lambda when
+    lambda_weighted, giving lambda j_lambda = nu j_nu, the form the paper's
+    library returns (its interface section).  j: [..., G, L]."""
+    s = np.einsum("...gl,g->...l", np.asarray(j, dtype=np.float64), np.asarray(weights, dtype=np.float64))
+    return s * lam if lambda_weighted else s

@@ -367,6 +367,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.lam);
     hipFree(c.errword);
     hipFree(c.queue);
+    hipFree(c.sizew);
     SurWork& w = ctx->sw;
     hipFree(w.bands); hipFree(w.X); hipFree(w.Xn); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
@@ -721,6 +722,25 @@ hsd_status hsd_plan_phase_ms(hsd_plan* p, double* ms) {
         HSD_HIP(ctx, hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
         ms[i] = t;
     }
+    return HSD_OK;
+}
+
+hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, const float* j_dev,
+                             const double* weights_host, int32_t lambda_weighted, double* out_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0) return HSD_OK;
+    if (!j_dev || !out_dev || (n_grains > 0 && !weights_host)) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!std::isfinite(weights_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "non-finite weight");
+    Ctx& c = ctx->c;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    HSD_HIP(ctx, hipStreamSynchronize(s));          // the weight buffer may still be read by earlier work
+    HSD_HIP(ctx, grow(c.sizew, c.sizew_cap, static_cast<size_t>(std::max(n_grains, 1))));
+    if (n_grains > 0)
+        HSD_HIP(ctx, hipMemcpy(c.sizew, weights_host, sizeof(double) * n_grains, hipMemcpyHostToDevice));
+    HSD_HIP(ctx, hsd::launch_sizedist(j_dev, c.sizew, c.lam, n_cells, n_grains, c.L, lambda_weighted ? 1 : 0, out_dev, s));
     return HSD_OK;
 }
 

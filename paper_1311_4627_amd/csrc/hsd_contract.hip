@@ -112,6 +112,21 @@ __global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
     if (lane == 0 && valid) a.diag[pair * 4 + 1] = static_cast<float>(4.0 * kPi * em);
 }
 
+// Size-distribution convolution (Sec. 2.3, eq:convolution on the size grid):
+// out[c][l] = (lambda_l if lw) * sum_g w_g j[c][g][l], FP64 sums; one thread
+// per (cell, wavelength), consecutive threads on consecutive wavelengths.
+__global__ void __launch_bounds__(256) k_sizedist(const float* j, const double* w, const double* lam, int n_cells,
+                                                  int G, int L, int lw, double* out) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= static_cast<long long>(n_cells) * L) return;
+    const long long c = i / L;
+    const int l = static_cast<int>(i - c * L);
+    const float* jc = j + c * G * L + l;
+    double acc = 0.0;
+    for (int g = 0; g < G; ++g) acc = fma(w[g], static_cast<double>(jc[static_cast<long long>(g) * L]), acc);
+    out[i] = lw ? acc * lam[l] : acc;
+}
+
 }  // namespace
 
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
@@ -125,6 +140,15 @@ hipError_t launch_diag(const DiagLaunch& a, hipStream_t s) {
     const size_t n_pairs = a.pairs ? static_cast<size_t>(a.n_list) : static_cast<size_t>(a.n_cells) * a.n_gslots;
     if (n_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_diag, dim3(static_cast<unsigned>((n_pairs + 15) / 16)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int lw,
+                           double* out, hipStream_t s) {
+    const long long n = static_cast<long long>(n_cells) * L;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sizedist, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, j, w, lam, n_cells, G,
+                       L, lw, out);
     return hipGetLastError();
 }
 

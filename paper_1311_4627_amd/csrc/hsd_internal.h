@@ -103,6 +103,7 @@ struct Ctx {
     long long* offs = nullptr;    size_t offs_cap = 0;
     int2* items = nullptr;        size_t items_cap = 0;
     unsigned* queue = nullptr;    // [kClasses] item counters of persistent launches
+    double* sizew = nullptr;      size_t sizew_cap = 0;   // size-distribution weights
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded
@@ -171,6 +172,8 @@ struct DiagLaunch {
     long long n_list = 0;
 };
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
+hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int lw,
+                           double* out, hipStream_t s);
 
 // ---- learned surrogate (hsd_surrogate.hip) ----
 struct Sur {

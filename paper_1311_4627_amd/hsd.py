@@ -32,7 +32,7 @@ SYMBOLS = (
     "hsd_plan_destroy", "hsd_autotune",
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
-    "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate",
+    "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
 )
 
 N_CLASSES = 4
@@ -133,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
                  "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.hsd_size_convolve.argtypes = [vp, i32, i32, vp, dp, i32, vp, vp]
+    lib.hsd_size_convolve.restype = ctypes.c_int
     return lib
 
 
@@ -367,6 +369,19 @@ class Context:
         if st != HSD_OK:
             self._raise(st, "hsd_solve_surrogate")
         return int(nfb.value)
+
+    def hsd_size_convolve(self, j, weights, out, lambda_weighted: bool = True, stream=None):
+        import torch
+        n_cells, G = int(j.shape[0]), int(j.shape[1])
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.shape != (G,):
+            raise ValueError("one weight per grain")
+        _check_dev(j, torch.float32, (n_cells, G, self.L), "j")
+        _check_dev(out, torch.float64, (n_cells, self.L), "out")
+        st = self._lib.hsd_size_convolve(self._h, n_cells, G, j.data_ptr(), _dptr(w), 1 if lambda_weighted else 0,
+                                         out.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_size_convolve")
 
     def hsd_sync(self):
         st = self._lib.hsd_sync(self._h)

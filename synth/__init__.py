@@ -24,5 +24,7 @@ from .configs import (  # noqa: F401
     bins_for_radius,
     workload,
     WORKLOAD_NAMES,
+    radii_cm,
+    size_weights,
 )
 from .fields import make_fields, FieldRecipe  # noqa: F401

@@ -216,3 +216,20 @@ def workload(name: str, n_cells: int | None = None) -> Workload:
         rec = FieldRecipe(seed=4627000 + 5, U_range=(0.1, 1.0e5), jitter=0.3, tau_V_range=None)
         return Workload(name, 5, lam, gs, n_cells or 262144, rec)
     raise KeyError(name)
+
+
+def size_weights(radii_cm: np.ndarray, q: float = 3.5, per_H: float = 1.0e-25) -> np.ndarray:
+    """Quadrature weights w_g of a power-law size distribution
+    dn/da = K a^-q per H atom (the workloads' stand-in for a measured size
+    distribution): the midpoint rule in ln a on the log-spaced radii,
+    w_g = K a_g^(1-q) dln a (half weights at both ends), K = per_H x 1 cm^(q-1)."""
+    a = np.asarray(radii_cm, dtype=np.float64)
+    la = np.log(a)
+    d = np.empty_like(a)
+    if a.shape[0] == 1:
+        d[:] = 1.0
+    else:
+        d[1:-1] = 0.5 * (la[2:] - la[:-2])
+        d[0] = 0.5 * (la[1] - la[0])
+        d[-1] = 0.5 * (la[-1] - la[-2])
+    return per_H * a ** (1.0 - q) * d

@@ -300,3 +300,32 @@ def test_maximum_sizes_match_oracle(hsd):
         e = j_rel_err(jj[c], jr)
         print(f"max sizes cell {c}: j rel err {e:.2e}", flush=True)
         assert e < J_TOL
+
+
+def test_size_convolution_matches_oracle(hsd):
+    # four radii of the batched workload, three cells: the library's solve and
+    # convolution against the oracle's spectra and its weighted sum
+    w = synth.workload("c2_batched", n_cells=3)
+    sel = [4, 12, 20, 31]
+    grains = [w.grains[i] for i in sel]
+    radii = synth.radii_cm(3.5, 250.0, 32)[sel]
+    weights = synth.size_weights(radii)
+    ctx = hsd.Context(w.lam_cm)
+    ids = [ctx.add_grain(g) for g in grains]
+    u = make_fields(w.lam_cm, w.field_recipe, 16384, cells=np.array([0, 9000, 16383]))
+    ud = torch.tensor(u, device="cuda")
+    j = torch.empty((3, 4, w.n_lambda), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(ud, ids, j, None)
+    out = torch.empty((3, w.n_lambda), dtype=torch.float64, device="cuda")
+    ctx.hsd_size_convolve(j, weights, out)
+    ctx.hsd_sync()
+    got = out.cpu().numpy()
+    # the weighted sum itself, on the library's own spectra
+    mine = oracle.size_convolution(j.cpu().numpy(), weights, w.lam_cm)
+    assert np.allclose(got, mine, rtol=1e-12, atol=0)
+    for c in range(3):
+        jr = np.stack([oracle.solve_pair(u[c], g, w.lam_cm)[1] for g in grains])
+        ref = oracle.size_convolution(jr, weights, w.lam_cm)
+        e = j_rel_err(got[c], ref)
+        print(f"size convolution cell {c}: rel err {e:.2e}", flush=True)
+        assert e < J_TOL

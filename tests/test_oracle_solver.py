@@ -219,3 +219,27 @@ def test_uneven_workload_grid_reaches_below_coldest_equilibrium():
         # below 6 K a sizeable part of the emission falls beyond 1000 um, off
         # the grid, so emitted-on-grid / absorbed sits below 1
         assert 0.8 < d["emitted"] / d["A_rep"] < 1.01
+
+
+def test_size_convolution_is_the_weighted_sum():
+    # eq:convolution on a discrete grid: linear in the weights, one unit
+    # weight returns that grain's spectrum (times lambda when weighted)
+    rng = np.random.default_rng(4)
+    lam = synth.wavelength_grid_cm(50)
+    j = rng.random((3, 4, 50))
+    e = np.zeros(4)
+    e[2] = 1.0
+    assert np.array_equal(oracle.size_convolution(j, e, lam, lambda_weighted=False), j[:, 2])
+    assert np.allclose(oracle.size_convolution(j, e, lam), j[:, 2] * lam, rtol=1e-15)
+    w1, w2 = rng.random(4), rng.random(4)
+    assert np.allclose(oracle.size_convolution(j, w1 + 2 * w2, lam),
+                       oracle.size_convolution(j, w1, lam) + 2 * oracle.size_convolution(j, w2, lam), rtol=1e-13)
+
+
+def test_power_law_size_weights_integrate_the_distribution():
+    # sum_g w_g f(a_g) approximates int K a^-q f(a) da: with f = 1 the closed
+    # form K (a_min^(1-q) - a_max^(1-q)) / (q - 1), to the midpoint rule's error
+    r = synth.radii_cm(3.5, 250.0, 256)
+    w = synth.size_weights(r, q=3.5, per_H=1.0)
+    exact = (r[0] ** -2.5 - r[-1] ** -2.5) / 2.5
+    assert abs(w.sum() / exact - 1) < 2e-3
