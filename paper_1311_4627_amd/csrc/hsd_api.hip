@@ -27,7 +27,6 @@ struct Batch {
 struct SurWork {
     float* bands = nullptr;       size_t bands_cap = 0;
     float* X = nullptr;           size_t X_cap = 0;       // raw inputs of a chunk
-    float* Xn = nullptr;          size_t Xn_cap = 0;      // normalised inputs
     double* A = nullptr;          size_t A_cap = 0;
     float* emit = nullptr;        size_t emit_cap = 0;
     unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs [chunk][64]
@@ -369,7 +368,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.queue);
     hipFree(c.sizew);
     SurWork& w = ctx->sw;
-    hipFree(w.bands); hipFree(w.X); hipFree(w.Xn); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.bands); hipFree(w.X); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);

@@ -221,17 +221,10 @@ hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t
 hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st);
 hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
-hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,
-                         hipStream_t st);
 hipError_t sur_pack(Sur& s, hipStream_t st);
 hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
                           const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
                           unsigned short* h1, hipStream_t st);
-hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, long long row0, int n_sel,
-                            int n_slots, const int* sel, float* j, float* emit, float* h0, float* h1,
-                            hipStream_t st);
-hipError_t sur_flag(const float* emit, const double* A, long long n, float tol, unsigned char* flag, unsigned* count,
-                    hipStream_t st);
 hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
                     const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
 hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,

@@ -173,15 +173,6 @@ __global__ void __launch_bounds__(256) k_gather(const float* X, const float* Y, 
             Yb[static_cast<long long>(b) * L + k] = (Y[r * L + k] - ym[k]) / ys[k];
 }
 
-// z-score rows in place order: out[r] = (X[r] - m) / s for all rows (inference inputs).
-__global__ void __launch_bounds__(256) k_norm_rows(const float* X, long long n, int w, const float* m, const float* s,
-                                                   float* out) {
-    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n * w) return;
-    const int k = static_cast<int>(i % w);
-    out[i] = (X[i] - m[k]) / s[k];
-}
-
 // Minibatch indices from a counter-based generator (SplitMix64 of seed and
 // position; uniform enough for sampling with replacement).
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
@@ -250,7 +241,7 @@ __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m
 // supplies A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16];
 // accumulator register i of lane l is D[4 (l / 16) + i][l % 16].  One
 // 256-thread block computes a 64 x 64 tile, each wave a 32 x 32 quarter.
-enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3, EPI_SPECTRUM = 4 };
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
 
 struct GemmArgs {
     const float* A; long long sai, sak;
@@ -262,15 +253,6 @@ struct GemmArgs {
     int M, N, K;
     int kchunk;                        // split K: block z sums k in [z kchunk, (z+1) kchunk) (EPI_STORE only)
     long long split_stride;            //   and writes its partial at C + z split_stride
-    // EPI_SPECTRUM: j = A_row 10^(y s_j + m_j), scattered to pair rows, and
-    // 4 pi int j dlambda accumulated per row
-    const float* ym; const float* ys;
-    const double* Arow;               // absorbed power per row
-    const float* wq;                  // [N] trapezoid weights times 4 pi
-    float* emit;                      // [M] accumulated emitted power
-    long long row0;                   // global row of the tile's row 0 (for the pair map)
-    int n_sel, n_slots;
-    const int* sel;                   // [n_sel] slot of each selected grain
 };
 
 template <int EPI>
@@ -343,18 +325,6 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long long i = m0 + wm + a * 16 + 4 * (lane >> 4) + r;
-            float part = 0.f;
-            float* jrow = nullptr;
-            double Ai = 0.0;
-            if constexpr (EPI == EPI_SPECTRUM) {
-                if (i < g.M) {
-                    const long long gr = g.row0 + i;
-                    const long long cell = gr / g.n_sel;
-                    const int s = static_cast<int>(gr - cell * g.n_sel);
-                    jrow = g.C + (cell * g.n_slots + g.sel[s]) * g.ldc;
-                    Ai = g.Arow[i];
-                }
-            }
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int j = n0 + wn + b * 16 + (lane & 15);
@@ -368,20 +338,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                     const float z = v + g.bias[j];
                     if (g.C) g.C[i * g.ldc + j] = z;
                     g.C2[i * g.ldc2 + j] = gelu(z);
-                } else if constexpr (EPI == EPI_GELU_BWD) {
-                    g.C[i * g.ldc + j] = v * gelu_grad(g.aux[i * g.ldaux + j]);
                 } else {
-                    const float y = (v + g.bias[j]) * g.ys[j] + g.ym[j];
-                    const float jv = static_cast<float>(Ai) * exp2f(y * 3.32192809488736235f);
-                    jrow[j] = jv;
-                    part += jv * g.wq[j];
+                    g.C[i * g.ldc + j] = v * gelu_grad(g.aux[i * g.ldaux + j]);
                 }
-            }
-            if constexpr (EPI == EPI_SPECTRUM) {
-                // the 16 lanes of a row group hold this row's columns
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 16);
-                if ((lane & 15) == 0 && i < g.M) atomicAdd(g.emit + i, part);
             }
         }
     }
@@ -423,20 +382,6 @@ hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
     hipLaunchKernelGGL(k_split_sum, dim3(static_cast<unsigned>((mn + 255) / 256)), dim3(256), 0, s, work, nz, mn, mn,
                        out);
     return hipGetLastError();
-}
-
-// Flag rows whose emitted power misses the absorbed power by more than tol.
-__global__ void __launch_bounds__(256) k_flag(const float* emit, const double* A, long long n, float tol,
-                                              unsigned char* flag, unsigned* count) {
-    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-    bool f = false;
-    if (i < n) {
-        const double r = static_cast<double>(emit[i]) / A[i];
-        f = !(fabs(r - 1.0) <= tol);
-        flag[i] = f ? 1 : 0;
-    }
-    const unsigned long long b = __ballot(f);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, static_cast<unsigned>(__popcll(b)));
 }
 
 // Per-pair diagnostics of surrogate rows and the energy-balance check: diag =
@@ -937,39 +882,6 @@ hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Inference for rows [row0, row0 + M) of a selection: normalised inputs Xn
-// [M][33] -> spectra scattered to j (pair rows), emitted power per row.
-hipError_t sur_predict_rows(Sur& s, int M, const float* Xn, const double* A, long long row0, int n_sel,
-                            int n_slots, const int* sel, float* j, float* emit, float* h0, float* h1,
-                            hipStream_t st) {
-    hipError_t e = hipSuccess;
-    const float* h = Xn;
-    int in = 33;
-    float* bufs[2] = {h0, h1};
-    for (int l = 0; l < 3 && e == hipSuccess; ++l) {
-        GemmArgs g = nt(h, in, s.w + s.off_W[l], in, nullptr, 256, M, 256, in);
-        g.C2 = bufs[l % 2];
-        g.ldc2 = 256;
-        g.bias = s.w + s.off_b[l];
-        e = gemm<EPI_BIAS_GELU>(g, st);
-        h = bufs[l % 2];
-        in = 256;
-    }
-    if (e != hipSuccess) return e;
-    GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, j, s.L, M, s.L, 256);
-    g.bias = s.w + s.off_b[3];
-    g.ym = s.ym;
-    g.ys = s.ys;
-    g.Arow = A;
-    g.wq = s.wq;
-    g.emit = emit;
-    g.row0 = row0;
-    g.n_sel = n_sel;
-    g.n_slots = n_slots;
-    g.sel = sel;
-    return gemm<EPI_SPECTRUM>(g, st);
-}
-
 // Weights in BF16 for inference (packed once per parameter change).
 hipError_t sur_pack(Sur& s, hipStream_t st) {
     if (s.wb_fresh) return hipSuccess;
@@ -1032,22 +944,6 @@ hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long l
     o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit;
     o.row0 = row0; o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
     return dense<256, true>(o, st);
-}
-
-hipError_t sur_norm_rows(const float* X, long long n, int w, const float* m, const float* sd, float* out,
-                         hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_norm_rows, dim3(static_cast<unsigned>((n * w + 255) / 256)), dim3(256), 0, st, X, n, w, m,
-                       sd, out);
-    return hipGetLastError();
-}
-
-hipError_t sur_flag(const float* emit, const double* A, long long n, float tol, unsigned char* flag, unsigned* count,
-                    hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, emit, A, n, tol, flag,
-                       count);
-    return hipGetLastError();
 }
 
 hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
