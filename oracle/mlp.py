@@ -22,7 +22,11 @@ inference kernel compute, so that their gradients and outputs can be checked:
 ``bf16=True`` rounds every matrix-product operand to bfloat16 (round to
 nearest even) and keeps everything else in FP64: the GPU's BF16 products with
 FP32 accumulation then differ from it only by accumulation order and by the
-rare operand whose FP32 value rounds the other way.
+rare operand whose FP32 value rounds the other way.  In the forward pass the
+input operand of the first and of the last layer is taken as two bfloat16
+terms, hi = bf16(x) and lo = bf16(x - hi), each multiplied by the same
+bfloat16 weights (a single bfloat16 keeps only 8 significant bits, which
+blurs the band energies by about 1%); the backward products use one term.
 """
 
 from __future__ import annotations
@@ -35,6 +39,8 @@ from scipy import special
 
 N_BANDS = 32
 SQRT2 = math.sqrt(2.0)
+# forward layers whose input operand is split into two bfloat16 terms
+SPLIT_LAYERS = (0, 3)
 
 
 # ---- features, targets, metric -------------------------------------------------
@@ -122,10 +128,16 @@ def pack(layers: Sequence[Tuple[np.ndarray, np.ndarray]]) -> np.ndarray:
     return np.concatenate([np.concatenate([W.ravel(), b]) for W, b in layers])
 
 
-def _mm(a: np.ndarray, b: np.ndarray, bf16: bool) -> np.ndarray:
-    if bf16:
-        a, b = bf16_round(a), bf16_round(b)
-    return a @ b
+def _mm(a: np.ndarray, b: np.ndarray, bf16: bool, split: bool = False) -> np.ndarray:
+    if not bf16:
+        return a @ b
+    b = bf16_round(b)
+    hi = bf16_round(a)
+    if not split:
+        return hi @ b
+    # the low term is rounded from the FP32 residual, as on the device
+    lo = bf16_round(np.asarray(a, dtype=np.float32) - hi.astype(np.float32))
+    return hi @ b + lo @ b
 
 
 def forward(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, bf16: bool = False):
@@ -135,7 +147,7 @@ def forward(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, bf16: bool =
     h = np.asarray(X, dtype=np.float64)
     hs, zs = [h], []
     for i, (W, b) in enumerate(layers):
-        z = _mm(h, W.T, bf16) + b
+        z = _mm(h, W.T, bf16, split=i in SPLIT_LAYERS) + b
         zs.append(z)
         h = gelu(z) if i + 1 < len(layers) else z
         hs.append(h)

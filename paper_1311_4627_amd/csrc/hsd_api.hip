@@ -29,8 +29,8 @@ struct SurWork {
     float* X = nullptr;           size_t X_cap = 0;       // raw inputs of a chunk
     double* A = nullptr;          size_t A_cap = 0;
     float* emit = nullptr;        size_t emit_cap = 0;
-    unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs [chunk][64]
-    unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][256]
+    unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs, hi and lo [chunk][96]
+    unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][512] (hi, lo)
     unsigned short* h1 = nullptr; size_t h1_cap = 0;
     int* sel = nullptr;           size_t sel_cap = 0;
     const double** cabs = nullptr; size_t cabs_cap = 0;
@@ -939,8 +939,8 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
     HSD_HIP(ctx, grow(w.X, w.X_cap, ch * 33));
     HSD_HIP(ctx, grow(w.A, w.A_cap, ch));
     HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch));
-    HSD_HIP(ctx, grow(w.xb, w.xb_cap, ch * 64));
-    HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 256));
+    HSD_HIP(ctx, grow(w.xb, w.xb_cap, ch * 96));
+    HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 512));
     HSD_HIP(ctx, grow(w.h1, w.h1_cap, ch * 256));
     for (long long r0 = 0; r0 < rows; r0 += kSurChunk) {
         const long long n = std::min(kSurChunk, rows - r0);

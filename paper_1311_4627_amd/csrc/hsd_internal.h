@@ -176,6 +176,10 @@ hipError_t launch_sizedist(const float* j, const double* w, const double* lam, i
                            double* out, hipStream_t s);
 
 // ---- learned surrogate (hsd_surrogate.hip) ----
+// Layers whose input operand enters the BF16 products as two terms, hi =
+// bf16(x) and lo = bf16(x - hi) (about 16 significant bits): the normalised
+// features (the network's input) and the last hidden activations.
+constexpr int kSplitIn[4] = {1, 0, 0, 1};
 struct Sur {
     Ctx* c = nullptr;
     int L = 0;

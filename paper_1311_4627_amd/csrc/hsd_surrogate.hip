@@ -36,6 +36,7 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
     u += 0x7FFFu + ((u >> 16) & 1u);
     return static_cast<unsigned short>(u >> 16);
 }
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
 
 __device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
 __device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
@@ -253,6 +254,8 @@ struct GemmArgs {
     int M, N, K;
     int kchunk;                        // split K: block z sums k in [z kchunk, (z+1) kchunk) (EPI_STORE only)
     long long split_stride;            //   and writes its partial at C + z split_stride
+    int asplit;                        // A as two BF16 terms: k in [K, 2K) stages A[i][k-K] - bf16(A[i][k-K])
+                                       //   against B[k-K][j] (not with split K)
 };
 
 template <int EPI>
@@ -271,7 +274,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool a_kfast = g.sak == 1;
     const bool b_kfast = g.sbk == 1;
-    int kbeg = 0, kend = g.K;
+    const int Kr = g.K;
+    int kbeg = 0, kend = g.asplit ? 2 * Kr : Kr;
     float* Cz = g.C;
     if constexpr (EPI == EPI_STORE) {
         if (g.kchunk > 0) {
@@ -289,7 +293,11 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             const long long gi = m0 + i;
             const int gk = k0 + k;
             float v = 0.f;
-            if (gi < g.M && gk < kend) v = g.A[gi * g.sai + gk * g.sak];
+            if (gi < g.M && gk < kend) {
+                const bool lo = gk >= Kr;
+                v = g.A[gi * g.sai + (lo ? gk - Kr : gk) * g.sak];
+                if (lo) v -= from_bf16(to_bf16(v));
+            }
             As[i][k] = to_bf16(v);
         }
 #pragma unroll
@@ -299,7 +307,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             const int k = b_kfast ? idx % BK : idx / BN;
             const int gj = n0 + j, gk = k0 + k;
             float v = 0.f;
-            if (gj < g.N && gk < kend) v = g.B[static_cast<long long>(gk) * g.sbk + static_cast<long long>(gj) * g.sbj];
+            if (gj < g.N && gk < kend) {
+                const int kr = gk >= Kr ? gk - Kr : gk;
+                v = g.B[static_cast<long long>(kr) * g.sbk + static_cast<long long>(gj) * g.sbj];
+            }
             Bs[j][k] = to_bf16(v);
         }
         __syncthreads();
@@ -440,10 +451,11 @@ __global__ void __launch_bounds__(256) k_fb_scatter(const float* diag, long long
 __global__ void __launch_bounds__(256) k_pack_bf16(const float* w, long long oW1, long long oW2, long long oW3,
                                                    long long oW4, int L, unsigned short* wb) {
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-    const long long n1 = 256 * 64, n2 = 256 * 256, n4 = static_cast<long long>(L) * 256;
+    const long long n1 = 256 * 96, n2 = 256 * 256, n4 = static_cast<long long>(L) * 256;
     if (i < n1) {
-        const int r = static_cast<int>(i / 64), k = static_cast<int>(i % 64);
-        wb[i] = k < 33 ? to_bf16(w[oW1 + r * 33 + k]) : 0;
+        // first layer against [hi | lo | 0] inputs: the 33 weights twice, then zeros
+        const int r = static_cast<int>(i / 96), k = static_cast<int>(i % 96);
+        wb[i] = k < 66 ? to_bf16(w[oW1 + r * 33 + (k < 33 ? k : k - 33)]) : 0;
     } else if (i < n1 + n2) {
         wb[i] = to_bf16(w[oW2 + (i - n1)]);
     } else if (i < n1 + 2 * n2) {
@@ -453,14 +465,22 @@ __global__ void __launch_bounds__(256) k_pack_bf16(const float* w, long long oW1
     }
 }
 
-// Normalised BF16 inputs, zero padded to 64: xb[r][k] = (X[r][k] - m_k) / s_k.
+// Normalised inputs as two BF16 terms, [r][0, 33) = hi = bf16(x) and
+// [r][33, 66) = lo = bf16(x - hi) with x = (X[r][k] - m_k) / s_k; [66, 96) = 0.
 __global__ void __launch_bounds__(256) k_norm_bf16(const float* X, long long n, const float* m, const float* sd,
                                                    unsigned short* xb) {
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n * 64) return;
-    const long long r = i >> 6;
-    const int k = static_cast<int>(i & 63);
-    xb[i] = k < 33 ? to_bf16((X[r * 33 + k] - m[k]) / sd[k]) : 0;
+    if (i >= n * 96) return;
+    const long long r = i / 96;
+    const int k = static_cast<int>(i - r * 96);
+    unsigned short v = 0;
+    if (k < 66) {
+        const int kk = k < 33 ? k : k - 33;
+        const float x = (X[r * 33 + kk] - m[kk]) / sd[kk];
+        const unsigned short hi = to_bf16(x);
+        v = k < 33 ? hi : to_bf16(x - from_bf16(hi));
+    }
+    xb[i] = v;
 }
 
 struct DenseArgs {
@@ -483,12 +503,17 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // 32 rows as two groups of 16, so every weight fragment read from LDS feeds
 // two matrix-core products.  v_mfma_f32_16x16x32_bf16 takes 8 inputs per lane;
 // step s uses k = (K/4) q + 8 s + 0..7 for lane l (q = l / 16) in both operands.
-template <int K, bool SPECTRUM>
+// SPLIT, hidden layer: each activation is also written as its low BF16 term,
+// out rows of 2N (hi, then lo).  SPLIT, output layer: input rows of 2K (hi,
+// then lo), both terms multiplied by the same weight fragment.
+template <int K, bool SPECTRUM, bool SPLIT>
 __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
     // rows per wave: 2 groups of 16 (hidden layers), 1 group (output layer,
     // whose epilogue needs the registers)
     constexpr int G = SPECTRUM ? 1 : 2;
     constexpr int NB = 128, TM = 64 * G, LDK = K + 8, S = K / 32;
+    constexpr int NT = SPECTRUM && SPLIT ? 2 : 1;       // input terms per row
+    constexpr int RIN = K * NT;                          // input row length
     __shared__ __align__(16) unsigned short Ws[NB][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n0 = blockIdx.x * NB;
@@ -510,13 +535,16 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const long long row = static_cast<long long>(t) * TM + wave * 16 * G + g * 16 + rl;
-            if (t < n_tiles && row < a.M) {
-                const u32x4* src = reinterpret_cast<const u32x4*>(a.in + row * K + (K / 4) * q);
 #pragma unroll
-                for (int v = 0; v < S; ++v) f[g][v] = src[v];
-            } else {
+            for (int h = 0; h < NT; ++h) {
+                if (t < n_tiles && row < a.M) {
+                    const u32x4* src = reinterpret_cast<const u32x4*>(a.in + row * RIN + h * K + (K / 4) * q);
 #pragma unroll
-                for (int v = 0; v < S; ++v) f[g][v] = u32x4{0u, 0u, 0u, 0u};
+                    for (int v = 0; v < S; ++v) f[g][h][v] = src[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < S; ++v) f[g][h][v] = u32x4{0u, 0u, 0u, 0u};
+                }
             }
         }
     };
@@ -533,7 +561,7 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
         }
     }
     // the next tile's inputs are loaded while this tile computes
-    u32x4 cur[G][S], nxt[G][S];
+    u32x4 cur[G][NT][S], nxt[G][NT][S];
     int t = blockIdx.y;
     load(t, cur);
     for (; t < n_tiles; t += gridDim.y) {
@@ -551,8 +579,10 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
                     bf16x8, *reinterpret_cast<const u32x4*>(&Ws[16 * c + rl][(K / 4) * q + 8 * st]));
 #pragma unroll
                 for (int g = 0; g < G; ++g)
-                    acc[g][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[g][st]), b,
-                                                                        acc[g][c], 0, 0, 0);
+#pragma unroll
+                    for (int h = 0; h < NT; ++h)
+                        acc[g][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[g][h][st]),
+                                                                            b, acc[g][c], 0, 0, 0);
             }
             // keep each step's weight fragments within the step (bounds register use)
             __builtin_amdgcn_sched_barrier(0);
@@ -565,20 +595,33 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
             for (int i = 0; i < 4; ++i) {
                 const long long r = static_cast<long long>(t) * TM + wave * 16 * G + g * 16 + 4 * q + i;
                 if constexpr (!SPECTRUM) {
+                    constexpr int NO = SPLIT ? 2 : 1;             // output terms per activation
                     if (r < a.M) {
-                        if (nc + 8 <= a.N) {
-                            unsigned pk[4];
+                        float hv[8];
+                        unsigned short hb[8], lb[8];
 #pragma unroll
-                            for (int c = 0; c < 8; c += 2) {
-                                const unsigned lo = to_bf16(gelu(acc[g][c][i] + a.bias[nc + c]));
-                                const unsigned hi = to_bf16(gelu(acc[g][c + 1][i] + a.bias[nc + c + 1]));
-                                pk[c / 2] = lo | (hi << 16);
-                            }
-                            *reinterpret_cast<u32x4*>(a.out + r * a.N + nc) = u32x4{pk[0], pk[1], pk[2], pk[3]};
+                        for (int c = 0; c < 8; ++c) {
+                            hv[c] = gelu(acc[g][c][i] + a.bias[nc + c < a.N ? nc + c : a.N - 1]);
+                            hb[c] = to_bf16(hv[c]);
+                            lb[c] = SPLIT ? to_bf16(hv[c] - from_bf16(hb[c])) : 0;
+                        }
+                        unsigned short* orow = a.out + r * (NO * a.N);
+                        if (nc + 8 <= a.N) {
+                            auto pack8 = [](const unsigned short* v) {
+                                return u32x4{v[0] | (static_cast<unsigned>(v[1]) << 16),
+                                             v[2] | (static_cast<unsigned>(v[3]) << 16),
+                                             v[4] | (static_cast<unsigned>(v[5]) << 16),
+                                             v[6] | (static_cast<unsigned>(v[7]) << 16)};
+                            };
+                            *reinterpret_cast<u32x4*>(orow + nc) = pack8(hb);
+                            if constexpr (SPLIT) *reinterpret_cast<u32x4*>(orow + a.N + nc) = pack8(lb);
                         } else {
 #pragma unroll
                             for (int c = 0; c < 8; ++c)
-                                if (nc + c < a.N) a.out[r * a.N + nc + c] = to_bf16(gelu(acc[g][c][i] + a.bias[nc + c]));
+                                if (nc + c < a.N) {
+                                    orow[nc + c] = hb[c];
+                                    if constexpr (SPLIT) orow[a.N + nc + c] = lb[c];
+                                }
                         }
                     }
                 } else {
@@ -613,7 +656,9 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
-            for (int v = 0; v < S; ++v) cur[g][v] = nxt[g][v];
+            for (int h = 0; h < NT; ++h)
+#pragma unroll
+                for (int v = 0; v < S; ++v) cur[g][h][v] = nxt[g][h][v];
     }
 }
 
@@ -781,12 +826,14 @@ GemmArgs nt(const float* A, int lda, const float* W, int ldw, float* C, int ldc,
 
 // Forward pass of a batch of B normalised rows Xb [B][33]; keeps the
 // pre-activations Z and activations H (training) and writes the output Yh.
+// The inputs of the first and the last layer enter as two BF16 terms each.
 hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep_z) {
     hipError_t e = hipSuccess;
     const float* h = Xb;
     int in = 33;
     for (int l = 0; l < 3 && e == hipSuccess; ++l) {
         GemmArgs g = nt(h, in, s.w + s.off_W[l], in, keep_z ? s.Z[l] : nullptr, 256, B, 256, in);
+        g.asplit = kSplitIn[l];
         g.C2 = s.H[l];
         g.ldc2 = 256;
         g.bias = s.w + s.off_b[l];
@@ -796,6 +843,7 @@ hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep
     }
     if (e != hipSuccess) return e;
     GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, s.Yh, s.L, B, s.L, 256);
+    g.asplit = kSplitIn[3];
     g.bias = s.w + s.off_b[3];
     return gemm<EPI_BIAS>(g, st);
 }
@@ -885,7 +933,7 @@ hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
 // Weights in BF16 for inference (packed once per parameter change).
 hipError_t sur_pack(Sur& s, hipStream_t st) {
     if (s.wb_fresh) return hipSuccess;
-    const long long n = 256LL * 64 + 2LL * 256 * 256 + static_cast<long long>(s.L) * 256;
+    const long long n = 256LL * 96 + 2LL * 256 * 256 + static_cast<long long>(s.L) * 256;
     if (!s.wb) {
         const hipError_t e = hipMalloc(&s.wb, sizeof(unsigned short) * n);
         if (e != hipSuccess) return e;
@@ -899,13 +947,13 @@ hipError_t sur_pack(Sur& s, hipStream_t st) {
 
 namespace {
 
-template <int K, bool SPEC>
+template <int K, bool SPEC, bool SPLIT>
 hipError_t dense(const DenseArgs& a, hipStream_t st) {
     const int nsplit = (a.N + 127) / 128;
     const int n_tiles = (a.M + (SPEC ? 63 : 127)) / (SPEC ? 64 : 128);
     // two blocks per CU fit (LDS): spread them over the column slices
     const int per_split = std::max(1, std::min(n_tiles, 512 / nsplit));
-    hipLaunchKernelGGL((k_dense<K, SPEC>), dim3(nsplit, per_split), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_dense<K, SPEC, SPLIT>), dim3(nsplit, per_split), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -913,37 +961,39 @@ hipError_t dense(const DenseArgs& a, hipStream_t st) {
 
 // Inference of rows [row0, row0 + M) of a selection from raw inputs X [M][33]:
 // spectra scattered to j (pair rows) and 4 pi int j dlambda added to emit.
+// Workspaces: xb [M][96], h0 [M][512], h1 [M][256] BF16.
 hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
                           const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
                           unsigned short* h1, hipStream_t st) {
     if (M <= 0) return hipSuccess;
     hipError_t e = sur_pack(s, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norm_bf16, dim3(static_cast<unsigned>((static_cast<long long>(M) * 64 + 255) / 256)),
+    hipLaunchKernelGGL(k_norm_bf16, dim3(static_cast<unsigned>((static_cast<long long>(M) * 96 + 255) / 256)),
                        dim3(256), 0, st, X, static_cast<long long>(M), s.xm, s.xs, xb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned short* W1 = s.wb;
-    const unsigned short* W2 = W1 + 256 * 64;
+    const unsigned short* W2 = W1 + 256 * 96;
     const unsigned short* W3 = W2 + 256 * 256;
     const unsigned short* W4 = W3 + 256 * 256;
     DenseArgs d{};
     d.M = M;
     d.N = 256;
     d.in = xb; d.W = W1; d.bias = s.w + s.off_b[0]; d.out = h0;
-    e = dense<64, false>(d, st);
+    e = dense<96, false, false>(d, st);
     if (e != hipSuccess) return e;
     d.in = h0; d.W = W2; d.bias = s.w + s.off_b[1]; d.out = h1;
-    e = dense<256, false>(d, st);
+    e = dense<256, false, false>(d, st);
     if (e != hipSuccess) return e;
+    // last hidden layer: hi and lo terms for the output layer
     d.in = h1; d.W = W3; d.bias = s.w + s.off_b[2]; d.out = h0;
-    e = dense<256, false>(d, st);
+    e = dense<256, false, true>(d, st);
     if (e != hipSuccess) return e;
     DenseArgs o{};
     o.in = h0; o.W = W4; o.bias = s.w + s.off_b[3]; o.M = M; o.N = s.L;
     o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit;
     o.row0 = row0; o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
-    return dense<256, true>(o, st);
+    return dense<256, true, true>(o, st);
 }
 
 hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,

@@ -86,6 +86,25 @@ def test_bf16_rounding_matches_torch():
     assert mlp.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6    # tie to even, upward
 
 
+def test_split_operand_keeps_sixteen_bits():
+    # hi + lo reproduces the FP32 operand to about 2^-17 relative, so the split
+    # product sits ~2^8 closer to the exact one than a single-term product
+    # with the same bfloat16 weights
+    rng = np.random.default_rng(11)
+    a = rng.normal(0, 1.5, (400, 33))
+    W = rng.normal(0, 0.3, (33, 64))
+    hi = mlp.bf16_round(a)
+    lo = mlp.bf16_round(np.asarray(a, np.float32) - hi.astype(np.float32))
+    assert np.all(np.abs(lo) <= 2.0 ** -8 * np.abs(hi))
+    assert np.max(np.abs(hi + lo - a) / np.abs(a)) < 2.0 ** -16
+    Wq = mlp.bf16_round(W)
+    exact = a @ Wq
+    e1 = np.abs(mlp._mm(a, W, True) - exact).max()
+    e2 = np.abs(mlp._mm(a, W, True, split=True) - exact).max()
+    assert e2 < e1 / 64
+    assert np.array_equal(mlp._mm(a, W, False), a @ W)
+
+
 def test_bf16_mode_is_close_to_fp64():
     flat, X, Y = _small_problem(9)
     l64, g64 = mlp.loss_and_grad(flat, SMALL, X, Y)
