@@ -26,9 +26,8 @@ struct Batch {
 // Workspace of surrogate solves (grown on demand, kept with the context).
 struct SurWork {
     float* bands = nullptr;       size_t bands_cap = 0;
-    float* X = nullptr;           size_t X_cap = 0;       // raw inputs of a chunk
     double* A = nullptr;          size_t A_cap = 0;
-    float* emit = nullptr;        size_t emit_cap = 0;
+    float* emit = nullptr;        size_t emit_cap = 0;    // emitted-power partials [column slice][chunk]
     unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs, hi and lo [chunk][96]
     unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][512] (hi, lo)
     unsigned short* h1 = nullptr; size_t h1_cap = 0;
@@ -368,7 +367,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.queue);
     hipFree(c.sizew);
     SurWork& w = ctx->sw;
-    hipFree(w.bands); hipFree(w.X); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);
@@ -936,20 +935,20 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
     const int n_sel = static_cast<int>(slots.size());
     const long long rows = static_cast<long long>(n_cells) * n_sel;
     const size_t ch = static_cast<size_t>(std::min(rows, kSurChunk));
-    HSD_HIP(ctx, grow(w.X, w.X_cap, ch * 33));
     HSD_HIP(ctx, grow(w.A, w.A_cap, ch));
-    HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch));
+    const int n_parts = hsd::sur_emit_parts(c.L);
+    HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch * n_parts));
     HSD_HIP(ctx, grow(w.xb, w.xb_cap, ch * 96));
     HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 512));
     HSD_HIP(ctx, grow(w.h1, w.h1_cap, ch * 256));
     for (long long r0 = 0; r0 < rows; r0 += kSurChunk) {
         const long long n = std::min(kSurChunk, rows - r0);
-        HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.wcT, w.loga, r0, n, n_sel, w.X, w.A, s));
-        HSD_HIP(ctx, hipMemsetAsync(w.emit, 0, sizeof(float) * n, s));
-        HSD_HIP(ctx, hsd::sur_infer_rows(sur, static_cast<int>(n), w.X, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
-                                         w.xb, w.h0, w.h1, s));
+        HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.wcT, w.loga, r0, n, n_sel, nullptr, w.A, w.xb, sur.xm, sur.xs,
+                                    s));
+        HSD_HIP(ctx, hsd::sur_infer_rows(sur, static_cast<int>(n), w.xb, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
+                                         w.h0, w.h1, s));
         if (diag)
-            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, r0, n, n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
+            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, r0, n, n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
     }
     return HSD_OK;
 }
@@ -977,7 +976,7 @@ hsd_status hsd_sur_features(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, 
     HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
     HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
     HSD_HIP(ctx, hsd::sur_pairs(c, u_dev, w.bands, w.wcT, w.loga, 0, static_cast<long long>(n_cells) * n_grains,
-                                n_grains, X_dev, A_dev, s));
+                                n_grains, X_dev, A_dev, nullptr, nullptr, nullptr, s));
     return HSD_OK;
 }
 

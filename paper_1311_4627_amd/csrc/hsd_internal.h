@@ -215,7 +215,8 @@ hipError_t sur_grow(Sur& s, int B);
 hipError_t sur_bands(const Ctx& c, const double* u, int n_cells, float* bands, hipStream_t st);
 hipError_t sur_wc(const Ctx& c, const double* const* cabs, int n_sel, double* wcT, hipStream_t st);
 hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* wcT, const float* loga,
-                     long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st);
+                     long long row0, long long n_rows, int n_sel, float* X, double* A, unsigned short* xb,
+                     const float* xm, const float* xs, hipStream_t st);
 hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st);
 hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd);
 hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep_z);
@@ -226,11 +227,12 @@ hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B,
 hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
 hipError_t sur_pack(Sur& s, hipStream_t st);
-hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
-                          const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
+hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
+                          int n_slots, const int* sel, float* j, float* emit, unsigned short* h0,
                           unsigned short* h1, hipStream_t st);
-hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
-                    const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
+int sur_emit_parts(int L);
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, long long row0, long long n, int n_sel,
+                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
 hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,
                           int* cellmap, long long* pairs, hipStream_t st);
 

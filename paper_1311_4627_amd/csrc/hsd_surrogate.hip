@@ -30,18 +30,42 @@ constexpr int kBands = 32;
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> bfloat16, round to nearest even (finite values).
+// FP32 -> bfloat16, round to nearest even (the hardware conversion).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned short to_bf16(float f) {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<unsigned short>(u >> 16);
+    return __builtin_bit_cast(unsigned short, static_cast<__bf16>(f));
+}
+// two values, lo in the low half
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 __device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
 
-__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfcf(-z * 0.70710678118654752f); }
+// erfc from the Chebyshev-fitted form of Numerical Recipes (Press et al.,
+// "erfcc"): erfc(x) = t exp(-x^2 + P(t)), t = 1 / (1 + |x|/2), P of degree 9,
+// fractional error below 1.2e-7 for x >= 0; erfc(-x) = 2 - erfc(x).  Branch
+// free: one reciprocal, one exp and ten FMAs.
+__device__ __forceinline__ float erfc_fast(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, ax, 1.0f));
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    const float r = t * __expf(fmaf(-ax, ax, p));
+    return x >= 0.f ? r : 2.0f - r;
+}
+__device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfc_fast(-z * 0.70710678118654752f); }
 __device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    return phi_cdf(z) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return phi_cdf(z) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 // ---- per-cell band energies --------------------------------------------------
@@ -72,10 +96,13 @@ __global__ void __launch_bounds__(256) k_wc(const double* const* cabs, const dou
 }
 
 // Pair rows R = cell * n_sel + s (s indexes the selected grains) in
-// [row0, row0 + n_rows): raw inputs (33 floats) and the absorbed power A, both
-// written at R - row0.  One wave per cell, one lane per selected grain: the
-// field value u_j is the same for every lane (a scalar load) and lane s reads
-// its own column of wcT, so the dot products need no reductions.
+// [row0, row0 + n_rows), written at R - row0: the absorbed power A (FP64), and
+// the inputs either raw (X, 33 floats) or normalised as the first layer reads
+// them (xb, 96 BF16: hi terms of the 33 inputs, their lo terms, zeros).
+// A[cell][s] = sum_j u[cell][j] wcT[j][s] is a small FP64 matrix product: a
+// block takes 8 cells x 64 selected grains and stages 64-wavelength slices of
+// both operands in LDS; each thread sums two cells of one grain in wavelength
+// order.
 struct PairArgs {
     const double* u;
     const float* bands;        // [n_cells][32]
@@ -86,43 +113,107 @@ struct PairArgs {
     int n_sel, L;
     float* X;                  // [n_rows][33] or null
     double* A;                 // [n_rows] or null
+    unsigned short* xb;        // [n_rows][96] or null
+    const float* xm; const float* xs;   // input statistics (xb)
 };
 
+constexpr int kPairCells = 8, kPairSlots = 64, kPairLam = 64;
+
 __global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
-    __shared__ double us[4][1024];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long cell = a.cell0 + static_cast<long long>(blockIdx.x) * 4 + wave;
-    const bool live = cell < a.cell0 + a.n_cells;
-    if (live) {
-        const double* uc = a.u + cell * a.L;
-        for (int j = lane; j < a.L; j += 64) us[wave][j] = uc[j];
+    __shared__ double us[kPairCells][kPairLam];
+    __shared__ double ws[kPairLam][kPairSlots];
+    const int tid = threadIdx.x;
+    const int sl = tid & 63, cg = tid >> 6;
+    const long long c0 = a.cell0 + static_cast<long long>(blockIdx.x) * kPairCells;
+    const int s0 = blockIdx.y * kPairSlots;
+    const int ns = min(kPairSlots, a.n_sel - s0);
+    const int nc = static_cast<int>(min(static_cast<long long>(kPairCells), a.cell0 + a.n_cells - c0));
+    if (a.A) {
+        double p0 = 0.0, p1 = 0.0;
+        for (int j0 = 0; j0 < a.L; j0 += kPairLam) {
+            const int nl = min(kPairLam, a.L - j0);
+            for (int e = tid; e < kPairCells * kPairLam; e += 256) {
+                const int cc = e / kPairLam, l = e % kPairLam;
+                us[cc][l] = cc < nc && l < nl ? a.u[(c0 + cc) * a.L + j0 + l] : 0.0;
+            }
+            for (int e = tid; e < kPairLam * kPairSlots; e += 256) {
+                const int l = e / kPairSlots, ss = e % kPairSlots;
+                ws[l][ss] = l < nl && ss < ns ? a.wcT[static_cast<long long>(j0 + l) * a.n_sel + s0 + ss] : 0.0;
+            }
+            __syncthreads();
+            for (int l = 0; l < nl; ++l) {
+                const double w = ws[l][sl];
+                p0 = fma(us[2 * cg][l], w, p0);
+                p1 = fma(us[2 * cg + 1][l], w, p1);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cc = 2 * cg + h;
+            const long long rr = (c0 + cc) * a.n_sel + s0 + sl - a.row0;
+            if (cc < nc && sl < ns && rr >= 0 && rr < a.n_rows) a.A[rr] = h ? p1 : p0;
+        }
+    }
+    // inputs: staged once in LDS (raw, and normalised as hi and lo terms), so
+    // that the write loops below issue stores only (a load between stores
+    // would wait for all of them: the memory counter is in order)
+    __shared__ float braw[kPairCells][kBands], araw[kPairSlots];
+    __shared__ unsigned short bnorm[kPairCells][2][kBands], anorm[kPairSlots][2];
+    {
+        const int cc = tid / kBands, k = tid % kBands;   // 256 threads = 8 cells x 32 bands
+        if (cc < nc) {
+            const float v = a.bands[(c0 + cc) * kBands + k];
+            braw[cc][k] = v;
+            if (a.xb) {
+                const float x = (v - a.xm[k]) / a.xs[k];
+                const unsigned short hi = to_bf16(x);
+                bnorm[cc][0][k] = hi;
+                bnorm[cc][1][k] = to_bf16(x - from_bf16(hi));
+            }
+        }
+        if (tid < ns) {
+            const float v = a.loga[s0 + tid];
+            araw[tid] = v;
+            if (a.xb) {
+                const float x = (v - a.xm[kBands]) / a.xs[kBands];
+                const unsigned short hi = to_bf16(x);
+                anorm[tid][0] = hi;
+                anorm[tid][1] = to_bf16(x - from_bf16(hi));
+            }
+        }
     }
     __syncthreads();
-    if (!live) return;
-    for (int s0 = 0; s0 < a.n_sel; s0 += 64) {
-        const int s = s0 + lane;
-        const long long rr = cell * a.n_sel + s - a.row0;      // output row
-        const bool mine = s < a.n_sel && rr >= 0 && rr < a.n_rows;
-        if (a.A) {
-            double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-            const double* wc = a.wcT + (s < a.n_sel ? s : 0);
-            const long long st = a.n_sel;
-            int j = 0;
-            for (; j + 4 <= a.L; j += 4) {
-                p0 = fma(us[wave][j], wc[j * st], p0);
-                p1 = fma(us[wave][j + 1], wc[(j + 1) * st], p1);
-                p2 = fma(us[wave][j + 2], wc[(j + 2) * st], p2);
-                p3 = fma(us[wave][j + 3], wc[(j + 3) * st], p3);
+    // the rows of one cell and this slot group are contiguous
+    for (int cc = 0; cc < nc; ++cc) {
+        const long long rbase = (c0 + cc) * a.n_sel + s0 - a.row0;
+        if (a.X) {
+            for (int e = tid; e < ns * 33; e += 256) {
+                const int ss = e / 33, k = e % 33;
+                const long long rr = rbase + ss;
+                if (rr >= 0 && rr < a.n_rows) a.X[rr * 33 + k] = k < kBands ? braw[cc][k] : araw[ss];
             }
-            for (; j < a.L; ++j) p0 = fma(us[wave][j], wc[j * st], p0);
-            if (mine) a.A[rr] = (p0 + p1) + (p2 + p3);
         }
-        if (a.X && mine) {
-            float* xr = a.X + rr * 33;
-            const float* bc = a.bands + cell * kBands;
-#pragma unroll 8
-            for (int k = 0; k < kBands; ++k) xr[k] = bc[k];
-            xr[kBands] = a.loga[s];
+        if (a.xb) {
+            // row layout: hi of the 33 inputs, lo of the 33 inputs, 30 zeros;
+            // two columns per 32-bit store
+            for (int e = tid; e < ns * 48; e += 256) {
+                const int ss = e / 48, k2 = 2 * (e % 48);
+                const long long rr = rbase + ss;
+                if (rr < 0 || rr >= a.n_rows) continue;
+                unsigned v = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int col = k2 + h;
+                    unsigned b = 0;
+                    if (col < 66) {
+                        const int term = col < 33 ? 0 : 1, k = col - 33 * term;
+                        b = k < kBands ? bnorm[cc][term][k] : anorm[ss][term];
+                    }
+                    v |= b << (16 * h);
+                }
+                reinterpret_cast<unsigned*>(a.xb + rr * 96)[k2 / 2] = v;
+            }
         }
     }
 }
@@ -398,17 +489,20 @@ hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
 // Per-pair diagnostics of surrogate rows and the energy-balance check: diag =
 // (A, 4 pi int j dlambda, A, flags) with flags bit 3 (value from the surrogate)
 // and bit 4 (|emitted / A - 1| > tol: the pair goes to the plain solve);
-// cnt[slot] and cnt[n_slots] count the flagged pairs.
-__global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, long long row0, long long n,
-                                                  int n_sel, int n_slots, const int* sel, float tol, float* diag,
-                                                  unsigned* cnt) {
+// cnt[slot] and cnt[n_slots] count the flagged pairs.  The emitted power is
+// the sum of the n_parts column-slice partials emit[x][r], in slice order (a
+// fixed order, so the check decides the same way on every run).
+__global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, int n_parts, long long row0,
+                                                  long long n, int n_sel, int n_slots, const int* sel, float tol,
+                                                  float* diag, unsigned* cnt) {
     const long long r = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (r >= n) return;
     const long long rg = row0 + r;
     const long long cell = rg / n_sel;
     const int slot = sel[static_cast<int>(rg - cell * n_sel)];
     const double a = A[r];
-    const float e = emit[r];
+    float e = 0.f;
+    for (int x = 0; x < n_parts; ++x) e += emit[x * n + r];
     const bool bad = !(fabs(static_cast<double>(e) / a - 1.0) <= tol);
     float* d = diag + (cell * n_slots + slot) * 4;
     d[0] = static_cast<float>(a);
@@ -465,24 +559,6 @@ __global__ void __launch_bounds__(256) k_pack_bf16(const float* w, long long oW1
     }
 }
 
-// Normalised inputs as two BF16 terms, [r][0, 33) = hi = bf16(x) and
-// [r][33, 66) = lo = bf16(x - hi) with x = (X[r][k] - m_k) / s_k; [66, 96) = 0.
-__global__ void __launch_bounds__(256) k_norm_bf16(const float* X, long long n, const float* m, const float* sd,
-                                                   unsigned short* xb) {
-    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n * 96) return;
-    const long long r = i / 96;
-    const int k = static_cast<int>(i - r * 96);
-    unsigned short v = 0;
-    if (k < 66) {
-        const int kk = k < 33 ? k : k - 33;
-        const float x = (X[r * 33 + kk] - m[kk]) / sd[kk];
-        const unsigned short hi = to_bf16(x);
-        v = k < 33 ? hi : to_bf16(x - from_bf16(hi));
-    }
-    xb[i] = v;
-}
-
 struct DenseArgs {
     const unsigned short* in;   // [M][K] bf16
     const unsigned short* W;    // [N][K] bf16
@@ -493,7 +569,8 @@ struct DenseArgs {
     float* j; int L;
     const float* ym; const float* ys;
     const double* Arow; const float* wq; float* emit;
-    long long row0; int n_sel, n_slots; const int* sel;
+    long long cell0; int off0;  // row r is selection entry (off0 + r) of cells from cell0 on
+    int n_sel, n_slots; const int* sel;
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -507,7 +584,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // out rows of 2N (hi, then lo).  SPLIT, output layer: input rows of 2K (hi,
 // then lo), both terms multiplied by the same weight fragment.
 template <int K, bool SPECTRUM, bool SPLIT>
-__global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_dense(DenseArgs a) {
     // rows per wave: 2 groups of 16 (hidden layers), 1 group (output layer,
     // whose epilogue needs the registers)
     constexpr int G = SPECTRUM ? 1 : 2;
@@ -516,20 +593,33 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
     constexpr int RIN = K * NT;                          // input row length
     __shared__ __align__(16) unsigned short Ws[NB][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n0 = blockIdx.x * NB;
-    // LDS row 16 c + m holds output column 8 m + c of the slice, so that the
-    // accumulators of lane l (MFMA column l % 16 of subtiles c = 0..7) are the
-    // 8 consecutive output columns 8 (l % 16) .. + 7: one vector store per row
+    // 1-D grid of nsplit column slices x ngrp row-tile groups (ngrp a multiple
+    // of 8).  Workgroups go to the 8 XCDs round robin by index, so block L
+    // runs on XCD L % 8; the mapping below puts every column slice of a group
+    // on the same XCD, where the group's input rows are fetched into L2 once
+    const int nsplit = (a.N + NB - 1) / NB;
+    const int ngrp = static_cast<int>(gridDim.x) / nsplit;
+    const int kk = static_cast<int>(blockIdx.x) >> 3;
+    const int slice = kk % nsplit;
+    const int grp = (kk / nsplit) * 8 + static_cast<int>(blockIdx.x & 7);
+    const int n0 = slice * NB;
+    // LDS row 16 c + m holds output column colof(c, m) of the slice, m the
+    // MFMA column (lane l % 16) of subtile c = 0..7.  Hidden layers: column
+    // 8 m + c, so a lane's 8 BF16 results are one 16-byte store and the 16
+    // lanes of a row write 256 contiguous bytes.  Output layer (FP32): columns
+    // 4 m + c for c < 4 and 64 + 4 m + (c - 4) for c >= 4, so each of the two
+    // 16-byte stores per lane and row also covers 256 contiguous bytes.
+    auto colof = [](int c, int m) { return SPECTRUM ? (c < 4 ? 4 * m + c : 64 + 4 * m + (c - 4)) : 8 * m + c; };
     for (int e = tid; e < NB * (K / 8); e += 256) {
         const int rr = e / (K / 8), k8 = (e % (K / 8)) * 8;
-        const int col = 8 * (rr & 15) + (rr >> 4);
+        const int col = colof(rr >> 4, rr & 15);
         u32x4 v = {0u, 0u, 0u, 0u};
         if (n0 + col < a.N) v = *reinterpret_cast<const u32x4*>(a.W + static_cast<long long>(n0 + col) * K + k8);
         *reinterpret_cast<u32x4*>(&Ws[rr][k8]) = v;
     }
     __syncthreads();
     const int q = lane >> 4, rl = lane & 15;
-    const int nc = n0 + 8 * rl;                    // first of this lane's 8 output columns
+    const int nc = n0 + 8 * rl;                    // hidden layers: first of this lane's 8 output columns
     const int n_tiles = (a.M + TM - 1) / TM;
     auto load = [&](int t, auto& f) {
 #pragma unroll
@@ -548,24 +638,46 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
             }
         }
     };
-    // epilogue constants of this lane's 8 columns (output layer):
-    // j = A 2^(acc e_c + f_c), e_c = s_c log2(10), f_c = (b_c s_c + m_c) log2(10)
+    // epilogue constants of this lane's 8 columns, held in registers so that
+    // no load sits between the epilogue's stores (the memory counter is in
+    // order: a wait for such a load would also wait for every store before it)
+    // hidden layers: the biases; output layer: j = A 2^(acc e_c + f_c),
+    // e_c = s_c log2(10), f_c = (b_c s_c + m_c) log2(10), and the quadrature weights
+    float b8[SPECTRUM ? 1 : 8];
+    if constexpr (!SPECTRUM) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) b8[c] = a.bias[nc + c < a.N ? nc + c : a.N - 1];
+    }
     float e8[SPECTRUM ? 8 : 1], f8[SPECTRUM ? 8 : 1], w8[SPECTRUM ? 8 : 1];
     if constexpr (SPECTRUM) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int n = nc + c < a.N ? nc + c : a.N - 1;
+            const int nn = n0 + colof(c, rl);
+            const int n = nn < a.N ? nn : a.N - 1;
             e8[c] = a.ys[n] * 3.32192809488736235f;
             f8[c] = (a.bias[n] * a.ys[n] + a.ym[n]) * 3.32192809488736235f;
-            w8[c] = nc + c < a.N ? a.wq[n] : 0.f;
+            w8[c] = nn < a.N ? a.wq[n] : 0.f;
         }
     }
     // the next tile's inputs are loaded while this tile computes
-    u32x4 cur[G][NT][S], nxt[G][NT][S];
-    int t = blockIdx.y;
-    load(t, cur);
-    for (; t < n_tiles; t += gridDim.y) {
-        load(t + gridDim.y, nxt);
+    // one tile: computes from cur while the next tile's inputs load into nxt;
+    // the two buffers alternate roles (no register copies between tiles)
+    using Frag = u32x4[G][NT][S];
+    auto tile = [&](const int t, Frag& cur, Frag& nxt) {
+        // output layer: destination slot and absorbed power of this lane's 4
+        // rows, loaded before the prefetch so the epilogue waits only for them
+        int slot4[SPECTRUM ? 4 : 1];
+        float A4[SPECTRUM ? 4 : 1];
+        if constexpr (SPECTRUM) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = t * TM + wave * 16 + 4 * q + i;
+                const unsigned rc = static_cast<unsigned>(a.off0 + (r < a.M ? r : a.M - 1));
+                slot4[i] = a.sel[rc % static_cast<unsigned>(a.n_sel)];
+                A4[i] = static_cast<float>(a.Arow[r < a.M ? r : a.M - 1]);
+            }
+        }
+        load(t + ngrp, nxt);
         f32x4 acc[G][8];
 #pragma unroll
         for (int g = 0; g < G; ++g)
@@ -597,68 +709,79 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a) {
                 if constexpr (!SPECTRUM) {
                     constexpr int NO = SPLIT ? 2 : 1;             // output terms per activation
                     if (r < a.M) {
-                        float hv[8];
-                        unsigned short hb[8], lb[8];
+                        // BF16 pairs: hi terms, and the lo terms bf16(x - hi)
+                        unsigned ph[4], pl[4];
 #pragma unroll
-                        for (int c = 0; c < 8; ++c) {
-                            hv[c] = gelu(acc[g][c][i] + a.bias[nc + c < a.N ? nc + c : a.N - 1]);
-                            hb[c] = to_bf16(hv[c]);
-                            lb[c] = SPLIT ? to_bf16(hv[c] - from_bf16(hb[c])) : 0;
+                        for (int c = 0; c < 8; c += 2) {
+                            const float x0 = gelu(acc[g][c][i] + b8[c]);
+                            const float x1 = gelu(acc[g][c + 1][i] + b8[c + 1]);
+                            ph[c / 2] = pack_bf16(x0, x1);
+                            pl[c / 2] = SPLIT ? pack_bf16(x0 - __uint_as_float(ph[c / 2] << 16),
+                                                          x1 - __uint_as_float(ph[c / 2] & 0xFFFF0000u))
+                                              : 0u;
                         }
                         unsigned short* orow = a.out + r * (NO * a.N);
                         if (nc + 8 <= a.N) {
-                            auto pack8 = [](const unsigned short* v) {
-                                return u32x4{v[0] | (static_cast<unsigned>(v[1]) << 16),
-                                             v[2] | (static_cast<unsigned>(v[3]) << 16),
-                                             v[4] | (static_cast<unsigned>(v[5]) << 16),
-                                             v[6] | (static_cast<unsigned>(v[7]) << 16)};
-                            };
-                            *reinterpret_cast<u32x4*>(orow + nc) = pack8(hb);
-                            if constexpr (SPLIT) *reinterpret_cast<u32x4*>(orow + a.N + nc) = pack8(lb);
+                            *reinterpret_cast<u32x4*>(orow + nc) = u32x4{ph[0], ph[1], ph[2], ph[3]};
+                            if constexpr (SPLIT)
+                                *reinterpret_cast<u32x4*>(orow + a.N + nc) = u32x4{pl[0], pl[1], pl[2], pl[3]};
                         } else {
 #pragma unroll
                             for (int c = 0; c < 8; ++c)
                                 if (nc + c < a.N) {
-                                    orow[nc + c] = hb[c];
-                                    if constexpr (SPLIT) orow[a.N + nc + c] = lb[c];
+                                    orow[nc + c] = static_cast<unsigned short>(ph[c / 2] >> (16 * (c & 1)));
+                                    if constexpr (SPLIT)
+                                        orow[a.N + nc + c] = static_cast<unsigned short>(pl[c / 2] >> (16 * (c & 1)));
                                 }
                         }
                     }
                 } else {
                     float part = 0.f;
                     if (r < a.M) {
-                        const long long gr = a.row0 + r;
-                        const long long cell = gr / a.n_sel;
-                        const int slot = a.sel[static_cast<int>(gr - cell * a.n_sel)];
-                        float* jrow = a.j + (cell * a.n_slots + slot) * a.L;
-                        const float Ar = static_cast<float>(a.Arow[r]);
+                        const long long cell =
+                            a.cell0 + static_cast<unsigned>(a.off0 + static_cast<int>(r)) / static_cast<unsigned>(a.n_sel);
+                        float* jrow = a.j + (cell * a.n_slots + slot4[i]) * a.L;
+                        const float Ar = A4[i];
                         float jv[8];
 #pragma unroll
                         for (int c = 0; c < 8; ++c) {
-                            jv[c] = Ar * exp2f(fmaf(acc[g][c][i], e8[c], f8[c]));
+                            jv[c] = Ar * __builtin_amdgcn_exp2f(fmaf(acc[g][c][i], e8[c], f8[c]));
                             part += jv[c] * w8[c];
                         }
-                        if (nc + 8 <= a.N) {
-                            *reinterpret_cast<float4*>(jrow + nc) = make_float4(jv[0], jv[1], jv[2], jv[3]);
-                            *reinterpret_cast<float4*>(jrow + nc + 4) = make_float4(jv[4], jv[5], jv[6], jv[7]);
-                        } else {
+                        // columns n0 + 4 rl + 0..3 and n0 + 64 + 4 rl + 0..3
 #pragma unroll
-                            for (int c = 0; c < 8; ++c)
-                                if (nc + c < a.N) jrow[nc + c] = jv[c];
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const int cb = n0 + 64 * hh + 4 * rl;
+                            if (cb + 4 <= a.N) {
+                                float* dst = jrow + cb;
+                                if ((reinterpret_cast<size_t>(dst) & 15) == 0) {
+                                    *reinterpret_cast<float4*>(dst) =
+                                        make_float4(jv[4 * hh], jv[4 * hh + 1], jv[4 * hh + 2], jv[4 * hh + 3]);
+                                } else {
+#pragma unroll
+                                    for (int c = 0; c < 4; ++c) dst[c] = jv[4 * hh + c];
+                                }
+                            } else {
+#pragma unroll
+                                for (int c = 0; c < 4; ++c)
+                                    if (cb + c < a.N) jrow[cb + c] = jv[4 * hh + c];
+                            }
                         }
                     }
 #pragma unroll
                     for (int m = 1; m < 16; m <<= 1) part += __shfl_xor(part, m, 16);
-                    if (rl == 0 && r < a.M) atomicAdd(a.emit + r, part);
+                    if (rl == 0 && r < a.M) a.emit[static_cast<long long>(slice) * a.M + r] = part;
                 }
             }
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int h = 0; h < NT; ++h)
-#pragma unroll
-                for (int v = 0; v < S; ++v) cur[g][h][v] = nxt[g][h][v];
+    };
+    Frag b0, b1;
+    int t = grp;
+    load(t, b0);
+    for (; t < n_tiles; t += 2 * ngrp) {
+        tile(t, b0, b1);
+        if (t + ngrp >= n_tiles) break;
+        tile(t + ngrp, b1, b0);
     }
 }
 
@@ -770,12 +893,15 @@ hipError_t sur_wc(const Ctx& c, const double* const* cabs, int n_sel, double* wc
 }
 
 hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* wcT, const float* loga,
-                     long long row0, long long n_rows, int n_sel, float* X, double* A, hipStream_t st) {
+                     long long row0, long long n_rows, int n_sel, float* X, double* A, unsigned short* xb,
+                     const float* xm, const float* xs, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     const long long cell0 = row0 / n_sel;
     const long long cell1 = (row0 + n_rows - 1) / n_sel;
-    PairArgs p{u, bands, wcT, loga, row0, n_rows, cell0, cell1 - cell0 + 1, n_sel, c.L, X, A};
-    hipLaunchKernelGGL(k_pairs, dim3(static_cast<unsigned>((p.n_cells + 3) / 4)), dim3(256), 0, st, p);
+    PairArgs p{u, bands, wcT, loga, row0, n_rows, cell0, cell1 - cell0 + 1, n_sel, c.L, X, A, xb, xm, xs};
+    const dim3 grid(static_cast<unsigned>((p.n_cells + kPairCells - 1) / kPairCells),
+                    static_cast<unsigned>((n_sel + kPairSlots - 1) / kPairSlots));
+    hipLaunchKernelGGL(k_pairs, grid, dim3(256), 0, st, p);
     return hipGetLastError();
 }
 
@@ -951,26 +1077,26 @@ template <int K, bool SPEC, bool SPLIT>
 hipError_t dense(const DenseArgs& a, hipStream_t st) {
     const int nsplit = (a.N + 127) / 128;
     const int n_tiles = (a.M + (SPEC ? 63 : 127)) / (SPEC ? 64 : 128);
-    // two blocks per CU fit (LDS): spread them over the column slices
-    const int per_split = std::max(1, std::min(n_tiles, 512 / nsplit));
-    hipLaunchKernelGGL((k_dense<K, SPEC, SPLIT>), dim3(nsplit, per_split), dim3(256), 0, st, a);
+    // two blocks per CU fit (LDS): about 512 blocks over the column slices;
+    // row-tile groups in multiples of 8 (one per XCD, see the kernel)
+    const int ngrp = (std::max(1, std::min(n_tiles, 512 / nsplit)) + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_dense<K, SPEC, SPLIT>), dim3(nsplit * ngrp), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Inference of rows [row0, row0 + M) of a selection from raw inputs X [M][33]:
-// spectra scattered to j (pair rows) and 4 pi int j dlambda added to emit.
-// Workspaces: xb [M][96], h0 [M][512], h1 [M][256] BF16.
-hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long long row0, int n_sel, int n_slots,
-                          const int* sel, float* j, float* emit, unsigned short* xb, unsigned short* h0,
+// Inference of rows [row0, row0 + M) of a selection from the normalised
+// inputs xb [M][96] (hi and lo terms, as sur_pairs writes them): spectra
+// scattered to j (pair rows); emit[x][r] = 4 pi int j dlambda over the
+// wavelengths of column slice x (sur_emit_parts(L) slices of 128).
+// Workspaces: h0 [M][512], h1 [M][256] BF16.
+hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
+                          int n_slots, const int* sel, float* j, float* emit, unsigned short* h0,
                           unsigned short* h1, hipStream_t st) {
     if (M <= 0) return hipSuccess;
+    if (static_cast<long long>(M) + n_sel >= (1LL << 31)) return hipErrorInvalidValue;
     hipError_t e = sur_pack(s, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_norm_bf16, dim3(static_cast<unsigned>((static_cast<long long>(M) * 96 + 255) / 256)),
-                       dim3(256), 0, st, X, static_cast<long long>(M), s.xm, s.xs, xb);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned short* W1 = s.wb;
     const unsigned short* W2 = W1 + 256 * 96;
@@ -992,15 +1118,19 @@ hipError_t sur_infer_rows(Sur& s, int M, const float* X, const double* A, long l
     DenseArgs o{};
     o.in = h0; o.W = W4; o.bias = s.w + s.off_b[3]; o.M = M; o.N = s.L;
     o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit;
-    o.row0 = row0; o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
+    // M + n_sel < 2^31 (one chunk), so the row arithmetic fits 32 bits
+    o.cell0 = row0 / n_sel; o.off0 = static_cast<int>(row0 - o.cell0 * n_sel);
+    o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
     return dense<256, true, true>(o, st);
 }
 
-hipError_t sur_diag(const double* A, const float* emit, long long row0, long long n, int n_sel, int n_slots,
-                    const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
+int sur_emit_parts(int L) { return (L + 127) / 128; }
+
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, long long row0, long long n, int n_sel,
+                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, row0, n,
-                       n_sel, n_slots, sel, tol, diag, cnt);
+    hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, n_parts,
+                       row0, n, n_sel, n_slots, sel, tol, diag, cnt);
     return hipGetLastError();
 }
 
