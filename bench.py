@@ -159,13 +159,13 @@ def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
         X = torch.empty((n, 33), dtype=torch.float32, device="cuda:0")
         A = torch.empty((n,), dtype=torch.float64, device="cuda:0")
         ctx.hsd_sur_features(u, sel, X, A)
-        Y = torch.empty((n, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+        Y = torch.empty((n, ssur.n_outputs(w4.n_lambda)), dtype=torch.float32, device="cuda:0")
         ctx.hsd_sur_targets(j.view(n, w4.n_lambda), A, Y)
         ctx.hsd_sync()
         del j, u
         gen_s = time.perf_counter() - t0
         sur = hsd.Surrogate(ctx)
-        sur.hsd_sur_set_params(ssur.init_params(w4.n_lambda))
+        sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(w4.n_lambda)))
         sur.hsd_sur_fit_norm(X, Y)
         t0 = time.perf_counter()
         trace = sur.hsd_sur_train(X, Y, steps=steps, batch=batch, lr=lr)
@@ -177,16 +177,24 @@ def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
         uh = torch.tensor(make_fields(w4.lam_cm, w4.notes["heldout_recipe"], nh), device="cuda:0")
         jr = torch.empty((nh, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
         jp = torch.empty_like(jr)
-        ctx.hsd_solve(uh, sel, jr, None)
-        sur.hsd_sur_predict(uh, sel, jp, None)
+        dr = torch.empty((nh, G, 4), dtype=torch.float32, device="cuda:0")
+        dp = torch.empty_like(dr)
+        ctx.hsd_solve(uh, sel, jr, dr)
+        sur.hsd_sur_predict(uh, sel, jp, dp)
         ctx.hsd_sync()
         err = _band_error(jp.cpu().numpy().reshape(-1, w4.n_lambda), jr.cpu().numpy().reshape(-1, w4.n_lambda),
                           w4.lam_cm)
+        # the energy-ratio output against the plain model's emitted / absorbed
+        dr = dr.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        dp = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        rerr = np.abs((dp[:, 2] / dp[:, 0]) / (dr[:, 1] / dr[:, 0]) - 1)
         report[comp] = {"train_pairs": n, "heldout_pairs": nh * G, "steps": steps, "batch": batch,
                         "data_s": round(gen_s, 2), "train_s": round(train_s, 2),
                         "loss_first": float(np.mean(trace[:20])), "loss_last": float(np.mean(trace[-100:])),
                         "heldout_band_err": {"median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
-                                             "p99": float(np.quantile(err, 0.99)), "max": float(err.max())}}
+                                             "p99": float(np.quantile(err, 0.99)), "max": float(err.max())},
+                        "heldout_energy_ratio_err": {"median": float(np.median(rerr)),
+                                                     "p99": float(np.quantile(rerr, 0.99)), "max": float(rerr.max())}}
         log(f"{comp}: trained {steps} steps in {train_s:.1f} s; held-out band error median "
             f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}")
         nets[comp] = sur
@@ -212,7 +220,7 @@ def bench_surrogate(args):
                 "steps": args.train_steps, "warmup": 0, "ms_per_step": 1e3 * tot_s / (args.train_steps * len(report)),
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 matmul, f32 master",
                 "data": "synthetic", "config": {"workload": "c4_train", "train_pairs": tot_pairs,
-                                                "net": "33-256-256-256-500 GELU"},
+                                                "net": "33-256-256-256-501 GELU"},
                 "per_composition": report}
         print(json.dumps(line))
         return
@@ -242,8 +250,19 @@ def bench_surrogate(args):
     log(f"plain: {t_plain * 1e3:.1f} ms per step")
     jsu = torch.empty_like(jpl)
     dsu = torch.empty_like(dpl)
-    t_sur, nfb = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=0.01, stream=stream), args.steps)
-    log(f"surrogate + fallback: {t_sur * 1e3:.1f} ms per step, {nfb} fallback pairs")
+    # the check against the absorbed power itself first (its results are not kept)
+    t_abs, nfb_abs = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=0.01, check=hsd.CHECK_ABSORBED,
+                                                           stream=stream), 1)
+    log(f"surrogate + fallback, check against A: {t_abs * 1e3:.1f} ms, {nfb_abs} fallback pairs")
+    n_pairs = w5.n_cells * G
+    rng = np.random.default_rng(4627005)
+    samp = np.sort(rng.choice(n_pairs, n_pairs // 100, replace=False))
+    idx = torch.tensor(samp, device="cuda:0")
+    jr = jpl.view(n_pairs, -1).index_select(0, idx).cpu().numpy()
+    e_abs = _band_error(jsu.view(n_pairs, -1).index_select(0, idx).cpu().numpy(), jr, w5.lam_cm)
+    t_sur, nfb = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=0.01, check=hsd.CHECK_MODEL,
+                                                       stream=stream), args.steps)
+    log(f"surrogate + fallback, check against the model's budget: {t_sur * 1e3:.1f} ms per step, {nfb} fallback pairs")
     # the network alone (every pair), timed with HIP events around its kernels
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     carb = [i for i, g in zip(ids, w5.grains) if g.composition == "carbonaceous"]
@@ -257,12 +276,7 @@ def bench_surrogate(args):
     t_net = ev0.elapsed_time(ev1) * 1e-3
     del jn
     # accuracy on a seeded 1% sample of the pairs, against the plain GPU solve
-    n_pairs = w5.n_cells * G
-    rng = np.random.default_rng(4627005)
-    samp = np.sort(rng.choice(n_pairs, n_pairs // 100, replace=False))
-    idx = torch.tensor(samp, device="cuda:0")
     jp = jsu.view(n_pairs, -1).index_select(0, idx).cpu().numpy()
-    jr = jpl.view(n_pairs, -1).index_select(0, idx).cpu().numpy()
     err = _band_error(jp, jr, w5.lam_cm)
     flags = dsu.view(n_pairs, 4)[:, 3].index_select(0, idx).cpu().numpy().astype(np.int64)
     by_sur = (flags & 8) != 0
@@ -271,7 +285,8 @@ def bench_surrogate(args):
     # the tolerance trade-off: fewer fallbacks, larger errors
     sweep = []
     for tol in (0.02, 0.05):
-        t_tol, nfb_tol = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=tol, stream=stream), 1)
+        t_tol, nfb_tol = timed(lambda: ctx.hsd_solve_surrogate(u, ids, surs, jsu, dsu, tol=tol, check=hsd.CHECK_MODEL,
+                                                               stream=stream), 1)
         e_tol = _band_error(jsu.view(n_pairs, -1).index_select(0, idx).cpu().numpy(), jr, w5.lam_cm)
         sweep.append({"tol": tol, "solves_per_s": n_pairs / t_tol, "speedup_vs_plain": t_plain / t_tol,
                       "fallback_fraction": nfb_tol / n_pairs, "sample_band_error_max": float(e_tol.max()),
@@ -283,9 +298,13 @@ def bench_surrogate(args):
             "warmup": 1, "ms_per_step": t_sur * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "bf16 matmul + f32/f64 fallback", "data": "synthetic",
             "config": {"workload": "c5_surrogate", "cells": w5.n_cells, "grains": G, "n_lambda": w5.n_lambda,
-                       "tol": 0.01},
+                       "tol": 0.01, "check": "emitted vs the predicted absorbed power of the plain model"},
             "plain_solves_per_s": n_pairs / t_plain, "speedup_vs_plain": t_plain / t_sur,
             "fallback_fraction": nfb / n_pairs,
+            "check_against_absorbed": {"tol": 0.01, "solves_per_s": n_pairs / t_abs,
+                                       "speedup_vs_plain": t_plain / t_abs, "fallback_fraction": nfb_abs / n_pairs,
+                                       "sample_band_error_max": float(e_abs.max()),
+                                       "sample_band_error_p99": float(np.quantile(e_abs, 0.99))},
             "sample_band_error": {"pairs": int(samp.shape[0]), "max": float(err.max()),
                                   "p99": float(np.quantile(err, 0.99)), "median": float(np.median(err)),
                                   "max_surrogate_pairs": float(err[by_sur].max()) if by_sur.any() else 0.0,

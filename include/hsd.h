@@ -258,16 +258,23 @@ void hsd_plan_destroy(hsd_plan* plan);
  *            the wavelength grid (band b spans the grid nodes
  *            floor(b (L-1) / 32) .. floor((b+1) (L-1) / 32), trapezoid rule),
  *            then log10 of the grain radius in cm;
- *   outputs  y [L]: log10(j_lambda / A), A = int c u C_abs dlambda the pair's
- *            absorbed power (trapezoid); training targets are
- *            log10(max(j, 1e-6 max j) / A) from the plain solve;
- *   network  33 -> 256 -> 256 -> 256 -> L, GELU (x Phi(x)) after each hidden
- *            layer; inputs z-scored per column, targets centred per column
- *            and divided by one pooled standard deviation (statistics of the
- *            training set); every matrix product rounds its operands to
- *            bfloat16 and accumulates in FP32; master weights FP32.
+ *   outputs  y [L + 1]: y_lambda = log10(j_lambda / A) for the L wavelengths,
+ *            A = int c u C_abs dlambda the pair's absorbed power
+ *            (trapezoid), then y_L = log10(E / A), E = 4 pi int j dlambda
+ *            the emitted power on the grid: the discrete model's own energy
+ *            budget, which misses 1 for coarse enthalpy bins (transitions
+ *            whose photon energy lies beyond the grid's short end carry no
+ *            rate);  training targets are log10(max(j, 1e-6 max j) / A) and
+ *            log10(E / A) of the plain solve;
+ *   network  33 -> 256 -> 256 -> 256 -> L + 1, GELU (x Phi(x)) after each
+ *            hidden layer; inputs z-scored per column, targets centred per
+ *            column, the L spectrum columns divided by one pooled standard
+ *            deviation and the ratio column by ten times its own
+ *            (statistics of the training set); every matrix product rounds its operands to
+ *            bfloat16 (the inputs of the first and last layer as two terms,
+ *            hi + lo) and accumulates in FP32; master weights FP32.
  * Parameters are one FP32 vector, layer by layer: W_l row-major [out][in],
- * then b_l (268,788 values for L = 500).  Rows of X_dev / Y_dev / A_dev are
+ * then b_l (269,045 values for L = 500).  Rows of X_dev / Y_dev / A_dev are
  * pairs in the order r = cell * n_grains + g. */
 typedef struct hsd_sur hsd_sur;
 hsd_status hsd_sur_create(hsd_ctx* ctx, hsd_sur** out);   /* weights uninitialised: set them */
@@ -277,7 +284,7 @@ hsd_status hsd_sur_n_params(hsd_sur* sur, int64_t* n_params_host);
 hsd_status hsd_sur_set_params(hsd_sur* sur, const float* params_host);
 hsd_status hsd_sur_get_params(hsd_sur* sur, float* params_host);
 /* Column means and standard deviations (> 0) of raw inputs [33] and targets
- * [L].  Synchronous. */
+ * [L + 1].  Synchronous. */
 hsd_status hsd_sur_set_norm(hsd_sur* sur, const double* x_mean_host, const double* x_std_host,
                             const double* y_mean_host, const double* y_std_host);
 hsd_status hsd_sur_get_norm(hsd_sur* sur, double* x_mean_host, double* x_std_host, double* y_mean_host,
@@ -287,13 +294,14 @@ hsd_status hsd_sur_get_norm(hsd_sur* sur, double* x_mean_host, double* x_std_hos
  * Grains need radius_cm > 0.  Asynchronous on `stream`. */
 hsd_status hsd_sur_features(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
                             const int32_t* grain_ids_host, float* X_dev, double* A_dev, void* stream);
-/* Raw targets Y_dev [n][L] from spectra j_dev [n][L] and absorbed powers
- * A_dev [n].  Asynchronous on `stream`. */
+/* Raw targets Y_dev [n][L + 1] from spectra j_dev [n][L] and absorbed
+ * powers A_dev [n].  Asynchronous on `stream`. */
 hsd_status hsd_sur_targets(hsd_ctx* ctx, int64_t n, const float* j_dev, const double* A_dev, float* Y_dev,
                            void* stream);
 /* Statistics of a training set (FP64 column sums on the device): input
- * column means and standard deviations, target column means and the pooled
- * target standard deviation (sqrt of the mean column variance, repeated),
+ * column means and standard deviations, target column means, the pooled
+ * standard deviation of the L spectrum columns (sqrt of their mean variance,
+ * repeated) and ten times that of the ratio column (a smaller loss weight),
  * stored as by hsd_sur_set_norm.  Synchronous. */
 hsd_status hsd_sur_fit_norm(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev);
 /* Test hook: mean squared error over the n rows (normalised targets) and
@@ -309,23 +317,35 @@ hsd_status hsd_sur_loss_grad(hsd_sur* sur, int32_t n, const float* X_dev, const 
  * hsd_sur_set_params.  Synchronous. */
 hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps,
                          int32_t batch, float lr, uint64_t seed, float* loss_host);
+/* Energy checks of hsd_solve_surrogate.  With E the surrogate's emitted
+ * power (4 pi int j dlambda on the grid) and A the pair's absorbed power:
+ *   HSD_CHECK_ABSORBED  flag the pair when |E / A - 1| > tol;
+ *   HSD_CHECK_MODEL     flag it when |E / (rho A) - 1| > tol, rho = 10^y_L
+ *                       the network's prediction of the plain model's own
+ *                       ratio E / A: the spectrum must carry the power the
+ *                       discrete model absorbs. */
+#define HSD_CHECK_ABSORBED 0
+#define HSD_CHECK_MODEL 1
 /* Surrogate spectra of every (cell, grain) pair: j_dev as in hsd_solve;
- * diag_dev (optional) = (A, 4 pi int j dlambda, A, flags) with flags bit 3
- * set (value from the surrogate) and bit 4 set where |emitted / A - 1| >
- * 0.01.  Asynchronous on `stream` (grows workspace). */
+ * diag_dev (optional) = (A, 4 pi int j dlambda, rho A, flags) with flags
+ * bit 3 set (value from the surrogate) and bit 4 set where the
+ * HSD_CHECK_MODEL test with tol = 0.01 fails.  Asynchronous on `stream`
+ * (grows workspace). */
 hsd_status hsd_sur_predict(hsd_sur* sur, int32_t n_cells, const double* u_dev, int32_t n_grains,
                            const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream);
 /* The surrogate with the plain solve as fallback: every pair is first
  * evaluated by the network surs_host[g] of its grain (one network may serve
- * several grains); a pair whose emitted power misses its absorbed power by
- * more than tol (relative; the energy balance of eq:steady-state) is
- * re-solved by the plain path, in place.  j_dev and diag_dev as in
- * hsd_solve; surrogate pairs carry diag flag bit 3, re-solved pairs carry the
- * plain solve's flags.  *n_fallback_host receives the number of re-solved
- * pairs.  Waits for the stream once (to size the fallback). */
+ * several grains); a pair that fails the energy check `check`
+ * (HSD_CHECK_ABSORBED or HSD_CHECK_MODEL, relative tolerance tol; the
+ * energy balance of eq:steady-state) is re-solved by the plain path, in
+ * place.  j_dev and diag_dev as in hsd_solve; surrogate pairs carry diag
+ * flag bit 3 and entry 2 = the power the check compares with (A or rho A),
+ * re-solved pairs carry the plain solve's diagnostics.  *n_fallback_host
+ * receives the number of re-solved pairs.  Waits for the stream once (to
+ * size the fallback). */
 hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
-                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, float* j_dev,
-                               float* diag_dev, int64_t* n_fallback_host, void* stream);
+                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, int32_t check,
+                               float* j_dev, float* diag_dev, int64_t* n_fallback_host, void* stream);
 
 #ifdef __cplusplus
 }

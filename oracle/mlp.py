@@ -11,10 +11,14 @@ inference kernel compute, so that their gradients and outputs can be checked:
   band b spans grid nodes floor(b (L-1) / 32) .. floor((b+1) (L-1) / 32) and
   its energy is the trapezoid integral of u over those nodes;
 * targets: y_lambda = log10(max(j_lambda, 1e-6 max j) / A), A the absorbed
-  power of the pair on the grid (trapezoid of c u C_abs);
-* the network: widths (33, 256, 256, 256, L), GELU (erf form) after every
-  hidden layer; inputs z-scored per column, targets centred per column and
-  scaled by one pooled standard deviation;
+  power of the pair on the grid (trapezoid of c u C_abs), then one more
+  output y_L = log10(E / A), E = 4 pi int j dlambda (trapezoid) the emitted
+  power: the plain model's own energy ratio (below 1 where coarse enthalpy
+  bins leave photons near the grid's short end without a transition);
+* the network: widths (33, 256, 256, 256, L + 1), GELU (erf form) after
+  every hidden layer; inputs z-scored per column, targets centred per column,
+  the L spectrum columns scaled by one pooled standard deviation and the
+  ratio column by RATIO_SCALE times its own (a smaller weight in the loss);
 * loss: mean squared error over samples and outputs; Adam updates;
 * the accuracy metric: band-integrated j over the same 32 bands, relative
   error over the bands holding at least 1e-3 of the pair's emitted power.
@@ -41,6 +45,8 @@ N_BANDS = 32
 SQRT2 = math.sqrt(2.0)
 # forward layers whose input operand is split into two bfloat16 terms
 SPLIT_LAYERS = (0, 3)
+# scale of the energy-ratio target, in units of its own standard deviation
+RATIO_SCALE = 10.0
 
 
 # ---- features, targets, metric -------------------------------------------------
@@ -65,10 +71,32 @@ def features(u: np.ndarray, lam: np.ndarray, radius_cm: float) -> np.ndarray:
     return np.concatenate([x, a], axis=-1)
 
 
-def targets(j: np.ndarray, absorbed) -> np.ndarray:
+def emitted_power(j: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """4 pi int j dlambda over the grid (trapezoid): (...,)."""
+    return 4.0 * math.pi * np.trapezoid(np.asarray(j, dtype=np.float64), lam, axis=-1)
+
+
+def targets(j: np.ndarray, absorbed, lam: np.ndarray) -> np.ndarray:
+    """Raw targets (..., L + 1): the floored log spectrum per absorbed power,
+    then log10 of emitted over absorbed power."""
     j = np.asarray(j, dtype=np.float64)
+    a = np.asarray(absorbed, dtype=np.float64)
     floor = 1e-6 * j.max(axis=-1, keepdims=True)
-    return np.log10(np.maximum(j, floor) / np.asarray(absorbed, dtype=np.float64)[..., None])
+    spec = np.log10(np.maximum(j, floor) / a[..., None])
+    ratio = np.log10(emitted_power(j, lam) / a)
+    return np.concatenate([spec, ratio[..., None]], axis=-1)
+
+
+def target_stats(Y: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Target normalisation of a training set Y [n, L + 1]: column means;
+    one pooled standard deviation (root mean column variance) for the L
+    spectrum columns, RATIO_SCALE times the ratio column's own for the last."""
+    mu, sd = zscore_stats(Y)
+    L = Y.shape[1] - 1
+    s = sd.copy()
+    s[:L] = math.sqrt(float(np.mean(sd[:L] ** 2)))
+    s[L] *= RATIO_SCALE
+    return mu, s
 
 
 def band_rel_error(j: np.ndarray, jref: np.ndarray, lam: np.ndarray, min_share: float = 1e-3) -> np.ndarray:

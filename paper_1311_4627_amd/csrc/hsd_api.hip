@@ -28,6 +28,7 @@ struct SurWork {
     float* bands = nullptr;       size_t bands_cap = 0;
     double* A = nullptr;          size_t A_cap = 0;
     float* emit = nullptr;        size_t emit_cap = 0;    // emitted-power partials [column slice][chunk]
+    float* rho = nullptr;         size_t rho_cap = 0;     // predicted energy ratios [chunk]
     unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs, hi and lo [chunk][96]
     unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][512] (hi, lo)
     unsigned short* h1 = nullptr; size_t h1_cap = 0;
@@ -367,7 +368,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.queue);
     hipFree(c.sizew);
     SurWork& w = ctx->sw;
-    hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.rho); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);
@@ -792,7 +793,8 @@ hsd_status hsd_sur_create(hsd_ctx* ctx, hsd_sur** out) {
     p->ctx = ctx;
     p->s.c = &ctx->c;
     p->s.L = ctx->c.L;
-    p->s.widths[4] = ctx->c.L;
+    p->s.n_out = ctx->c.L + 1;
+    p->s.widths[4] = p->s.n_out;
     const hipError_t e = hsd::sur_alloc(p->s);
     if (e != hipSuccess) {
         hsd::sur_free(p->s);
@@ -848,7 +850,7 @@ hsd_status hsd_sur_set_norm(hsd_sur* p, const double* x_mean, const double* x_st
     if (!p) return HSD_ERR_INVALID_ARG;
     hsd_ctx* ctx = p->ctx;
     if (!x_mean || !x_std || !y_mean || !y_std) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
-    const int L = p->s.L;
+    const int L = p->s.n_out;
     std::vector<float> a(33), b(33), c(L), d(L);
     for (int k = 0; k < 33; ++k) {
         if (!(x_std[k] > 0.0) || !std::isfinite(x_mean[k])) return fail(ctx, HSD_ERR_INVALID_ARG, "bad input statistics");
@@ -874,7 +876,7 @@ hsd_status hsd_sur_get_norm(hsd_sur* p, double* x_mean, double* x_std, double* y
     hsd_ctx* ctx = p->ctx;
     if (!x_mean || !x_std || !y_mean || !y_std) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
     if (!p->s.have_norm) return fail(ctx, HSD_ERR_STATE, "no statistics set");
-    const int L = p->s.L;
+    const int L = p->s.n_out;
     std::vector<float> a(33), b(33), c(L), d(L);
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
     HSD_HIP(ctx, hipMemcpy(a.data(), p->s.xm, sizeof(float) * 33, hipMemcpyDeviceToHost));
@@ -924,9 +926,11 @@ hsd_status sur_select(hsd_ctx* ctx, const std::vector<int>& slots, const int32_t
 constexpr long long kSurChunk = 262144;   // pair rows per inference chunk
 
 // Surrogate spectra of every (cell, slot) pair of `slots` into j, with diag
-// entries and the energy-balance flags (bit 4) counted in sw.cnt.
+// entries and the energy-balance flags (bit 4, check HSD_CHECK_*) counted in
+// sw.cnt.
 hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u, int32_t n_grains,
-                   const int32_t* ids, const std::vector<int>& slots, float tol, float* j, float* diag, hipStream_t s) {
+                   const int32_t* ids, const std::vector<int>& slots, float tol, int check, float* j, float* diag,
+                   hipStream_t s) {
     Ctx& c = ctx->c;
     SurWork& w = ctx->sw;
     if (!sur.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
@@ -936,8 +940,9 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
     const long long rows = static_cast<long long>(n_cells) * n_sel;
     const size_t ch = static_cast<size_t>(std::min(rows, kSurChunk));
     HSD_HIP(ctx, grow(w.A, w.A_cap, ch));
-    const int n_parts = hsd::sur_emit_parts(c.L);
+    const int n_parts = hsd::sur_emit_parts(sur.n_out);
     HSD_HIP(ctx, grow(w.emit, w.emit_cap, ch * n_parts));
+    HSD_HIP(ctx, grow(w.rho, w.rho_cap, ch));
     HSD_HIP(ctx, grow(w.xb, w.xb_cap, ch * 96));
     HSD_HIP(ctx, grow(w.h0, w.h0_cap, ch * 512));
     HSD_HIP(ctx, grow(w.h1, w.h1_cap, ch * 256));
@@ -946,9 +951,10 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
         HSD_HIP(ctx, hsd::sur_pairs(c, u, w.bands, w.wcT, w.loga, r0, n, n_sel, nullptr, w.A, w.xb, sur.xm, sur.xs,
                                     s));
         HSD_HIP(ctx, hsd::sur_infer_rows(sur, static_cast<int>(n), w.xb, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
-                                         w.h0, w.h1, s));
+                                         w.rho, w.h0, w.h1, s));
         if (diag)
-            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, r0, n, n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
+            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, check == HSD_CHECK_MODEL ? w.rho : nullptr, r0, n,
+                                       n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
     }
     return HSD_OK;
 }
@@ -987,7 +993,7 @@ hsd_status hsd_sur_targets(hsd_ctx* ctx, int64_t n, const float* j_dev, const do
     if (n == 0) return HSD_OK;
     if (!j_dev || !A_dev || !Y_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
-    HSD_HIP(ctx, hsd::sur_targets(j_dev, A_dev, n, ctx->c.L, Y_dev, static_cast<hipStream_t>(stream)));
+    HSD_HIP(ctx, hsd::sur_targets(j_dev, A_dev, ctx->c.lam, n, ctx->c.L, Y_dev, static_cast<hipStream_t>(stream)));
     return HSD_OK;
 }
 
@@ -999,13 +1005,17 @@ hsd_status hsd_sur_fit_norm(hsd_sur* p, int64_t n, const float* X_dev, const flo
     HSD_HIP(ctx, hipDeviceSynchronize());
     std::vector<double> xm, xs, ym, ys;
     HSD_HIP(ctx, hsd::sur_colstats(X_dev, n, 33, xm, xs));
-    HSD_HIP(ctx, hsd::sur_colstats(Y_dev, n, p->s.L, ym, ys));
-    // targets: one pooled standard deviation for every wavelength
+    HSD_HIP(ctx, hsd::sur_colstats(Y_dev, n, p->s.n_out, ym, ys));
+    // spectrum targets: one pooled standard deviation for every wavelength;
+    // the energy-ratio target: kRatioScale times its own (a smaller weight in
+    // the loss, so that the ratio does not take the spectrum's capacity)
+    const int L = p->s.L;
     double pooled = 0.0;
-    for (double v : ys) pooled += v * v;
-    pooled = std::sqrt(pooled / ys.size());
+    for (int k = 0; k < L; ++k) pooled += ys[k] * ys[k];
+    pooled = std::sqrt(pooled / L);
     if (!(pooled > 0.0)) pooled = 1.0;
-    std::fill(ys.begin(), ys.end(), pooled);
+    std::fill(ys.begin(), ys.begin() + L, pooled);
+    ys[L] *= hsd::kRatioScale;
     return hsd_sur_set_norm(p, xm.data(), xs.data(), ym.data(), ys.data());
 }
 
@@ -1028,7 +1038,7 @@ hsd_status hsd_sur_loss_grad(hsd_sur* p, int32_t n, const float* X_dev, const fl
     HSD_HIP(ctx, hipDeviceSynchronize());
     double l = 0.0;
     HSD_HIP(ctx, hipMemcpy(&l, s.loss, sizeof(double), hipMemcpyDeviceToHost));
-    *loss_host = l / (static_cast<double>(n) * s.L);
+    *loss_host = l / (static_cast<double>(n) * s.n_out);
     if (grad_host) HSD_HIP(ctx, hipMemcpy(grad_host, s.g, sizeof(float) * s.n_params, hipMemcpyDeviceToHost));
     return HSD_OK;
 }
@@ -1066,7 +1076,7 @@ hsd_status hsd_sur_train(hsd_sur* p, int64_t n, const float* X_dev, const float*
     if (e == hipSuccess && trace) {
         std::vector<double> h(steps);
         e = hipMemcpy(h.data(), trace, sizeof(double) * steps, hipMemcpyDeviceToHost);
-        for (int k = 0; k < steps; ++k) loss_host[k] = static_cast<float>(h[k] / (static_cast<double>(batch) * s.L));
+        for (int k = 0; k < steps; ++k) loss_host[k] = static_cast<float>(h[k] / (static_cast<double>(batch) * s.n_out));
     }
     if (trace) (void)hipFree(trace);
     if (e != hipSuccess) return hip_fail(ctx, e, "hsd_sur_train");
@@ -1092,12 +1102,13 @@ hsd_status hsd_sur_predict(hsd_sur* p, int32_t n_cells, const double* u_dev, int
     HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
     std::vector<int> slots(n_grains);
     for (int g = 0; g < n_grains; ++g) slots[g] = g;
-    return sur_run(ctx, p->s, n_cells, u_dev, n_grains, grain_ids_host, slots, 0.01f, j_dev, diag_dev, s);
+    return sur_run(ctx, p->s, n_cells, u_dev, n_grains, grain_ids_host, slots, 0.01f, HSD_CHECK_MODEL, j_dev,
+                   diag_dev, s);
 }
 
 hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
-                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, float* j_dev,
-                               float* diag_dev, int64_t* n_fallback_host, void* stream) {
+                               const int32_t* grain_ids_host, hsd_sur* const* surs_host, float tol, int32_t check,
+                               float* j_dev, float* diag_dev, int64_t* n_fallback_host, void* stream) {
     if (!ctx) return HSD_ERR_INVALID_ARG;
     if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
     if (!n_fallback_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null fallback count");
@@ -1106,6 +1117,8 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     if (!u_dev || !grain_ids_host || !surs_host || !j_dev || !diag_dev)
         return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
     if (!(tol >= 0.f)) return fail(ctx, HSD_ERR_INVALID_ARG, "tol must be >= 0");
+    if (check != HSD_CHECK_ABSORBED && check != HSD_CHECK_MODEL)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "check must be HSD_CHECK_ABSORBED or HSD_CHECK_MODEL");
     for (int g = 0; g < n_grains; ++g) {
         if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
         if (!surs_host[g] || surs_host[g]->ctx != ctx) return fail(ctx, HSD_ERR_INVALID_ARG, "missing or foreign surrogate");
@@ -1126,7 +1139,7 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
         std::vector<int> slots;
         for (int g = 0; g < n_grains; ++g)
             if (surs_host[g] == net) slots.push_back(g);
-        const hsd_status st = sur_run(ctx, net->s, n_cells, u_dev, n_grains, grain_ids_host, slots, tol, j_dev,
+        const hsd_status st = sur_run(ctx, net->s, n_cells, u_dev, n_grains, grain_ids_host, slots, tol, check, j_dev,
                                       diag_dev, s);
         if (st != HSD_OK) return st;
     }

@@ -180,9 +180,13 @@ hipError_t launch_sizedist(const float* j, const double* w, const double* lam, i
 // bf16(x) and lo = bf16(x - hi) (about 16 significant bits): the normalised
 // features (the network's input) and the last hidden activations.
 constexpr int kSplitIn[4] = {1, 0, 0, 1};
+// Normalisation scale of the energy-ratio output, in units of its standard
+// deviation over the training set.
+constexpr double kRatioScale = 10.0;
 struct Sur {
     Ctx* c = nullptr;
-    int L = 0;
+    int L = 0;                 // wavelengths of the spectrum
+    int n_out = 0;             // network outputs: L spectrum values, then the energy ratio
     int widths[5] = {33, 256, 256, 256, 0};
     long long n_params = 0;
     long long off_W[4] = {}, off_b[4] = {};
@@ -193,9 +197,9 @@ struct Sur {
     long long t = 0;           // Adam steps taken
     float* xm = nullptr;       // [33] input means / stds
     float* xs = nullptr;
-    float* ym = nullptr;       // [L] target means / stds
+    float* ym = nullptr;       // [n_out] target means / stds
     float* ys = nullptr;
-    float* wq = nullptr;       // [L] 4 pi x trapezoid weights
+    float* wq = nullptr;       // [n_out] 4 pi x trapezoid weights (0 for the ratio output)
     bool have_norm = false;
     // training workspace (grown on demand)
     int cap_B = 0;
@@ -217,7 +221,8 @@ hipError_t sur_wc(const Ctx& c, const double* const* cabs, int n_sel, double* wc
 hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const double* wcT, const float* loga,
                      long long row0, long long n_rows, int n_sel, float* X, double* A, unsigned short* xb,
                      const float* xm, const float* xs, hipStream_t st);
-hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st);
+hipError_t sur_targets(const float* j, const double* A, const double* lam, long long n, int L, float* Y,
+                       hipStream_t st);
 hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd);
 hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep_z);
 hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st);
@@ -228,11 +233,11 @@ hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
 hipError_t sur_pack(Sur& s, hipStream_t st);
 hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
-                          int n_slots, const int* sel, float* j, float* emit, unsigned short* h0,
+                          int n_slots, const int* sel, float* j, float* emit, float* rho, unsigned short* h0,
                           unsigned short* h1, hipStream_t st);
-int sur_emit_parts(int L);
-hipError_t sur_diag(const double* A, const float* emit, int n_parts, long long row0, long long n, int n_sel,
-                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
+int sur_emit_parts(int n_out);
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
+                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
 hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,
                           int* cellmap, long long* pairs, hipStream_t st);
 

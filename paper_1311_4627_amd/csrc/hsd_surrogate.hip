@@ -218,20 +218,31 @@ __global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
     }
 }
 
-// Raw targets from spectra: one wave per row.
-__global__ void __launch_bounds__(256) k_targets(const float* j, const double* A, long long n, int L, float* Y) {
+// Raw targets from spectra, one wave per row: Y[r][k] = log10(max(j, 1e-6
+// max j) / A) for the L wavelengths, Y[r][L] = log10(4 pi int j dlambda / A)
+// (trapezoid, FP64 sums).
+__global__ void __launch_bounds__(256) k_targets(const float* j, const double* A, const double* lam, long long n,
+                                                 int L, float* Y) {
     const int lane = threadIdx.x & 63;
     const long long r = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (r >= n) return;
     const float* jr = j + r * L;
     float mx = 0.f;
-    for (int k = lane; k < L; k += 64) mx = fmaxf(mx, jr[k]);
+    double em = 0.0;
+    for (int k = lane; k < L; k += 64) {
+        mx = fmaxf(mx, jr[k]);
+        if (k + 1 < L) em += 0.5 * (lam[k + 1] - lam[k]) * (static_cast<double>(jr[k]) + jr[k + 1]);
+    }
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+    for (int m = 1; m < 64; m <<= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+        em += __shfl_xor(em, m, 64);
+    }
     const double fl = 1e-6 * static_cast<double>(mx);
     const double a = A[r];
-    for (int k = lane; k < L; k += 64)
-        Y[r * L + k] = static_cast<float>(log10(fmax(static_cast<double>(jr[k]), fl) / a));
+    float* yr = Y + r * (L + 1);
+    for (int k = lane; k < L; k += 64) yr[k] = static_cast<float>(log10(fmax(static_cast<double>(jr[k]), fl) / a));
+    if (lane == 0) yr[L] = static_cast<float>(log10(4.0 * kPi * em / a));
 }
 
 // Column sums and sums of squares in FP64 (one thread per column, blocks of
@@ -487,27 +498,30 @@ hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
 }
 
 // Per-pair diagnostics of surrogate rows and the energy-balance check: diag =
-// (A, 4 pi int j dlambda, A, flags) with flags bit 3 (value from the surrogate)
-// and bit 4 (|emitted / A - 1| > tol: the pair goes to the plain solve);
+// (A, 4 pi int j dlambda, R, flags) with R = A, or R = rho A when the
+// predicted energy ratios rho are given, flags bit 3 (value from the
+// surrogate) and bit 4 (|emitted / R - 1| > tol: the pair goes to the plain
+// solve);
 // cnt[slot] and cnt[n_slots] count the flagged pairs.  The emitted power is
 // the sum of the n_parts column-slice partials emit[x][r], in slice order (a
 // fixed order, so the check decides the same way on every run).
-__global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, int n_parts, long long row0,
-                                                  long long n, int n_sel, int n_slots, const int* sel, float tol,
-                                                  float* diag, unsigned* cnt) {
+__global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, int n_parts, const float* rho,
+                                                  long long row0, long long n, int n_sel, int n_slots, const int* sel,
+                                                  float tol, float* diag, unsigned* cnt) {
     const long long r = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (r >= n) return;
     const long long rg = row0 + r;
     const long long cell = rg / n_sel;
     const int slot = sel[static_cast<int>(rg - cell * n_sel)];
     const double a = A[r];
+    const double ref = rho ? a * static_cast<double>(rho[r]) : a;
     float e = 0.f;
     for (int x = 0; x < n_parts; ++x) e += emit[x * n + r];
-    const bool bad = !(fabs(static_cast<double>(e) / a - 1.0) <= tol);
+    const bool bad = !(fabs(static_cast<double>(e) / ref - 1.0) <= tol);
     float* d = diag + (cell * n_slots + slot) * 4;
     d[0] = static_cast<float>(a);
     d[1] = e;
-    d[2] = static_cast<float>(a);
+    d[2] = static_cast<float>(ref);
     d[3] = bad ? 24.f : 8.f;
     if (bad) {
         atomicAdd(cnt + slot, 1u);
@@ -566,9 +580,10 @@ struct DenseArgs {
     int M, N;
     unsigned short* out;        // hidden: [M][N] bf16
     // spectrum epilogue
-    float* j; int L;
+    float* j; int L;            // spectrum rows of L; output column L is the energy ratio
     const float* ym; const float* ys;
     const double* Arow; const float* wq; float* emit;
+    float* rho;                 // [M] predicted energy ratio 10^y_L
     long long cell0; int off0;  // row r is selection entry (off0 + r) of cells from cell0 on
     int n_sel, n_slots; const int* sel;
 };
@@ -748,11 +763,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                             jv[c] = Ar * __builtin_amdgcn_exp2f(fmaf(acc[g][c][i], e8[c], f8[c]));
                             part += jv[c] * w8[c];
                         }
-                        // columns n0 + 4 rl + 0..3 and n0 + 64 + 4 rl + 0..3
+                        // columns n0 + 4 rl + 0..3 and n0 + 64 + 4 rl + 0..3: the
+                        // spectrum below L, the energy ratio at L
 #pragma unroll
                         for (int hh = 0; hh < 2; ++hh) {
                             const int cb = n0 + 64 * hh + 4 * rl;
-                            if (cb + 4 <= a.N) {
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if (cb + c == a.L)
+                                    a.rho[r] = __builtin_amdgcn_exp2f(
+                                        fmaf(acc[g][4 * hh + c][i], e8[4 * hh + c], f8[4 * hh + c]));
+                            if (cb + 4 <= a.L) {
                                 float* dst = jrow + cb;
                                 if ((reinterpret_cast<size_t>(dst) & 15) == 0) {
                                     *reinterpret_cast<float4*>(dst) =
@@ -764,7 +785,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                             } else {
 #pragma unroll
                                 for (int c = 0; c < 4; ++c)
-                                    if (cb + c < a.N) jrow[cb + c] = jv[4 * hh + c];
+                                    if (cb + c < a.L) jrow[cb + c] = jv[4 * hh + c];
                             }
                         }
                     }
@@ -811,18 +832,18 @@ hipError_t sur_alloc(Sur& s) {
         if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
     };
     al(s.w, s.n_params); al(s.g, s.n_params); al(s.m, s.n_params); al(s.v, s.n_params);
-    al(s.xm, 33); al(s.xs, 33); al(s.ym, s.L); al(s.ys, s.L); al(s.wq, s.L); al(s.loss, 1);
+    al(s.xm, 33); al(s.xs, 33); al(s.ym, s.n_out); al(s.ys, s.n_out); al(s.wq, s.n_out); al(s.loss, 1);
     if (e == hipSuccess) e = hipMemset(s.m, 0, sizeof(float) * s.n_params);
     if (e == hipSuccess) e = hipMemset(s.v, 0, sizeof(float) * s.n_params);
     if (e == hipSuccess) {
-        std::vector<float> wq(s.L, 0.f);
+        std::vector<float> wq(s.n_out, 0.f);   // the ratio output carries no weight
         const std::vector<double>& lam = s.c->lam_host;
         for (int j = 0; j + 1 < s.L; ++j) {
             const double h = 0.5 * (lam[j + 1] - lam[j]) * 4.0 * kPi;
             wq[j] += static_cast<float>(h);
             wq[j + 1] += static_cast<float>(h);
         }
-        e = hipMemcpy(s.wq, wq.data(), sizeof(float) * s.L, hipMemcpyHostToDevice);
+        e = hipMemcpy(s.wq, wq.data(), sizeof(float) * s.n_out, hipMemcpyHostToDevice);
     }
     return e;
 }
@@ -861,7 +882,7 @@ hipError_t sur_grow(Sur& s, int B) {
         if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
     };
     const size_t b = static_cast<size_t>(B);
-    al(s.Xb, b * 33); al(s.Yb, b * s.L); al(s.Yh, b * s.L); al(s.dY, b * s.L);
+    al(s.Xb, b * 33); al(s.Yb, b * s.n_out); al(s.Yh, b * s.n_out); al(s.dY, b * s.n_out);
     for (int i = 0; i < 3; ++i) {
         al(s.Z[i], b * 256);
         al(s.H[i], b * 256);
@@ -873,8 +894,8 @@ hipError_t sur_grow(Sur& s, int B) {
     s.splits = std::max(1, std::min(32, B / 256));
     (void)hipFree(s.split_work);
     s.split_work = nullptr;
-    al(s.split_work, static_cast<size_t>(s.splits) * std::max(s.L, 256) * 256 +
-                         static_cast<size_t>((B + 31) / 32) * std::max(s.L, 256));
+    al(s.split_work, static_cast<size_t>(s.splits) * std::max(s.n_out, 256) * 256 +
+                         static_cast<size_t>((B + 31) / 32) * std::max(s.n_out, 256));
     if (e == hipSuccess) s.cap_B = B;
     return e;
 }
@@ -905,9 +926,10 @@ hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const do
     return hipGetLastError();
 }
 
-hipError_t sur_targets(const float* j, const double* A, long long n, int L, float* Y, hipStream_t st) {
+hipError_t sur_targets(const float* j, const double* A, const double* lam, long long n, int L, float* Y,
+                       hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_targets, dim3(static_cast<unsigned>((n + 3) / 4)), dim3(256), 0, st, j, A, n, L, Y);
+    hipLaunchKernelGGL(k_targets, dim3(static_cast<unsigned>((n + 3) / 4)), dim3(256), 0, st, j, A, lam, n, L, Y);
     return hipGetLastError();
 }
 
@@ -968,7 +990,7 @@ hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep
         in = 256;
     }
     if (e != hipSuccess) return e;
-    GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, s.Yh, s.L, B, s.L, 256);
+    GemmArgs g = nt(h, 256, s.w + s.off_W[3], 256, s.Yh, s.n_out, B, s.n_out, 256);
     g.asplit = kSplitIn[3];
     g.bias = s.w + s.off_b[3];
     return gemm<EPI_BIAS>(g, st);
@@ -978,7 +1000,7 @@ hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep
 hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st) {
     hipError_t e = hipSuccess;
     const float* dz = s.dY;
-    int nout = s.L;
+    int nout = s.n_out;
     for (int l = 3; l >= 0 && e == hipSuccess; --l) {
         const int nin = s.widths[l];
         const float* hin = l > 0 ? s.H[l - 1] : Xb;
@@ -1015,7 +1037,7 @@ hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st) {
 }
 
 hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
-    const long long n = static_cast<long long>(B) * s.L;
+    const long long n = static_cast<long long>(B) * s.n_out;
     hipError_t e = hipMemsetAsync(s.loss, 0, sizeof(double), st);
     if (e != hipSuccess) return e;
     const long long blocks = std::min<long long>(1024, (n + 255) / 256);
@@ -1025,7 +1047,7 @@ hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
 }
 
 hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, st, X, Y, s.idx, B, s.L, s.xm, s.xs, s.ym, s.ys, s.Xb, s.Yb);
+    hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, st, X, Y, s.idx, B, s.n_out, s.xm, s.xs, s.ym, s.ys, s.Xb, s.Yb);
     return hipGetLastError();
 }
 
@@ -1059,13 +1081,13 @@ hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
 // Weights in BF16 for inference (packed once per parameter change).
 hipError_t sur_pack(Sur& s, hipStream_t st) {
     if (s.wb_fresh) return hipSuccess;
-    const long long n = 256LL * 96 + 2LL * 256 * 256 + static_cast<long long>(s.L) * 256;
+    const long long n = 256LL * 96 + 2LL * 256 * 256 + static_cast<long long>(s.n_out) * 256;
     if (!s.wb) {
         const hipError_t e = hipMalloc(&s.wb, sizeof(unsigned short) * n);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_pack_bf16, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, s.w, s.off_W[0],
-                       s.off_W[1], s.off_W[2], s.off_W[3], s.L, s.wb);
+                       s.off_W[1], s.off_W[2], s.off_W[3], s.n_out, s.wb);
     const hipError_t e = hipGetLastError();
     if (e == hipSuccess) s.wb_fresh = true;
     return e;
@@ -1089,10 +1111,11 @@ hipError_t dense(const DenseArgs& a, hipStream_t st) {
 // Inference of rows [row0, row0 + M) of a selection from the normalised
 // inputs xb [M][96] (hi and lo terms, as sur_pairs writes them): spectra
 // scattered to j (pair rows); emit[x][r] = 4 pi int j dlambda over the
-// wavelengths of column slice x (sur_emit_parts(L) slices of 128).
-// Workspaces: h0 [M][512], h1 [M][256] BF16.
+// wavelengths of column slice x (sur_emit_parts(n_out) slices of 128);
+// rho[r] = the predicted energy ratio.  Workspaces: h0 [M][512], h1 [M][256]
+// BF16.
 hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
-                          int n_slots, const int* sel, float* j, float* emit, unsigned short* h0,
+                          int n_slots, const int* sel, float* j, float* emit, float* rho, unsigned short* h0,
                           unsigned short* h1, hipStream_t st) {
     if (M <= 0) return hipSuccess;
     if (static_cast<long long>(M) + n_sel >= (1LL << 31)) return hipErrorInvalidValue;
@@ -1116,21 +1139,21 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
     e = dense<256, false, true>(d, st);
     if (e != hipSuccess) return e;
     DenseArgs o{};
-    o.in = h0; o.W = W4; o.bias = s.w + s.off_b[3]; o.M = M; o.N = s.L;
-    o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit;
+    o.in = h0; o.W = W4; o.bias = s.w + s.off_b[3]; o.M = M; o.N = s.n_out;
+    o.j = j; o.L = s.L; o.ym = s.ym; o.ys = s.ys; o.Arow = A; o.wq = s.wq; o.emit = emit; o.rho = rho;
     // M + n_sel < 2^31 (one chunk), so the row arithmetic fits 32 bits
     o.cell0 = row0 / n_sel; o.off0 = static_cast<int>(row0 - o.cell0 * n_sel);
     o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
     return dense<256, true, true>(o, st);
 }
 
-int sur_emit_parts(int L) { return (L + 127) / 128; }
+int sur_emit_parts(int n_out) { return (n_out + 127) / 128; }
 
-hipError_t sur_diag(const double* A, const float* emit, int n_parts, long long row0, long long n, int n_sel,
-                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
+                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, n_parts,
-                       row0, n, n_sel, n_slots, sel, tol, diag, cnt);
+                       rho, row0, n, n_sel, n_slots, sel, tol, diag, cnt);
     return hipGetLastError();
 }
 

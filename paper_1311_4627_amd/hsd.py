@@ -39,6 +39,8 @@ N_CLASSES = 4
 CLASS_BINS = ((513, 1024), (257, 512), (129, 256), (16, 128))   # bin-count range of each solver class
 PLAN_TIMING = 1
 PLAN_CONCURRENT = 2
+CHECK_ABSORBED = 0      # surrogate energy check against the absorbed power A
+CHECK_MODEL = 1         # ... against rho A, rho the predicted energy ratio of the plain model
 
 
 class HsdError(RuntimeError):
@@ -128,7 +130,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_sur_train.argtypes = [vp, i64, vp, vp, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
     lib.hsd_sur_predict.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
     lib.hsd_solve_surrogate.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.c_float,
-                                        vp, vp, ctypes.POINTER(i64), vp]
+                                        i32, vp, vp, ctypes.POINTER(i64), vp]
     for name in ("hsd_sur_create", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
                  "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
                  "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate"):
@@ -345,13 +347,13 @@ class Context:
         n = int(A.shape[0])
         _check_dev(j, torch.float32, (n, self.L), "j")
         _check_dev(A, torch.float64, (n,), "A")
-        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        _check_dev(Y, torch.float32, (n, self.L + 1), "Y")
         st = self._lib.hsd_sur_targets(self._h, n, j.data_ptr(), A.data_ptr(), Y.data_ptr(), _stream_ptr(stream))
         if st != HSD_OK:
             self._raise(st, "hsd_sur_targets")
 
     def hsd_solve_surrogate(self, u, grain_ids: Sequence[int], surs: Sequence["Surrogate"], j, diag, tol=0.01,
-                            stream=None) -> int:
+                            check: int = CHECK_MODEL, stream=None) -> int:
         import torch
         n_cells = int(u.shape[0])
         ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
@@ -365,7 +367,8 @@ class Context:
         nfb = ctypes.c_int64()
         st = self._lib.hsd_solve_surrogate(self._h, n_cells, u.data_ptr(), G,
                                            ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), hs, float(tol),
-                                           j.data_ptr(), diag.data_ptr(), ctypes.byref(nfb), _stream_ptr(stream))
+                                           int(check), j.data_ptr(), diag.data_ptr(), ctypes.byref(nfb),
+                                           _stream_ptr(stream))
         if st != HSD_OK:
             self._raise(st, "hsd_solve_surrogate")
         return int(nfb.value)
@@ -439,7 +442,8 @@ class Surrogate:
         n = ctypes.c_int64()
         self._check(self._lib.hsd_sur_n_params(h, ctypes.byref(n)), "hsd_sur_n_params")
         self.n_params = int(n.value)
-        self.L = ctx.L
+        self.L = ctx.L                  # spectrum length
+        self.n_out = ctx.L + 1          # network outputs: the spectrum, then the energy ratio
 
     def _check(self, st, what):
         if st != HSD_OK:
@@ -470,12 +474,12 @@ class Surrogate:
     def hsd_sur_set_norm(self, x_mean, x_std, y_mean, y_std):
         a, b = (np.ascontiguousarray(v, dtype=np.float64) for v in (x_mean, x_std))
         c, d = (np.ascontiguousarray(v, dtype=np.float64) for v in (y_mean, y_std))
-        if a.shape != (33,) or b.shape != (33,) or c.shape != (self.L,) or d.shape != (self.L,):
+        if a.shape != (33,) or b.shape != (33,) or c.shape != (self.n_out,) or d.shape != (self.n_out,):
             raise ValueError("statistics have the wrong shape")
         self._check(self._lib.hsd_sur_set_norm(self._h, _dptr(a), _dptr(b), _dptr(c), _dptr(d)), "hsd_sur_set_norm")
 
     def hsd_sur_get_norm(self):
-        a, b, c, d = np.empty(33), np.empty(33), np.empty(self.L), np.empty(self.L)
+        a, b, c, d = np.empty(33), np.empty(33), np.empty(self.n_out), np.empty(self.n_out)
         self._check(self._lib.hsd_sur_get_norm(self._h, _dptr(a), _dptr(b), _dptr(c), _dptr(d)), "hsd_sur_get_norm")
         return a, b, c, d
 
@@ -483,14 +487,14 @@ class Surrogate:
         import torch
         n = int(X.shape[0])
         _check_dev(X, torch.float32, (n, 33), "X")
-        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        _check_dev(Y, torch.float32, (n, self.n_out), "Y")
         self._check(self._lib.hsd_sur_fit_norm(self._h, n, X.data_ptr(), Y.data_ptr()), "hsd_sur_fit_norm")
 
     def hsd_sur_loss_grad(self, X, Y):
         import torch
         n = int(X.shape[0])
         _check_dev(X, torch.float32, (n, 33), "X")
-        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        _check_dev(Y, torch.float32, (n, self.n_out), "Y")
         loss = ctypes.c_double()
         g = np.empty(self.n_params, dtype=np.float32)
         self._check(self._lib.hsd_sur_loss_grad(self._h, n, X.data_ptr(), Y.data_ptr(), ctypes.byref(loss), _fptr(g)),
@@ -501,7 +505,7 @@ class Surrogate:
         import torch
         n = int(X.shape[0])
         _check_dev(X, torch.float32, (n, 33), "X")
-        _check_dev(Y, torch.float32, (n, self.L), "Y")
+        _check_dev(Y, torch.float32, (n, self.n_out), "Y")
         trace = np.zeros(max(int(steps), 1), dtype=np.float32)
         self._check(self._lib.hsd_sur_train(self._h, n, X.data_ptr(), Y.data_ptr(), int(steps), int(batch),
                                             float(lr), int(seed), _fptr(trace)), "hsd_sur_train")

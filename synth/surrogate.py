@@ -16,6 +16,12 @@ HIDDEN = (256, 256, 256)
 N_IN = 33
 
 
+def n_outputs(n_lambda: int) -> int:
+    """Network outputs for a spectrum of n_lambda wavelengths: the spectrum,
+    then the energy ratio."""
+    return int(n_lambda) + 1
+
+
 def widths(n_out: int):
     return (N_IN,) + HIDDEN + (int(n_out),)
 

@@ -55,7 +55,7 @@ def _training_set(hsd, n_cells, composition="carbonaceous", heldout=False):
     X = torch.empty((n_cells * G, 33), dtype=torch.float32, device="cuda")
     A = torch.empty((n_cells * G,), dtype=torch.float64, device="cuda")
     ctx.hsd_sur_features(ud, ids, X, A)
-    Y = torch.empty((n_cells * G, w.n_lambda), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n_cells * G, ssur.n_outputs(w.n_lambda)), dtype=torch.float32, device="cuda")
     ctx.hsd_sur_targets(j.view(-1, w.n_lambda), A, Y)
     ctx.hsd_sync()
     return dict(w=w, ctx=ctx, ids=ids, grains=grains, u=u, ud=ud, j=j, diag=diag, X=X, A=A, Y=Y)
@@ -71,7 +71,7 @@ def test_features_and_targets_match_reference(hsd, small):
     w, G = d["w"], len(d["ids"])
     X = d["X"].cpu().numpy().reshape(-1, G, 33)
     A = d["A"].cpu().numpy().reshape(-1, G)
-    Y = d["Y"].cpu().numpy().reshape(-1, G, w.n_lambda)
+    Y = d["Y"].cpu().numpy().reshape(-1, G, ssur.n_outputs(w.n_lambda))
     j = d["j"].cpu().numpy()
     for c in (0, 37, 95):
         for g in (0, 21, 63):
@@ -81,20 +81,22 @@ def test_features_and_targets_match_reference(hsd, small):
             s = oracle.grain_setup(gr, w.lam_cm)
             Ar = float(np.trapezoid(oracle.C * d["u"][c] * s.cabs, w.lam_cm))
             assert abs(A[c, g] / Ar - 1) < 1e-12
-            yr = mlp.targets(j[c, g].astype(np.float64), Ar)
+            yr = mlp.targets(j[c, g].astype(np.float64), Ar, w.lam_cm)
             assert np.max(np.abs(Y[c, g] - yr)) < 1e-5
 
 
 def test_loss_and_gradient_match_bf16_reference(hsd, small):
     d = small
     sur = hsd.Surrogate(d["ctx"])
-    flat = ssur.init_params(d["w"].n_lambda, seed=99)
+    flat = ssur.init_params(ssur.n_outputs(d["w"].n_lambda), seed=99)
     sur.hsd_sur_set_params(flat)
     sur.hsd_sur_fit_norm(d["X"], d["Y"])
     xm, xs, ym, ys = sur.hsd_sur_get_norm()
     Xr, Yr = d["X"].cpu().numpy().astype(np.float64), d["Y"].cpu().numpy().astype(np.float64)
     mu, sd = mlp.zscore_stats(Xr)
     assert np.allclose(xm, mu, rtol=1e-5, atol=1e-5) and np.allclose(xs, sd, rtol=1e-4)
+    mu, sd = mlp.target_stats(Yr)
+    assert np.allclose(ym, mu, rtol=1e-5, atol=1e-5) and np.allclose(ys, sd, rtol=1e-4)
     n = 512
     rows = np.random.default_rng(3).choice(Xr.shape[0], n, replace=False)
     Xb = torch.tensor(Xr[rows], dtype=torch.float32, device="cuda")
@@ -103,7 +105,7 @@ def test_loss_and_gradient_match_bf16_reference(hsd, small):
     # reference on the same normalised rows (the GPU's FP32 statistics)
     Xn = (Xr[rows] - xm) / xs
     Yn = (Yr[rows] - ym) / ys
-    widths = ssur.widths(d["w"].n_lambda)
+    widths = ssur.widths(ssur.n_outputs(d["w"].n_lambda))
     lref, gref = mlp.loss_and_grad(flat.astype(np.float64), widths, Xn, Yn, bf16=True)
     print(f"loss {loss:.6e} ref {lref:.6e}", flush=True)
     assert abs(loss / lref - 1) < 1e-3
@@ -122,7 +124,7 @@ def test_training_lowers_loss_and_beats_a_table(hsd):
     h = _training_set(hsd, 64, heldout=True)
     w, G = d["w"], len(d["ids"])
     sur = hsd.Surrogate(d["ctx"])
-    sur.hsd_sur_set_params(ssur.init_params(w.n_lambda))
+    sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(w.n_lambda)))
     sur.hsd_sur_fit_norm(d["X"], d["Y"])
     trace = sur.hsd_sur_train(d["X"], d["Y"], steps=4000, batch=4096, lr=4e-3)
     print(f"loss: first {trace[:20].mean():.4e} last {trace[-50:].mean():.4e}", flush=True)
@@ -139,7 +141,7 @@ def test_training_lowers_loss_and_beats_a_table(hsd):
     # the table method: the training pair of the same grain with the nearest
     # total field energy, its spectrum per absorbed power times this pair's A
     Xt = d["X"].cpu().numpy().reshape(-1, G, 33)
-    Yt = d["Y"].cpu().numpy().reshape(-1, G, w.n_lambda)
+    Yt = d["Y"].cpu().numpy().reshape(-1, G, ssur.n_outputs(w.n_lambda))[..., :w.n_lambda]
     Xh = h["X"].cpu().numpy().reshape(-1, G, 33)
     Ah = h["A"].cpu().numpy().reshape(-1, G)
     etot_t = np.log10(np.sum(10.0 ** Xt[:, 0, :32].astype(np.float64), axis=1))
@@ -158,7 +160,7 @@ def test_fallback_is_the_plain_solve(hsd, small):
     d = small
     w, ctx, ids = d["w"], d["ctx"], d["ids"]
     sur = hsd.Surrogate(ctx)
-    sur.hsd_sur_set_params(ssur.init_params(w.n_lambda, seed=5))
+    sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(w.n_lambda), seed=5))
     sur.hsd_sur_fit_norm(d["X"], d["Y"])
     sur.hsd_sur_train(d["X"], d["Y"], steps=400, batch=512, lr=2e-3)
     G = len(ids)
@@ -176,12 +178,25 @@ def test_fallback_is_the_plain_solve(hsd, small):
     assert nfb == int(np.sum(~surp))
     pflags = dp[..., 3].to(torch.int32).cpu().numpy()
     assert np.array_equal(~surp, (pflags & 16) != 0)
-    # surrogate pairs: the prediction, and the energy check holds
+    # surrogate pairs: the prediction, and the energy check holds against the
+    # model's predicted budget rho A (diag entry 2)
     assert torch.equal(j[torch.tensor(surp, device="cuda")], jp[torch.tensor(surp, device="cuda")])
     dd = diag.cpu().numpy()
-    assert np.all(np.abs(dd[surp][:, 1] / dd[surp][:, 0] - 1) <= 0.01 + 1e-6)
+    assert np.all(np.abs(dd[surp][:, 1] / dd[surp][:, 2] - 1) <= 0.01 + 1e-6)
+    assert np.array_equal(dd[surp][:, 2], dp.cpu().numpy()[surp][:, 2])
     # fallback pairs: exactly the plain solve
     je, de = d["j"], d["diag"]
+    fb = torch.tensor(~surp, device="cuda")
+    assert torch.equal(j[fb], je[fb]) and torch.equal(diag[fb], de[fb])
+    # the check against the absorbed power itself
+    nfa = ctx.hsd_solve_surrogate(d["ud"], ids, [sur] * G, j, diag, tol=0.01, check=hsd.CHECK_ABSORBED)
+    ctx.hsd_sync()
+    dd = diag.cpu().numpy()
+    surp = (dd[..., 3].astype(np.int32) & 8) != 0
+    print(f"fallback (check against A) {nfa} of {n_cells * G} pairs", flush=True)
+    assert nfa == int(np.sum(~surp))
+    assert np.all(np.abs(dd[surp][:, 1] / dd[surp][:, 0] - 1) <= 0.01 + 1e-6)
+    assert np.array_equal(dd[surp][:, 2], dd[surp][:, 0])
     fb = torch.tensor(~surp, device="cuda")
     assert torch.equal(j[fb], je[fb]) and torch.equal(diag[fb], de[fb])
     # tol = 0: every pair falls back and the output is the plain solve
@@ -189,6 +204,8 @@ def test_fallback_is_the_plain_solve(hsd, small):
     ctx.hsd_sync()
     assert nfb0 == n_cells * G
     assert torch.equal(j, je) and torch.equal(diag, de)
+    with pytest.raises(hsd.HsdError):
+        ctx.hsd_solve_surrogate(d["ud"], ids, [sur] * G, j, diag, tol=0.01, check=7)
     sur.close()
 
 
@@ -199,7 +216,7 @@ def test_inference_matches_bf16_reference(hsd, small):
     d = small
     w, G = d["w"], len(d["ids"])
     sur = hsd.Surrogate(d["ctx"])
-    flat = ssur.init_params(w.n_lambda, seed=17)
+    flat = ssur.init_params(ssur.n_outputs(w.n_lambda), seed=17)
     sur.hsd_sur_set_params(flat)
     sur.hsd_sur_fit_norm(d["X"], d["Y"])
     sur.hsd_sur_train(d["X"], d["Y"], steps=200, batch=512, lr=2e-3)     # weights away from their init
@@ -212,13 +229,20 @@ def test_inference_matches_bf16_reference(hsd, small):
     torch.cuda.synchronize()
     X = d["X"].cpu().numpy()[: n_cells * G].astype(np.float64)
     A = d["A"].cpu().numpy()[: n_cells * G]
-    yhat, _ = mlp.forward(flat, ssur.widths(w.n_lambda), (X - xm) / xs, bf16=True)
-    jref = A[:, None] * 10.0 ** (yhat * ys + ym)
+    yhat, _ = mlp.forward(flat, ssur.widths(ssur.n_outputs(w.n_lambda)), (X - xm) / xs, bf16=True)
+    yraw = yhat * ys + ym
+    jref = A[:, None] * 10.0 ** yraw[:, :w.n_lambda]
     jg = jp.cpu().numpy().reshape(-1, w.n_lambda).astype(np.float64)
     rel = np.abs(jg / jref - 1)
     print(f"inference vs reference: median {np.median(rel):.2e} max {rel.max():.2e}", flush=True)
     assert np.median(rel) < 2e-4 and rel.max() < 2e-2
     # emitted power of each pair: 4 pi trapezoid of its spectrum
     em = 4 * math.pi * np.trapezoid(jg, w.lam_cm, axis=1)
-    assert np.allclose(dp.cpu().numpy().reshape(-1, 4)[:, 1], em, rtol=1e-5)
+    dg = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
+    assert np.allclose(dg[:, 1], em, rtol=1e-5)
+    # the energy-ratio output: diag entry 2 = rho A
+    rho = dg[:, 2] / dg[:, 0]
+    rr = np.abs(rho / 10.0 ** yraw[:, w.n_lambda] - 1)
+    print(f"energy ratio vs reference: max {rr.max():.2e}", flush=True)
+    assert rr.max() < 1e-3
     sur.close()

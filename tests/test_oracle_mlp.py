@@ -146,11 +146,19 @@ def test_targets_and_band_error():
     rng = np.random.default_rng(1)
     j = np.exp(rng.normal(size=(3, 500)))
     A = np.array([2.0, 3.0, 4.0])
-    y = mlp.targets(j, A)
-    assert np.allclose(10 ** y * A[:, None], j, rtol=1e-12)
+    y = mlp.targets(j, A, lam)
+    assert y.shape == (3, 501)
+    assert np.allclose(10 ** y[:, :500] * A[:, None], j, rtol=1e-12)
     jz = j.copy()
     jz[0, :10] = 0.0
-    assert np.all(np.isfinite(mlp.targets(jz, A)))
+    assert np.all(np.isfinite(mlp.targets(jz, A, lam)))
+    # the ratio column: for a spectrum linear in lambda the trapezoid rule is
+    # exact, E = 4 pi (a (l1 - l0) + b (l1^2 - l0^2) / 2)
+    a, b = 3.0, 5.0e4
+    jl = a + b * lam
+    E = 4.0 * np.pi * (a * (lam[-1] - lam[0]) + 0.5 * b * (lam[-1] ** 2 - lam[0] ** 2))
+    yl = mlp.targets(jl[None, :], np.array([7.0]), lam)
+    assert abs(10 ** yl[0, 500] * 7.0 / E - 1) < 1e-12
     assert np.all(mlp.band_rel_error(j, j, lam) == 0.0)
     assert np.allclose(mlp.band_rel_error(1.01 * j, j, lam), 0.01, rtol=1e-10)
 
@@ -159,3 +167,8 @@ def test_zscore_stats():
     A = np.array([[1.0, 5.0], [3.0, 5.0]])
     mu, sd = mlp.zscore_stats(A)
     assert np.allclose(mu, [2.0, 5.0]) and np.allclose(sd, [1.0, 1.0])
+    # targets: spectrum columns share sqrt(mean variance), the ratio keeps its own
+    Y = np.array([[0.0, 0.0, 1.0], [2.0, 4.0, 1.5]])
+    mu, sd = mlp.target_stats(Y)
+    assert np.allclose(mu, [1.0, 2.0, 1.25])
+    assert np.allclose(sd, [np.sqrt((1.0 + 4.0) / 2)] * 2 + [0.25 * mlp.RATIO_SCALE])
