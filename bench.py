@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=48)
     ap.add_argument("--eager", action="store_true", help="time hsd_solve calls instead of plan replays")
     ap.add_argument("--retune", action="store_true", help="time the launch configurations again")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="launch every class as an ordinary grid (what a concurrent plan launches; for counter runs)")
     ap.add_argument("--train-steps", type=int, default=60000, help="surrogate training steps per composition")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM byte counters)")
@@ -374,6 +376,15 @@ def main():
     tune_s = time.perf_counter() - t0
     print(f"launch configuration ({'cached' if tuned['cached'] else 'timed'} in {tune_s:.1f} s): {tuned['cfg']}",
           file=sys.stderr, flush=True)
+    # the configuration the timed launches use: a concurrent plan launches
+    # every class as an ordinary grid
+    launched = [dict(c) for c in tuned["cfg"]]
+    if args.no_persistent or not args.eager:
+        for c in launched:
+            c["persistent"] = 0
+    if args.no_persistent:
+        for cls, c in enumerate(launched):
+            ctx.hsd_set_class_cfg(cls, **c)
 
     plan = None
     if not args.eager:
@@ -441,7 +452,7 @@ def main():
                    "bins": f"{max(g.n_bins for g in w.grains)}..{min(g.n_bins for g in w.grains)} "
                            f"(sum {sum(g.n_bins for g in w.grains)})",
                    "launch": "eager" if plan is None else "plan (HIP graphs, concurrent classes)",
-                   "class_cfg": tuned["cfg"]},
+                   "class_cfg": launched},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": EXP2_PEAK / 1e12, "unit": "Texp2/s",
                      "frac": achieved / EXP2_PEAK, "traffic": recorded_traffic(),
                      "kernel": "fused rates/recursion (k_solve)", "kernel_ms": phase[0],

@@ -177,9 +177,11 @@ hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, co
  * own kernel shape: class 0 holds 513..1024 bins, class 1 257..512, class 2
  * 129..256 and class 3 16..128.  Per class:
  *   kg          row slots evaluated per straight-line group: 2 or 4;
- *   wide        class 0 only: 0 = 32 lanes per pair with 32 row slots each
- *               and the absorbed-power table in LDS, 1 = 64 lanes per pair
- *               with 16 row slots each;
+ *   wide        the alternate lane layout, classes 0 and 1 only.  Class 0:
+ *               0 = 32 lanes per pair with 32 row slots each and the
+ *               absorbed-power table in LDS, 1 = 64 lanes with 16 slots;
+ *               class 1: 0 = 32 lanes with 16 slots, 1 = 16 lanes with 32
+ *               slots and the absorbed-power table in LDS;
  *   persistent  0 = one workgroup per work item (items in an order that
  *               gives each XCD whole cell blocks), 1 = a grid of the
  *               workgroups that fit on the device at once, fed items longest
@@ -233,7 +235,10 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
  *          hsd_plan_phase_ms waits for the last launch and writes the phases'
  *          milliseconds to ms_host[0..2].
  *          HSD_PLAN_CONCURRENT: the solver classes run as parallel branches
- *          of the graph, so one class's tail overlaps the next class.
+ *          of the graph, so one class's tail overlaps the next class; the
+ *          classes then launch as ordinary grids whatever their persistent
+ *          setting (a persistent grid takes every workgroup slot of the
+ *          device and would hold the other branches off it).
  * The buffers must stay allocated, and the grains registered, while the plan
  * lives.  A plan is used by one thread at a time; replays of one plan on
  * different streams must not overlap (they share its workspace).

@@ -497,8 +497,8 @@ hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg
     if (!ctx) return HSD_ERR_INVALID_ARG;
     if (!cfg || cls < 0 || cls >= hsd::kClasses) return fail(ctx, HSD_ERR_INVALID_ARG, "bad class or null config");
     if (cfg->kg != 2 && cfg->kg != 4) return fail(ctx, HSD_ERR_INVALID_ARG, "kg must be 2 or 4");
-    if (cfg->wide != 0 && (cfg->wide != 1 || cls != 0))
-        return fail(ctx, HSD_ERR_INVALID_ARG, "wide is 0 or 1, and 1 only for class 0");
+    if (cfg->wide != 0 && (cfg->wide != 1 || cls > 1))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "wide is 0 or 1, and 1 only for classes 0 and 1");
     if (cfg->persistent != 0 && cfg->persistent != 1) return fail(ctx, HSD_ERR_INVALID_ARG, "persistent is 0 or 1");
     hsd::ClassCfg& k = ctx->c.cfg[cls];
     k.kg = cfg->kg;
@@ -539,7 +539,7 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
         const hsd::ClassCfg keep = c.cfg[ci];
         hsd::ClassCfg best = keep;
         double best_ms = 1e300;
-        for (int wide = 0; wide <= (ci == 0 ? 1 : 0) && st == HSD_OK; ++wide)
+        for (int wide = 0; wide <= (ci <= 1 ? 1 : 0) && st == HSD_OK; ++wide)
             for (int pers = 0; pers <= 1 && st == HSD_OK; ++pers)
                 for (int kg = 2; kg <= 4 && st == HSD_OK; kg += 2) {
                     c.cfg[ci] = hsd::ClassCfg{kg, wide, pers};
@@ -626,6 +626,22 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
     p->n_grains = n_grains;
     p->ids.assign(grain_ids_host, grain_ids_host + n_grains);
     p->timing = (flags & HSD_PLAN_TIMING) != 0;
+    const bool conc = (flags & HSD_PLAN_CONCURRENT) != 0;
+    // concurrent branches launch ordinary grids: the context's persistent
+    // settings are set aside while the plan is built and restored on return
+    struct KeepCfg {
+        Ctx& c;
+        hsd::ClassCfg saved[hsd::kClasses];
+        KeepCfg(Ctx& cc, bool off) : c(cc) {
+            for (int i = 0; i < hsd::kClasses; ++i) {
+                saved[i] = c.cfg[i];
+                if (off) c.cfg[i].persistent = 0;
+            }
+        }
+        ~KeepCfg() {
+            for (int i = 0; i < hsd::kClasses; ++i) c.cfg[i] = saved[i];
+        }
+    } keep_cfg(c, conc);
     plan_batch(c, n_cells, n_grains, p->ids.data(), p->b);
     hipError_t e = hipSuccess;
     auto al = [&](auto*& ptr, size_t count) {
@@ -645,7 +661,6 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
         e = hipMemcpy(p->items, p->b.items.data(), sizeof(int2) * p->b.items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->queue, 0, sizeof(unsigned) * hsd::kClasses);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
-    const bool conc = (flags & HSD_PLAN_CONCURRENT) != 0;
     for (int i = 0; conc && i < hsd::kClasses && e == hipSuccess; ++i)
         e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking);
     for (int i = 0; conc && i <= hsd::kClasses && e == hipSuccess; ++i)

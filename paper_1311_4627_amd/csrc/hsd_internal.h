@@ -82,7 +82,8 @@ constexpr int kClasses = 4;
 constexpr int kClassHi[kClasses] = {1024, 512, 256, 128};   // class c holds kClassHi[c+1] < bins <= kClassHi[c]
 struct ClassCfg {
     int kg = 2;          // row slots per straight-line group: 2 or 4
-    int wide = 0;        // > 512 bins: 0 = 32 lanes x 32 slots with Cum in LDS, 1 = 64 lanes x 16 slots
+    int wide = 0;        // alternate lane layout: > 512 bins: 0 = 32 lanes x 32 slots with Cum in LDS,
+                         // 1 = 64 x 16; 257..512 bins: 0 = 32 x 16, 1 = 16 x 32 with Cum in LDS
     int persistent = 0;  // 1 = persistent grid fed by an atomic item counter
 };
 

@@ -729,19 +729,26 @@ constexpr int kWaves = 4;
 }  // namespace
 
 // Bin-count classes: lanes per pair P and row slots per lane R (P R >= bins).
-//   <= 128 bins: P 16, R 8;  <= 256: P 16, R 16;  <= 512: P 32, R 16;
-//   <= 1024: P 32, R 32 with the Cum table kept in LDS, or (wide) P 64, R 16.
-int solve_cells_per_item(const ClassCfg& cfg, int cls) {
-    const int nb_max = kClassHi[cls];
-    if (nb_max <= 256) return kWaves * 4;
-    if (nb_max > 512 && cfg.wide) return kWaves;
-    return kWaves * 2;
+//   <= 128 bins: P 16, R 8;  <= 256: P 16, R 16;
+//   <= 512: P 32, R 16, or (alternate layout) P 16, R 32 with the Cum table
+//           kept in LDS: twice the rows per lane and step, so the per-step
+//           work (suffix sums, the column's X) is spread over twice the rates;
+//   <= 1024: P 32, R 32 with the Cum table kept in LDS, or (alternate) P 64, R 16.
+namespace {
+int class_lanes(const ClassCfg& cfg, int cls) {
+    if (cls == 0) return cfg.wide ? 64 : 32;
+    if (cls == 1) return cfg.wide ? 16 : 32;
+    return 16;
 }
+bool class_ldscum(const ClassCfg& cfg, int cls) { return (cls == 0 && !cfg.wide) || (cls == 1 && cfg.wide); }
+}  // namespace
+
+int solve_cells_per_item(const ClassCfg& cfg, int cls) { return kWaves * (64 / class_lanes(cfg, cls)); }
 
 // LDS floats per pair: the log2 table with its sentinels, plus the Cum table
-// when it stays in LDS (> 512 bins, narrow layout).
+// when it stays in LDS.
 int tab_stride(const Ctx& c, int cls) {
-    if (kClassHi[cls] <= 512 || c.cfg[cls].wide) return (c.L + 3 + 3) & ~3;
+    if (!class_ldscum(c.cfg[cls], cls)) return (c.L + 3 + 3) & ~3;
     return (2 * c.L + 3 + 3) & ~3;
 }
 
@@ -752,7 +759,9 @@ int solve_capacity(const Ctx& c, int cls) {
     switch (cls) {
         case 3: return cap_phys<16, 8, kWaves, false>(cfg.kg, ts);
         case 2: return cap_phys<16, 16, kWaves, false>(cfg.kg, ts);
-        case 1: return cap_phys<32, 16, kWaves, false>(cfg.kg, ts);
+        case 1:
+            if (cfg.wide) return cap_phys<16, 32, kWaves, true>(cfg.kg, ts);
+            return cap_phys<32, 16, kWaves, false>(cfg.kg, ts);
         default:
             if (cfg.wide) return cap_phys<64, 16, kWaves, false>(cfg.kg, ts);
             return cap_phys<32, 32, kWaves, true>(cfg.kg, ts);
@@ -788,7 +797,9 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int cls, const int2
     switch (cls) {
         case 3: return launch_phys<16, 8, kWaves, false>(ka, n_items, cfg.kg, q, s);
         case 2: return launch_phys<16, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
-        case 1: return launch_phys<32, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
+        case 1:
+            if (cfg.wide) return launch_phys<16, 32, kWaves, true>(ka, n_items, cfg.kg, q, s);
+            return launch_phys<32, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
         default:
             if (cfg.wide) return launch_phys<64, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
             return launch_phys<32, 32, kWaves, true>(ka, n_items, cfg.kg, q, s);

@@ -62,7 +62,7 @@ def _eager(ctx, w, ids, u):
 def _set_all(ctx, hsd, **kw):
     for c in range(hsd.N_CLASSES):
         cfg = dict(kw)
-        if c != 0:
+        if c > 1:
             cfg["wide"] = 0
         ctx.hsd_set_class_cfg(c, **cfg)
 
@@ -95,13 +95,13 @@ def test_class_config_rejects_bad_values(hsd, c2_small):
         with pytest.raises(hsd.HsdError):
             ctx.hsd_set_class_cfg(0, **bad)
     with pytest.raises(hsd.HsdError):
-        ctx.hsd_set_class_cfg(1, kg=2, wide=1)
+        ctx.hsd_set_class_cfg(2, kg=2, wide=1)
     with pytest.raises(hsd.HsdError):
         ctx.hsd_set_class_cfg(4, kg=2)
     assert ctx.hsd_get_class_cfg(0) == {"kg": 2, "wide": 0, "persistent": 0}
 
 
-@pytest.mark.parametrize("flags,pers", [(0, 0), (3, 1), (2, 0)])
+@pytest.mark.parametrize("flags,pers", [(0, 0), (1, 1), (3, 1), (2, 0)])
 def test_plan_replays_match_eager(hsd, c2_small, flags, pers):
     w, ctx, ids, u0 = c2_small
     u = u0.clone()
@@ -205,8 +205,8 @@ def test_autotune_keeps_fastest_and_results(hsd, c2_small, tmp_path):
     j0, d0 = _eager(ctx, w, ids, u)
     try:
         recs = ctx.hsd_autotune(u, ids, runs=3)
-        # class 0: kg x persistent x wide; classes 1..3: kg x persistent
-        assert len(recs) == 8 + 4 + 4 + 4
+        # classes 0 and 1: kg x persistent x layout; classes 2 and 3: kg x persistent
+        assert len(recs) == 8 + 8 + 4 + 4
         assert all(r["ms"] > 0 and math.isfinite(r["ms"]) for r in recs)
         for c in range(hsd.N_CLASSES):
             mine = [r for r in recs if r["cls"] == c]
