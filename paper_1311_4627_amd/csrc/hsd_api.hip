@@ -29,6 +29,7 @@ struct SurWork {
     double* A = nullptr;          size_t A_cap = 0;
     float* emit = nullptr;        size_t emit_cap = 0;    // emitted-power partials [column slice][chunk]
     float* rho = nullptr;         size_t rho_cap = 0;     // predicted energy ratios [chunk]
+    long long* fblist = nullptr;  size_t fblist_cap = 0;  // flagged pairs, in the order the check found them
     unsigned short* xb = nullptr; size_t xb_cap = 0;      // BF16 normalised inputs, hi and lo [chunk][96]
     unsigned short* h0 = nullptr; size_t h0_cap = 0;      // BF16 activations [chunk][512] (hi, lo)
     unsigned short* h1 = nullptr; size_t h1_cap = 0;
@@ -368,7 +369,7 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.queue);
     hipFree(c.sizew);
     SurWork& w = ctx->sw;
-    hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.rho); hipFree(w.h0); hipFree(w.h1);
+    hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.rho); hipFree(w.fblist); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);
@@ -945,7 +946,7 @@ constexpr long long kSurChunk = 262144;   // pair rows per inference chunk
 // sw.cnt.
 hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u, int32_t n_grains,
                    const int32_t* ids, const std::vector<int>& slots, float tol, int check, float* j, float* diag,
-                   hipStream_t s) {
+                   long long* list, long long list_cap, hipStream_t s) {
     Ctx& c = ctx->c;
     SurWork& w = ctx->sw;
     if (!sur.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
@@ -969,7 +970,7 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
                                          w.rho, w.h0, w.h1, s));
         if (diag)
             HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, check == HSD_CHECK_MODEL ? w.rho : nullptr, r0, n,
-                                       n_sel, n_grains, w.sel, tol, diag, w.cnt, s));
+                                       n_sel, n_grains, w.sel, tol, diag, w.cnt, list, list_cap, s));
     }
     return HSD_OK;
 }
@@ -1118,7 +1119,7 @@ hsd_status hsd_sur_predict(hsd_sur* p, int32_t n_cells, const double* u_dev, int
     std::vector<int> slots(n_grains);
     for (int g = 0; g < n_grains; ++g) slots[g] = g;
     return sur_run(ctx, p->s, n_cells, u_dev, n_grains, grain_ids_host, slots, 0.01f, HSD_CHECK_MODEL, j_dev,
-                   diag_dev, s);
+                   diag_dev, nullptr, 0, s);
 }
 
 hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
@@ -1146,6 +1147,11 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     HSD_HIP(ctx, grow(w.cnt, w.cnt_cap, static_cast<size_t>(n_grains) + 1));
     HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * (n_grains + 1), s));
     HSD_HIP(ctx, hsd::sur_bands(c, u_dev, n_cells, w.bands, s));
+    // flagged pairs are listed by the check, up to an eighth of the pairs (at
+    // least 2^20); beyond that the fallback scans every pair's flags
+    const long long n_pairs = static_cast<long long>(n_cells) * n_grains;
+    const long long list_cap = std::min(n_pairs, std::max(1LL << 20, n_pairs / 8));
+    HSD_HIP(ctx, grow(w.fblist, w.fblist_cap, static_cast<size_t>(list_cap)));
     // one pass per network over the grains it serves
     std::vector<hsd_sur*> nets;
     for (int g = 0; g < n_grains; ++g)
@@ -1155,7 +1161,7 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
         for (int g = 0; g < n_grains; ++g)
             if (surs_host[g] == net) slots.push_back(g);
         const hsd_status st = sur_run(ctx, net->s, n_cells, u_dev, n_grains, grain_ids_host, slots, tol, check, j_dev,
-                                      diag_dev, s);
+                                      diag_dev, w.fblist, list_cap, s);
         if (st != HSD_OK) return st;
     }
     // flagged pairs per slot
@@ -1180,8 +1186,11 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     HSD_HIP(ctx, hipMemcpyAsync(w.seg_off, off.data(), sizeof(int) * n_grains, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(w.seg_cnt, counts.data(), sizeof(int) * n_grains, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * n_grains, s));        // reused as cursors
-    HSD_HIP(ctx, hsd::sur_fb_scatter(diag_dev, static_cast<long long>(n_cells) * n_grains, n_grains, w.seg_off, w.cnt,
-                                     w.cellmap, w.pairs, s));
+    if (nfb <= list_cap)
+        HSD_HIP(ctx, hsd::sur_fb_scatter_list(w.fblist, nfb, n_grains, w.seg_off, w.cnt, w.cellmap, w.pairs, s));
+    else            // more flagged pairs than the list holds: scan every pair's flags
+        HSD_HIP(ctx, hsd::sur_fb_scatter(diag_dev, static_cast<long long>(n_cells) * n_grains, n_grains, w.seg_off,
+                                         w.cnt, w.cellmap, w.pairs, s));
     Batch& b = ctx->batch;
     plan_batch_lists(c, counts, n_grains, grain_ids_host, b);
     HSD_HIP(ctx, grow(c.Pt, c.Pt_cap, static_cast<size_t>(std::max(b.rows, 1LL))));

@@ -238,7 +238,10 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
                           unsigned short* h1, hipStream_t st);
 int sur_emit_parts(int n_out);
 hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
-                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st);
+                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
+                    long long list_cap, hipStream_t st);
+hipError_t sur_fb_scatter_list(const long long* list, long long n, int n_slots, const int* seg_off, unsigned* cursor,
+                               int* cellmap, long long* pairs, hipStream_t st);
 hipError_t sur_fb_scatter(const float* diag, long long n_pairs, int n_slots, const int* seg_off, unsigned* cursor,
                           int* cellmap, long long* pairs, hipStream_t st);
 

@@ -501,36 +501,60 @@ hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
 // (A, 4 pi int j dlambda, R, flags) with R = A, or R = rho A when the
 // predicted energy ratios rho are given, flags bit 3 (value from the
 // surrogate) and bit 4 (|emitted / R - 1| > tol: the pair goes to the plain
-// solve);
-// cnt[slot] and cnt[n_slots] count the flagged pairs.  The emitted power is
-// the sum of the n_parts column-slice partials emit[x][r], in slice order (a
-// fixed order, so the check decides the same way on every run).
+// solve); cnt[slot] and cnt[n_slots] count the flagged pairs, and the first
+// list_cap flagged pairs (in no particular order) are appended to list.  The
+// emitted power is the sum of the n_parts column-slice partials emit[x][r],
+// in slice order (a fixed order, so the check decides the same way on every
+// run).  Row r of the chunk is selection entry off0 + r of cells from cell0 on
+// (n + n_sel < 2^31).
 __global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, int n_parts, const float* rho,
-                                                  long long row0, long long n, int n_sel, int n_slots, const int* sel,
-                                                  float tol, float* diag, unsigned* cnt) {
-    const long long r = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+                                                  long long cell0, int off0, int n, int n_sel, int n_slots,
+                                                  const int* sel, float tol, float* diag, unsigned* cnt,
+                                                  long long* list, long long list_cap) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
-    const long long rg = row0 + r;
-    const long long cell = rg / n_sel;
-    const int slot = sel[static_cast<int>(rg - cell * n_sel)];
+    const unsigned rs = static_cast<unsigned>(off0 + r);
+    const long long cell = cell0 + rs / static_cast<unsigned>(n_sel);
+    const int slot = sel[rs % static_cast<unsigned>(n_sel)];
     const double a = A[r];
     const double ref = rho ? a * static_cast<double>(rho[r]) : a;
     float e = 0.f;
-    for (int x = 0; x < n_parts; ++x) e += emit[x * n + r];
+    for (int x = 0; x < n_parts; ++x) e += emit[static_cast<long long>(x) * n + r];
     const bool bad = !(fabs(static_cast<double>(e) / ref - 1.0) <= tol);
-    float* d = diag + (cell * n_slots + slot) * 4;
-    d[0] = static_cast<float>(a);
-    d[1] = e;
-    d[2] = static_cast<float>(ref);
-    d[3] = bad ? 24.f : 8.f;
+    const long long pair = cell * n_slots + slot;
+    float* d = diag + pair * 4;
+    const float4 v = make_float4(static_cast<float>(a), e, static_cast<float>(ref), bad ? 24.f : 8.f);
+    if ((reinterpret_cast<size_t>(diag) & 15) == 0) {
+        *reinterpret_cast<float4*>(d) = v;
+    } else {
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+    }
     if (bad) {
         atomicAdd(cnt + slot, 1u);
-        atomicAdd(cnt + n_slots, 1u);
+        const unsigned pos = atomicAdd(cnt + n_slots, 1u);
+        if (pos < list_cap) list[pos] = pair;
     }
 }
 
 // Lists of the flagged pairs per slot (order within a slot is arbitrary; each
 // pair's result does not depend on it).
+// The same per-slot lists from the check's list of flagged pairs.
+__global__ void __launch_bounds__(256) k_fb_scatter_list(const long long* list, long long n, int n_slots,
+                                                         const int* seg_off, unsigned* cursor, int* cellmap,
+                                                         long long* pairs) {
+    const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const long long p = list[i];
+    const int slot = static_cast<int>(p % n_slots);
+    const unsigned pos = atomicAdd(cursor + slot, 1u);
+    const long long k = seg_off[slot] + static_cast<long long>(pos);
+    cellmap[k] = static_cast<int>(p / n_slots);
+    pairs[k] = p;
+}
+
 __global__ void __launch_bounds__(256) k_fb_scatter(const float* diag, long long n_pairs, int n_slots,
                                                     const int* seg_off, unsigned* cursor, int* cellmap,
                                                     long long* pairs) {
@@ -1150,10 +1174,22 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
 int sur_emit_parts(int n_out) { return (n_out + 127) / 128; }
 
 hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
-                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, hipStream_t st) {
+                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
+                    long long list_cap, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (n + n_sel >= (1LL << 31)) return hipErrorInvalidValue;
+    const long long cell0 = row0 / n_sel;
+    const int off0 = static_cast<int>(row0 - cell0 * n_sel);
     hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, n_parts,
-                       rho, row0, n, n_sel, n_slots, sel, tol, diag, cnt);
+                       rho, cell0, off0, static_cast<int>(n), n_sel, n_slots, sel, tol, diag, cnt, list, list_cap);
+    return hipGetLastError();
+}
+
+hipError_t sur_fb_scatter_list(const long long* list, long long n, int n_slots, const int* seg_off, unsigned* cursor,
+                               int* cellmap, long long* pairs, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fb_scatter_list, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, list, n,
+                       n_slots, seg_off, cursor, cellmap, pairs);
     return hipGetLastError();
 }
 

@@ -246,3 +246,29 @@ def test_inference_matches_bf16_reference(hsd, small):
     print(f"energy ratio vs reference: max {rr.max():.2e}", flush=True)
     assert rr.max() < 1e-3
     sur.close()
+
+
+def test_fallback_beyond_the_flag_list(hsd):
+    # more flagged pairs than the check's list holds (2^20): the fallback
+    # scans every pair's flags instead, and tol = 0 still gives the plain solve
+    w = synth.workload("c4_train")
+    grains = [g for g in w.grains if g.composition == "carbonaceous"]
+    ctx = hsd.Context(w.lam_cm)
+    ids = [ctx.add_grain(g) for g in grains]
+    n_cells = 16448                      # 16448 x 64 = 1,052,672 pairs > 2^20
+    u = torch.tensor(make_fields(w.lam_cm, w.field_recipe, n_cells), device="cuda")
+    G, L = len(ids), w.n_lambda
+    je = torch.empty((n_cells, G, L), dtype=torch.float32, device="cuda")
+    de = torch.empty((n_cells, G, 4), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(u, ids, je, de)
+    sur = hsd.Surrogate(ctx)
+    sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(L), seed=23))
+    sur.hsd_sur_set_norm(np.full(33, -3.0), np.full(33, 2.0), np.full(L + 1, -2.0), np.full(L + 1, 0.5))
+    j = torch.empty_like(je)
+    d = torch.empty_like(de)
+    nfb = ctx.hsd_solve_surrogate(u, ids, [sur] * G, j, d, tol=0.0)
+    ctx.hsd_sync()
+    print(f"fallback {nfb} of {n_cells * G} pairs", flush=True)
+    assert nfb == n_cells * G
+    assert torch.equal(j, je) and torch.equal(d, de)
+    sur.close()
