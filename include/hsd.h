@@ -198,6 +198,22 @@ typedef struct {
 hsd_status hsd_get_class_cfg(hsd_ctx* ctx, int32_t cls, hsd_class_cfg* cfg_host);
 hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg_host);
 
+/* Emission contraction (Sec. 2.3, eq:emission): j = (P~ B~) max P s_lambda,
+ * a (cells x bins) . (bins x wavelengths) product per grain with both
+ * operands in [0, 1] and FP32 accumulation, on the matrix cores in one of
+ *   HSD_CONTRACT_FP32    FP32 products (v_mfma_f32_16x16x4_f32);
+ *   HSD_CONTRACT_BF16X3  each operand x split as hi = bf16(x), lo =
+ *                        bf16(x - hi), |x - hi - lo| <= 2^-16 |x|, and the
+ *                        product taken as hi hi + hi lo + lo hi on BF16
+ *                        matrix cores (v_mfma_f32_16x16x32_bf16): every term
+ *                        within 3 2^-16 = 4.6e-5 of the exact product, and
+ *                        since all terms are >= 0, so is each j value.
+ * The default is HSD_CONTRACT_BF16X3.  Affects later solves and later plans. */
+#define HSD_CONTRACT_FP32 0
+#define HSD_CONTRACT_BF16X3 1
+hsd_status hsd_set_contract(hsd_ctx* ctx, int32_t mode);
+hsd_status hsd_get_contract(hsd_ctx* ctx, int32_t* mode_host);
+
 /* ---- Autotuner ----
  * Time every configuration of every bin-count class that the listed grains
  * occupy, on the given batch, and keep the fastest per class in the context

@@ -115,7 +115,7 @@ hipError_t grow(T*& p, size_t& cap, size_t need) {
 void free_grain(Grain& g) {
     hipFree(g.E); hipFree(g.dE); hipFree(g.T); hipFree(g.cool); hipFree(g.colpar); hipFree(g.dpar);
     hipFree(g.gam); hipFree(g.invgap); hipFree(g.jstar); hipFree(g.jrep); hipFree(g.cabs); hipFree(g.Bt);
-    hipFree(g.bscale);
+    hipFree(g.bscale); hipFree(g.Bh); hipFree(g.Bl);
     g = Grain{};
 }
 
@@ -266,6 +266,7 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
             const Grain& gr = c.grains[ids[g]];
             hsd::ContractLaunch cl{d.Pt + b.offs[g], d.pscale, gr.Bt, gr.bscale, j, n_cells, gr.n_bins,
                                    c.L, c.Lp, n_grains, g};
+            cl.Bh = gr.Bh; cl.Bl = gr.Bl; cl.nbp = gr.nbp; cl.mode = c.contract;
             HSD_HIP(ctx, hsd::launch_contract(cl, s));
         }
     }
@@ -421,6 +422,8 @@ hsd_status hsd_add_grain(hsd_ctx* ctx, const hsd_grain_desc* d, int32_t* grain_i
     al(g.E, n); al(g.dE, n); al(g.T, n); al(g.cool, n); al(g.colpar, n); al(g.dpar, n); al(g.gam, n);
     al(g.invgap, n); al(g.jstar, n); al(g.jrep, n); al(g.cabs, c.L); al(g.Bt, static_cast<size_t>(n) * Lp);
     al(g.bscale, Lp);
+    g.nbp = (n + 31) / 32 * 32;
+    al(g.Bh, Lp * static_cast<size_t>(g.nbp)); al(g.Bl, Lp * static_cast<size_t>(g.nbp));
     if (e == hipSuccess) e = hipMemcpy(g.cabs, d->cabs_host, sizeof(double) * c.L, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hsd::build_grain_tables(c, g);
     if (e != hipSuccess) {
@@ -505,6 +508,21 @@ hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg
     k.kg = cfg->kg;
     k.wide = cfg->wide;
     k.persistent = cfg->persistent;
+    return HSD_OK;
+}
+
+hsd_status hsd_set_contract(hsd_ctx* ctx, int32_t mode) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (mode != HSD_CONTRACT_FP32 && mode != HSD_CONTRACT_BF16X3)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "mode must be HSD_CONTRACT_FP32 or HSD_CONTRACT_BF16X3");
+    ctx->c.contract = mode;
+    return HSD_OK;
+}
+
+hsd_status hsd_get_contract(hsd_ctx* ctx, int32_t* mode) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!mode) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    *mode = ctx->c.contract;
     return HSD_OK;
 }
 
@@ -1224,6 +1242,7 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
         const Grain& gr = c.grains[grain_ids_host[g]];
         hsd::ContractLaunch cl{c.Pt + b.offs[g], c.pscale, gr.Bt, gr.bscale, j_dev, counts[g], gr.n_bins,
                                c.L, c.Lp, n_grains, g, w.cellmap + off[g]};
+        cl.Bh = gr.Bh; cl.Bl = gr.Bl; cl.nbp = gr.nbp; cl.mode = c.contract;
         HSD_HIP(ctx, hsd::launch_contract(cl, s));
     }
     hsd::DiagLaunch dl{c.lam, j_dev, diag_dev, n_cells, c.L, n_grains, w.pairs, nfb};

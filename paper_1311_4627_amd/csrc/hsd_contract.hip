@@ -19,6 +19,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int APAD = 1, BPAD = 4;
+constexpr int BK3 = 32, LK3 = BK3 + 8;      // split-BF16 kernel: k per step, LDS row length (ushorts)
 
 // One 256-thread block computes a 64 (cells) x 64 (wavelengths) tile; each of
 // its four waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 blocks.
@@ -95,6 +96,115 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
     }
 }
 
+// The same product with each operand split into two BF16 terms, x = hi + lo
+// (hi = bf16(x), lo = bf16(x - hi)), and hi hi + hi lo + lo hi accumulated in
+// FP32 on v_mfma_f32_16x16x32_bf16 (16 times the FP32 matrix-core rate; the
+// dropped lo lo term and the split's remainders keep every product within
+// 3 2^-16 of exact).  P~ is split as it is staged in LDS; the grain's table
+// comes pre-split and transposed (Bh, Bl: [Lp][nbp]).  Same tiles, XCD order
+// and epilogue as k_contract; in step s lane l supplies row l % 16 of its A
+// block with k = 8 (l / 16) + 0..7 and column l % 16 of its B block with the
+// same k, so every product still sums over each k once.
+typedef unsigned int u32x4c __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8c __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned pack_hi2(float x0, float x1, unsigned& lo) {
+    const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
+    const __bf16 l0 = static_cast<__bf16>(x0 - static_cast<float>(h0));
+    const __bf16 l1 = static_cast<__bf16>(x1 - static_cast<float>(h1));
+    lo = __builtin_bit_cast(unsigned short, l0) | (static_cast<unsigned>(__builtin_bit_cast(unsigned short, l1)) << 16);
+    return __builtin_bit_cast(unsigned short, h0) | (static_cast<unsigned>(__builtin_bit_cast(unsigned short, h1)) << 16);
+}
+
+__global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
+    __shared__ __align__(16) unsigned short Ah[BM][LK3];
+    __shared__ __align__(16) unsigned short Al[BM][LK3];
+    __shared__ __align__(16) unsigned short Bhs[BN][LK3];
+    __shared__ __align__(16) unsigned short Bls[BN][LK3];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nlt = a.Lp / BN;
+    const int b = blockIdx.x;
+    const int m = b / 8;
+    const int rt = 8 * (m / nlt) + (b % 8);
+    if (rt * BM >= a.n_cells) return;          // padding tile: the whole block leaves before any barrier
+    const int row0 = rt * BM;
+    const int col0 = (m % nlt) * BN;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // loaders: thread t stages row (or column) t / 4, k = 8 (t % 4) + 0..7
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    const bool arow_ok = (row0 + lr) < a.n_cells;
+    const float* Arow = a.Pt + static_cast<size_t>(row0 + lr) * a.nb;
+    const size_t boff = static_cast<size_t>(col0 + lr) * a.nbp + lk;
+    const int rl = lane & 15, q = lane >> 4;
+    // the next step's operands are loaded into registers while this step's
+    // products run
+    float4 v0, v1;
+    u32x4c bh, bl;
+    auto fetch = [&](int k0) {
+        v0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        v1 = v0;
+        if (k0 < a.nbp) {
+            if (arow_ok && k0 + lk < a.nb) {      // nb is a multiple of 8: a chunk is wholly inside or outside
+                v0 = *reinterpret_cast<const float4*>(Arow + k0 + lk);
+                v1 = *reinterpret_cast<const float4*>(Arow + k0 + lk + 4);
+            }
+            bh = *reinterpret_cast<const u32x4c*>(a.Bh + boff + k0);
+            bl = *reinterpret_cast<const u32x4c*>(a.Bl + boff + k0);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.nbp; k0 += BK3) {
+        unsigned l0, l1, l2, l3;
+        const unsigned h0 = pack_hi2(v0.x, v0.y, l0), h1 = pack_hi2(v0.z, v0.w, l1);
+        const unsigned h2 = pack_hi2(v1.x, v1.y, l2), h3 = pack_hi2(v1.z, v1.w, l3);
+        const u32x4c ahv = {h0, h1, h2, h3}, alv = {l0, l1, l2, l3};
+        *reinterpret_cast<u32x4c*>(&Ah[lr][lk]) = ahv;
+        *reinterpret_cast<u32x4c*>(&Al[lr][lk]) = alv;
+        *reinterpret_cast<u32x4c*>(&Bhs[lr][lk]) = bh;
+        *reinterpret_cast<u32x4c*>(&Bls[lr][lk]) = bl;
+        __syncthreads();
+        fetch(k0 + BK3);
+        bf16x8c ah[2], al[2], bhf[2], blf[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            ah[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[wr + 16 * t + rl][8 * q]));
+            al[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[wr + 16 * t + rl][8 * q]));
+            bhf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bhs[wc + 16 * t + rl][8 * q]));
+            blf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bls[wc + 16 * t + rl][8 * q]));
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], blf[bj], acc[bi][bj], 0, 0, 0);
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = row0 + wr + bi * 16 + 4 * (lane >> 4) + i;
+            if (row >= a.n_cells) continue;
+            const size_t cell = a.rowmap ? static_cast<size_t>(a.rowmap[row]) : static_cast<size_t>(row);
+            const float ps = a.pscale[cell * a.n_gslots + a.gslot];
+            float* jrow = a.j + (cell * a.n_gslots + a.gslot) * a.L;
+            for (int bj = 0; bj < 2; ++bj) {
+                const int col = col0 + wc + bj * 16 + (lane & 15);
+                if (col < a.L) jrow[col] = acc[bi][bj][i] * ps * a.bscale[col];
+            }
+        }
+    }
+}
+
 // Emitted power of each pair, 4 pi int j dlambda (trapezoid, FP64 sum), one
 // 16-lane segment per pair; the other diagnostics come from the solver.
 __global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
@@ -132,6 +242,11 @@ __global__ void __launch_bounds__(256) k_sizedist(const float* j, const double* 
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
     if (a.n_cells <= 0) return hipSuccess;
     const int nrt8 = ((a.n_cells + BM - 1) / BM + 7) / 8 * 8;
+    if (a.mode == 1) {
+        if (!a.Bh || !a.Bl || a.nbp < a.nb || a.nbp % BK3 != 0 || a.nb % 8 != 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_contract3, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_contract, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

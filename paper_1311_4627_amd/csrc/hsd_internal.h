@@ -60,6 +60,9 @@ struct Grain {
     double* cabs = nullptr;    // [L]
     float* Bt = nullptr;       // [n][Lp] C_abs B_lambda(T_i) [E_i >= hc/lambda] / s_lambda
     float* bscale = nullptr;   // [Lp]   s_lambda (0 where the column is empty)
+    int nbp = 0;               // n rounded up to 32
+    unsigned short* Bh = nullptr;   // [Lp][nbp] Bt transposed as BF16 hi terms (zero padded)
+    unsigned short* Bl = nullptr;   // [Lp][nbp] and lo terms bf16(Bt - hi)
 };
 
 // Kernel-side view of a grain for the solver.
@@ -106,6 +109,7 @@ struct Ctx {
     unsigned* queue = nullptr;    // [kClasses] item counters of persistent launches
     double* sizew = nullptr;      size_t sizew_cap = 0;   // size-distribution weights
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
+    int contract = 1;             // emission contraction: 0 FP32 products, 1 three BF16 products (hi/lo split)
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -161,6 +165,10 @@ struct ContractLaunch {
     float* j;                 // [n_cells][n_gslots][L]
     int n_cells, nb, L, Lp, n_gslots, gslot;   // n_cells: rows of the slot's P~ block
     const int* rowmap = nullptr;              // optional: cell of each row (pair lists)
+    const unsigned short* Bh = nullptr;       // split-BF16 mode: the grain's hi / lo tables [Lp][nbp]
+    const unsigned short* Bl = nullptr;
+    int nbp = 0;
+    int mode = 0;                             // 0 FP32 products, 1 split BF16
 };
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
 

@@ -231,6 +231,20 @@ __global__ void k_planck_scale(int n, int Lp, const double* raw, float* Bt, floa
     bscale[j] = static_cast<float>(m);
 }
 
+// The scaled Planck table as two BF16 terms for the split-BF16 contraction,
+// transposed (wavelength-major) and zero padded to nbp bins:
+// Bh[j][i] = bf16(Bt[i][j]), Bl[j][i] = bf16(Bt[i][j] - Bh[j][i]).
+__global__ void k_planck_split(int n, int Lp, int nbp, const float* Bt, unsigned short* Bh, unsigned short* Bl) {
+    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= static_cast<long long>(Lp) * nbp) return;
+    const int j = static_cast<int>(t / nbp), i = static_cast<int>(t - static_cast<long long>(j) * nbp);
+    const float v = i < n ? Bt[static_cast<size_t>(i) * Lp + j] : 0.f;
+    const __bf16 hi = static_cast<__bf16>(v);
+    const __bf16 lo = static_cast<__bf16>(v - static_cast<float>(hi));
+    Bh[t] = __builtin_bit_cast(unsigned short, hi);
+    Bl[t] = __builtin_bit_cast(unsigned short, lo);
+}
+
 __device__ int first_at_least(const double* lam, int L, double lnlam0, double dlnlam, double x) {
     // first j with lam[j] >= x, L if none; closed-form guess corrected on the actual grid values
     if (!(x > 0.0)) return 0;
@@ -356,6 +370,12 @@ hipError_t build_grain_tables(Ctx& c, Grain& g) {
     if ((e = hipGetLastError()) != hipSuccess) { hipFree(raw); return e; }
     hipLaunchKernelGGL(k_planck_scale, dim3((Lp + 63) / 64), dim3(64), 0, 0, n, Lp, raw, g.Bt, g.bscale);
     if ((e = hipGetLastError()) != hipSuccess) { hipFree(raw); return e; }
+    {
+        const long long tot = static_cast<long long>(Lp) * g.nbp;
+        hipLaunchKernelGGL(k_planck_split, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, 0, n, Lp,
+                           g.nbp, g.Bt, g.Bh, g.Bl);
+        if ((e = hipGetLastError()) != hipSuccess) { hipFree(raw); return e; }
+    }
     hipLaunchKernelGGL(k_tables, dim3((n + 63) / 64), dim3(64), 0, 0, n, L, g.E_lo, g.E_hi, c.lnlam0, c.dlnlam,
                        c.lam, g.E, g.dE, g.cool, g.colpar, g.dpar, g.gam, g.invgap, g.jstar, g.jrep);
     if ((e = hipGetLastError()) != hipSuccess) { hipFree(raw); return e; }

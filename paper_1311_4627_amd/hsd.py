@@ -28,7 +28,7 @@ STATUS_NAMES = {
 SYMBOLS = (
     "hsd_create", "hsd_destroy", "hsd_last_error", "hsd_add_grain", "hsd_grain_tables",
     "hsd_solve", "hsd_solve_P", "hsd_solve_from_rates", "hsd_sync", "hsd_set_timing", "hsd_phase_ms",
-    "hsd_get_class_cfg", "hsd_set_class_cfg", "hsd_plan_create", "hsd_plan_launch", "hsd_plan_phase_ms",
+    "hsd_get_class_cfg", "hsd_set_class_cfg", "hsd_set_contract", "hsd_get_contract", "hsd_plan_create", "hsd_plan_launch", "hsd_plan_phase_ms",
     "hsd_plan_destroy", "hsd_autotune",
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
@@ -37,6 +37,8 @@ SYMBOLS = (
 
 N_CLASSES = 4
 CLASS_BINS = ((513, 1024), (257, 512), (129, 256), (16, 128))   # bin-count range of each solver class
+CONTRACT_FP32 = 0       # emission contraction on FP32 matrix cores
+CONTRACT_BF16X3 = 1     # ... as three BF16 products of hi/lo split operands (the default)
 PLAN_TIMING = 1
 PLAN_CONCURRENT = 2
 CHECK_ABSORBED = 0      # surrogate energy check against the absorbed power A
@@ -102,6 +104,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_get_class_cfg.argtypes = [vp, i32, cp]
     lib.hsd_get_class_cfg.restype = ctypes.c_int
     lib.hsd_set_class_cfg.argtypes = [vp, i32, cp]
+    lib.hsd_set_contract.argtypes = [vp, i32]
+    lib.hsd_set_contract.restype = ctypes.c_int
+    lib.hsd_get_contract.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.hsd_get_contract.restype = ctypes.c_int
     lib.hsd_set_class_cfg.restype = ctypes.c_int
     lib.hsd_plan_create.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, i32, ctypes.POINTER(vp)]
     lib.hsd_plan_create.restype = ctypes.c_int
@@ -290,6 +296,18 @@ class Context:
         st = self._lib.hsd_set_class_cfg(self._h, int(cls), ctypes.byref(c))
         if st != HSD_OK:
             self._raise(st, "hsd_set_class_cfg")
+
+    def hsd_set_contract(self, mode: int):
+        st = self._lib.hsd_set_contract(self._h, int(mode))
+        if st != HSD_OK:
+            self._raise(st, "hsd_set_contract")
+
+    def hsd_get_contract(self) -> int:
+        m = ctypes.c_int32()
+        st = self._lib.hsd_get_contract(self._h, ctypes.byref(m))
+        if st != HSD_OK:
+            self._raise(st, "hsd_get_contract")
+        return int(m.value)
 
     def hsd_autotune(self, u, grain_ids: Sequence[int], runs: int = 4):
         """Time every class configuration on this batch; the context keeps the

@@ -195,6 +195,36 @@ def test_deterministic(hsd, c1):
     assert np.array_equal(outs[0][:, 0], outs[0][:, 1])
 
 
+def test_contraction_modes_agree(hsd):
+    # the split-BF16 contraction (default) against the FP32 one on every pair
+    # of a batched subset: each j within 3 2^-16 of the FP32 result (plus FP32
+    # accumulation order), and a bad mode rejected
+    w = synth.workload("c2_batched")
+    ctx = hsd.Context(w.lam_cm)
+    ids = [ctx.add_grain(g) for g in w.grains]
+    n = 512
+    ud = torch.tensor(make_fields(w.lam_cm, w.field_recipe, w.n_cells, cells=np.arange(n)), device="cuda")
+    assert ctx.hsd_get_contract() == hsd.CONTRACT_BF16X3
+    out = {}
+    for mode in (hsd.CONTRACT_BF16X3, hsd.CONTRACT_FP32):
+        ctx.hsd_set_contract(mode)
+        j = torch.empty((n, len(ids), w.n_lambda), dtype=torch.float32, device="cuda")
+        ctx.hsd_solve(ud, ids, j)
+        ctx.hsd_sync()
+        out[mode] = j.cpu().numpy().astype(np.float64)
+    ctx.hsd_set_contract(hsd.CONTRACT_BF16X3)
+    a, b = out[hsd.CONTRACT_BF16X3], out[hsd.CONTRACT_FP32]
+    # the range the tolerances cover: values down to 1e-10 of the pair's
+    # maximum (far below, products of FP32-subnormal size may round to 0)
+    m = b >= 1e-10 * b.max(axis=-1, keepdims=True)
+    rel = np.abs(a[m] / b[m] - 1)
+    print(f"split BF16 vs FP32 contraction: median {np.median(rel):.2e} max {rel.max():.2e} "
+          f"over {m.sum()} values", flush=True)
+    assert rel.max() < 3 * 2.0 ** -16 + 2e-6
+    with pytest.raises(hsd.HsdError):
+        ctx.hsd_set_contract(2)
+
+
 def test_c2_full_batch_sampled_pairs(hsd):
     # the full batched workload (16384 cells x 32 radii) in one call, as the
     # benchmark runs it; sampled pairs against the oracle
