@@ -171,7 +171,6 @@ def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
         trace = sur.hsd_sur_train(X, Y, steps=steps, batch=batch, lr=lr)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0
-        del X, Y, A
         # held-out cells: plain vs surrogate
         nh = w4.notes["heldout_cells"]
         uh = torch.tensor(make_fields(w4.lam_cm, w4.notes["heldout_recipe"], nh), device="cuda:0")
@@ -188,15 +187,32 @@ def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
         dr = dr.cpu().numpy().reshape(-1, 4).astype(np.float64)
         dp = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
         rerr = np.abs((dp[:, 2] / dp[:, 0]) / (dr[:, 1] / dr[:, 0]) - 1)
+        # the cheap method the surrogate replaces: a table of training spectra
+        # indexed by the field's total energy alone (nearest training cell, same
+        # grain), scaled by the pair's own absorbed power
+        Xh = torch.empty((nh * G, 33), dtype=torch.float32, device="cuda:0")
+        Ah = torch.empty((nh * G,), dtype=torch.float64, device="cuda:0")
+        ctx.hsd_sur_features(uh, sel, Xh, Ah)
+        etot_t = torch.log10((10.0 ** X.view(w4.n_cells, G, 33)[:, 0, :32].double()).sum(dim=1))
+        etot_h = torch.log10((10.0 ** Xh.view(nh, G, 33)[:, 0, :32].double()).sum(dim=1))
+        nn = torch.argmin((etot_h[:, None] - etot_t[None, :]).abs(), dim=1)
+        rows = (nn[:, None] * G + torch.arange(G, device="cuda:0")[None, :]).reshape(-1)
+        jt = (10.0 ** Y.index_select(0, rows)[:, :w4.n_lambda].double()) * Ah[:, None]
+        terr = _band_error(jt.cpu().numpy(), jr.cpu().numpy().reshape(-1, w4.n_lambda), w4.lam_cm)
+        del X, Y, A, Xh, Ah, jt
         report[comp] = {"train_pairs": n, "heldout_pairs": nh * G, "steps": steps, "batch": batch,
                         "data_s": round(gen_s, 2), "train_s": round(train_s, 2),
                         "loss_first": float(np.mean(trace[:20])), "loss_last": float(np.mean(trace[-100:])),
                         "heldout_band_err": {"median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
                                              "p99": float(np.quantile(err, 0.99)), "max": float(err.max())},
                         "heldout_energy_ratio_err": {"median": float(np.median(rerr)),
-                                                     "p99": float(np.quantile(rerr, 0.99)), "max": float(rerr.max())}}
+                                                     "p99": float(np.quantile(rerr, 0.99)), "max": float(rerr.max())},
+                        "table_baseline_band_err": {"median": float(np.median(terr)),
+                                                    "p99": float(np.quantile(terr, 0.99)),
+                                                    "max": float(terr.max())}}
         log(f"{comp}: trained {steps} steps in {train_s:.1f} s; held-out band error median "
-            f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}")
+            f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}; "
+            f"table method median {np.median(terr):.4f} p99 {np.quantile(terr, 0.99):.4f}")
         nets[comp] = sur
     return nets, report
 
@@ -328,6 +344,8 @@ def main():
     ap.add_argument("--cpu-cells", type=int, default=48)
     ap.add_argument("--eager", action="store_true", help="time hsd_solve calls instead of plan replays")
     ap.add_argument("--retune", action="store_true", help="time the launch configurations again")
+    ap.add_argument("--contract", choices=("bf16x3", "fp32"), default="bf16x3",
+                    help="emission contraction: three BF16 products of split operands, or FP32")
     ap.add_argument("--no-persistent", action="store_true",
                     help="launch every class as an ordinary grid (what a concurrent plan launches; for counter runs)")
     ap.add_argument("--train-steps", type=int, default=60000, help="surrogate training steps per composition")
@@ -362,6 +380,7 @@ def main():
 
     w = synth.workload(args.workload)
     ctx = hsd.Context(w.lam_cm, device=0)
+    ctx.hsd_set_contract(hsd.CONTRACT_FP32 if args.contract == "fp32" else hsd.CONTRACT_BF16X3)
     t0 = time.perf_counter()
     ids = [ctx.add_grain(g) for g in w.grains]
     setup_s = time.perf_counter() - t0
@@ -452,6 +471,7 @@ def main():
                    "bins": f"{max(g.n_bins for g in w.grains)}..{min(g.n_bins for g in w.grains)} "
                            f"(sum {sum(g.n_bins for g in w.grains)})",
                    "launch": "eager" if plan is None else "plan (HIP graphs, concurrent classes)",
+                   "contraction": args.contract,
                    "class_cfg": launched},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": EXP2_PEAK / 1e12, "unit": "Texp2/s",
                      "frac": achieved / EXP2_PEAK, "traffic": recorded_traffic(),
