@@ -335,7 +335,9 @@ hsd_status hsd_sur_loss_grad(hsd_sur* sur, int32_t n, const float* X_dev, const 
  * `seed`; learning rate warms up linearly over the first 2% of steps, then
  * decays as a cosine to 5% of `lr`.  loss_host (optional) receives each
  * step's minibatch loss.  Optimiser state carries over between calls until
- * hsd_sur_set_params.  Synchronous. */
+ * hsd_sur_set_params.  On return the parameters are the exponential moving
+ * average of the call's iterates (decay min(0.999, 1 - 20 / steps), started
+ * from the parameters at the call).  Synchronous. */
 hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps,
                          int32_t batch, float lr, uint64_t seed, float* loss_host);
 /* Energy checks of hsd_solve_surrogate.  With E the surrogate's emitted

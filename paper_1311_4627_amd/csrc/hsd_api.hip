@@ -1092,6 +1092,11 @@ hsd_status hsd_sur_train(hsd_sur* p, int64_t n, const float* X_dev, const float*
     if (loss_host && steps > 0) HSD_HIP(ctx, hipMalloc(&trace, sizeof(double) * steps));
     hipError_t e = hipSuccess;
     const int warm = std::max(1, steps / 50);
+    // the trained parameters are the moving average of the iterates (decay
+    // min(0.999, 1 - 20 / steps)), which smooths the last steps' noise
+    const float ema_decay = static_cast<float>(std::min(0.999, 1.0 - 20.0 / std::max(steps, 1)));
+    const bool ema = steps > 0 && ema_decay > 0.f;
+    if (ema) e = hipMemcpyAsync(s.we, s.w, sizeof(float) * s.n_params, hipMemcpyDeviceToDevice, st);
     for (int k = 0; k < steps && e == hipSuccess; ++k) {
         // linear warm-up, then cosine decay to 5% of lr
         double f = 1.0;
@@ -1104,7 +1109,11 @@ hsd_status hsd_sur_train(hsd_sur* p, int64_t n, const float* X_dev, const float*
         if (e == hipSuccess && trace)
             e = hipMemcpyAsync(trace + k, s.loss, sizeof(double), hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hsd::sur_backward(s, batch, s.Xb, st);
-        if (e == hipSuccess) e = hsd::sur_adam(s, static_cast<float>(lr * f), st);
+        if (e == hipSuccess) e = hsd::sur_adam(s, static_cast<float>(lr * f), st, ema, ema_decay);
+    }
+    if (e == hipSuccess && ema) {
+        e = hipMemcpyAsync(s.w, s.we, sizeof(float) * s.n_params, hipMemcpyDeviceToDevice, st);
+        s.wb_fresh = false;
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess && trace) {

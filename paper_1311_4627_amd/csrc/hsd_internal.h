@@ -203,6 +203,7 @@ struct Sur {
     float* g = nullptr;        // gradients
     float* m = nullptr;        // Adam moments
     float* v = nullptr;
+    float* we = nullptr;       // moving average of the weights over the training steps
     long long t = 0;           // Adam steps taken
     float* xm = nullptr;       // [33] input means / stds
     float* xs = nullptr;
@@ -239,7 +240,7 @@ hipError_t sur_loss(Sur& s, int B, hipStream_t st);
 hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st);
 hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st);
 hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
-hipError_t sur_adam(Sur& s, float lr, hipStream_t st);
+hipError_t sur_adam(Sur& s, float lr, hipStream_t st, bool ema = false, float ema_decay = 0.f);
 hipError_t sur_pack(Sur& s, hipStream_t st);
 hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
                           int n_slots, const int* sel, float* j, float* emit, float* rho, unsigned short* h0,

@@ -324,8 +324,10 @@ __global__ void __launch_bounds__(256) k_colsum(const float* dz, int B, int N, f
 }
 
 // Adam (Kingma & Ba) with bias correction folded into the step size.
+// One Adam step; we (if given) follows the iterates as a moving average,
+// we = ed we + (1 - ed) w.
 __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m, float* v, long long n, float lr_t,
-                                              float b1, float b2, float eps_t) {
+                                              float b1, float b2, float eps_t, float* we, float ed) {
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -333,7 +335,9 @@ __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    w[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+    const float wi = w[i] - lr_t * mi / (sqrtf(vi) + eps_t);
+    w[i] = wi;
+    if (we) we[i] = fmaf(ed, we[i] - wi, wi);
 }
 
 // ---- BF16 matrix-core GEMM ----------------------------------------------------------
@@ -855,7 +859,7 @@ hipError_t sur_alloc(Sur& s) {
     auto al = [&](auto*& p, size_t n) {
         if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
     };
-    al(s.w, s.n_params); al(s.g, s.n_params); al(s.m, s.n_params); al(s.v, s.n_params);
+    al(s.w, s.n_params); al(s.g, s.n_params); al(s.m, s.n_params); al(s.v, s.n_params); al(s.we, s.n_params);
     al(s.xm, 33); al(s.xs, 33); al(s.ym, s.n_out); al(s.ys, s.n_out); al(s.wq, s.n_out); al(s.loss, 1);
     if (e == hipSuccess) e = hipMemset(s.m, 0, sizeof(float) * s.n_params);
     if (e == hipSuccess) e = hipMemset(s.v, 0, sizeof(float) * s.n_params);
@@ -873,7 +877,7 @@ hipError_t sur_alloc(Sur& s) {
 }
 
 void sur_free(Sur& s) {
-    for (float* p : {s.w, s.g, s.m, s.v, s.xm, s.xs, s.ym, s.ys, s.wq, s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
+    for (float* p : {s.w, s.g, s.m, s.v, s.we, s.xm, s.xs, s.ym, s.ys, s.wq, s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
     for (int i = 0; i < 3; ++i) {
         (void)hipFree(s.Z[i]);
         (void)hipFree(s.H[i]);
@@ -1088,7 +1092,7 @@ hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st) {
     return e;
 }
 
-hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
+hipError_t sur_adam(Sur& s, float lr, hipStream_t st, bool ema, float ema_decay) {
     ++s.t;
     s.wb_fresh = false;
     const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
@@ -1098,7 +1102,7 @@ hipError_t sur_adam(Sur& s, float lr, hipStream_t st) {
     const float lr_t = static_cast<float>(lr * std::sqrt(c2) / c1);
     const float eps_t = static_cast<float>(eps * std::sqrt(c2));
     hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((s.n_params + 255) / 256)), dim3(256), 0, st, s.w, s.g,
-                       s.m, s.v, s.n_params, lr_t, 0.9f, 0.999f, eps_t);
+                       s.m, s.v, s.n_params, lr_t, 0.9f, 0.999f, eps_t, ema ? s.we : nullptr, ema_decay);
     return hipGetLastError();
 }
 
