@@ -422,7 +422,7 @@ hsd_status hsd_add_grain(hsd_ctx* ctx, const hsd_grain_desc* d, int32_t* grain_i
     al(g.E, n); al(g.dE, n); al(g.T, n); al(g.cool, n); al(g.colpar, n); al(g.dpar, n); al(g.gam, n);
     al(g.invgap, n); al(g.jstar, n); al(g.jrep, n); al(g.cabs, c.L); al(g.Bt, static_cast<size_t>(n) * Lp);
     al(g.bscale, Lp);
-    g.nbp = (n + 31) / 32 * 32;
+    g.nbp = (n + 63) / 64 * 64;
     al(g.Bh, Lp * static_cast<size_t>(g.nbp)); al(g.Bl, Lp * static_cast<size_t>(g.nbp));
     if (e == hipSuccess) e = hipMemcpy(g.cabs, d->cabs_host, sizeof(double) * c.L, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hsd::build_grain_tables(c, g);

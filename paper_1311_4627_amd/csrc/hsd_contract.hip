@@ -19,7 +19,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int APAD = 1, BPAD = 4;
-constexpr int BK3 = 32, LK3 = BK3 + 8;      // split-BF16 kernel: k per step, LDS row length (ushorts)
+constexpr int BK3 = 64, LK3 = BK3 + 8;      // split-BF16 kernel: k per step, LDS row length (ushorts)
 
 // One 256-thread block computes a 64 (cells) x 64 (wavelengths) tile; each of
 // its four waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 blocks.
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
 // FP32 on v_mfma_f32_16x16x32_bf16 (16 times the FP32 matrix-core rate; the
 // dropped lo lo term and the split's remainders keep every product within
 // 3 2^-16 of exact).  P~ is split as it is staged in LDS; the grain's table
-// comes pre-split and transposed (Bh, Bl: [Lp][nbp]).  Same tiles, XCD order
+// comes pre-split and transposed (Bh, Bl: [Lp][nbp], nbp a multiple of 64).  Same tiles, XCD order
 // and epilogue as k_contract; in step s lane l supplies row l % 16 of its A
 // block with k = 8 (l / 16) + 0..7 and column l % 16 of its B block with the
 // same k, so every product still sums over each k once.
@@ -136,56 +136,66 @@ __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // loaders: thread t stages row (or column) t / 4, k = 8 (t % 4) + 0..7
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    // loaders: thread t stages row (or column) t / 4, k = 16 (t % 4) + 0..15
+    const int lr = tid >> 2, lk = (tid & 3) * 16;
     const bool arow_ok = (row0 + lr) < a.n_cells;
     const float* Arow = a.Pt + static_cast<size_t>(row0 + lr) * a.nb;
     const size_t boff = static_cast<size_t>(col0 + lr) * a.nbp + lk;
     const int rl = lane & 15, q = lane >> 4;
     // the next step's operands are loaded into registers while this step's
     // products run
-    float4 v0, v1;
-    u32x4c bh, bl;
+    float4 v[4];
+    u32x4c bh[2], bl[2];
     auto fetch = [&](int k0) {
-        v0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        v1 = v0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (k0 < a.nbp) {
-            if (arow_ok && k0 + lk < a.nb) {      // nb is a multiple of 8: a chunk is wholly inside or outside
-                v0 = *reinterpret_cast<const float4*>(Arow + k0 + lk);
-                v1 = *reinterpret_cast<const float4*>(Arow + k0 + lk + 4);
+            if (arow_ok && k0 + lk < a.nb) {      // nb is a multiple of 16: a chunk is wholly inside or outside
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] = *reinterpret_cast<const float4*>(Arow + k0 + lk + 4 * c);
             }
-            bh = *reinterpret_cast<const u32x4c*>(a.Bh + boff + k0);
-            bl = *reinterpret_cast<const u32x4c*>(a.Bl + boff + k0);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                bh[c] = *reinterpret_cast<const u32x4c*>(a.Bh + boff + k0 + 8 * c);
+                bl[c] = *reinterpret_cast<const u32x4c*>(a.Bl + boff + k0 + 8 * c);
+            }
         }
     };
     fetch(0);
     for (int k0 = 0; k0 < a.nbp; k0 += BK3) {
-        unsigned l0, l1, l2, l3;
-        const unsigned h0 = pack_hi2(v0.x, v0.y, l0), h1 = pack_hi2(v0.z, v0.w, l1);
-        const unsigned h2 = pack_hi2(v1.x, v1.y, l2), h3 = pack_hi2(v1.z, v1.w, l3);
-        const u32x4c ahv = {h0, h1, h2, h3}, alv = {l0, l1, l2, l3};
-        *reinterpret_cast<u32x4c*>(&Ah[lr][lk]) = ahv;
-        *reinterpret_cast<u32x4c*>(&Al[lr][lk]) = alv;
-        *reinterpret_cast<u32x4c*>(&Bhs[lr][lk]) = bh;
-        *reinterpret_cast<u32x4c*>(&Bls[lr][lk]) = bl;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            unsigned l0, l1, l2, l3;
+            const unsigned h0 = pack_hi2(v[2 * c].x, v[2 * c].y, l0), h1 = pack_hi2(v[2 * c].z, v[2 * c].w, l1);
+            const unsigned h2 = pack_hi2(v[2 * c + 1].x, v[2 * c + 1].y, l2);
+            const unsigned h3 = pack_hi2(v[2 * c + 1].z, v[2 * c + 1].w, l3);
+            const u32x4c ahv = {h0, h1, h2, h3}, alv = {l0, l1, l2, l3};
+            *reinterpret_cast<u32x4c*>(&Ah[lr][lk + 8 * c]) = ahv;
+            *reinterpret_cast<u32x4c*>(&Al[lr][lk + 8 * c]) = alv;
+            *reinterpret_cast<u32x4c*>(&Bhs[lr][lk + 8 * c]) = bh[c];
+            *reinterpret_cast<u32x4c*>(&Bls[lr][lk + 8 * c]) = bl[c];
+        }
         __syncthreads();
         fetch(k0 + BK3);
-        bf16x8c ah[2], al[2], bhf[2], blf[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            ah[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[wr + 16 * t + rl][8 * q]));
-            al[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[wr + 16 * t + rl][8 * q]));
-            bhf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bhs[wc + 16 * t + rl][8 * q]));
-            blf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bls[wc + 16 * t + rl][8 * q]));
-        }
+        for (int ks = 0; ks < BK3; ks += 32) {
+            bf16x8c ah[2], al[2], bhf[2], blf[2];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], blf[bj], acc[bi][bj], 0, 0, 0);
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+            for (int t = 0; t < 2; ++t) {
+                ah[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[wr + 16 * t + rl][ks + 8 * q]));
+                al[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[wr + 16 * t + rl][ks + 8 * q]));
+                bhf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bhs[wc + 16 * t + rl][ks + 8 * q]));
+                blf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bls[wc + 16 * t + rl][ks + 8 * q]));
             }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], blf[bj], acc[bi][bj], 0, 0, 0);
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+                }
+        }
         __syncthreads();
     }
 #pragma unroll
@@ -243,7 +253,7 @@ hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
     if (a.n_cells <= 0) return hipSuccess;
     const int nrt8 = ((a.n_cells + BM - 1) / BM + 7) / 8 * 8;
     if (a.mode == 1) {
-        if (!a.Bh || !a.Bl || a.nbp < a.nb || a.nbp % BK3 != 0 || a.nb % 8 != 0) return hipErrorInvalidValue;
+        if (!a.Bh || !a.Bl || a.nbp < a.nb || a.nbp % BK3 != 0 || a.nb % 16 != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_contract3, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
         return hipGetLastError();
     }

@@ -60,7 +60,7 @@ struct Grain {
     double* cabs = nullptr;    // [L]
     float* Bt = nullptr;       // [n][Lp] C_abs B_lambda(T_i) [E_i >= hc/lambda] / s_lambda
     float* bscale = nullptr;   // [Lp]   s_lambda (0 where the column is empty)
-    int nbp = 0;               // n rounded up to 32
+    int nbp = 0;               // n rounded up to 64
     unsigned short* Bh = nullptr;   // [Lp][nbp] Bt transposed as BF16 hi terms (zero padded)
     unsigned short* Bl = nullptr;   // [Lp][nbp] and lo terms bf16(Bt - hi)
 };
