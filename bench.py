@@ -362,8 +362,8 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design note, "
-              f"not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no multi-GPU path "
+              f"(its sharding is described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload in ("c4_train", "c5_surrogate"):

@@ -273,7 +273,7 @@ void hsd_plan_destroy(hsd_plan* plan);
 /* ---- Learned surrogate ----
  * Not part of the paper's method: a learned approximation of it (the paper's
  * introduction names precomputed emissivity tables as the cheap alternative
- * to the full solve), with the plain solve as its fallback and its judge.
+ * to the full solve), with the plain solve as its fallback and its accuracy reference.
  * One network maps a (field, grain) pair to its spectrum:
  *   inputs   x [33]: log10 of the field's energy int u dlambda in 32 bands of
  *            the wavelength grid (band b spans the grid nodes
