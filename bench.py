@@ -25,7 +25,10 @@ values recorded there.
 The CPU baseline is the FP64 oracle timed on the host cores over a bounded,
 stratified sample of the same workload (a few cells times every radius); the
 one-time per-grain setup is excluded, as the GPU's per-grain precompute is.
-It runs before anything touches the GPU.
+It runs before anything touches the GPU.  The oracle's spectra of that sample
+are then compared with the timed run's own output for the same pairs
+(oracle_error: the largest relative error on j_lambda over the wavelengths
+within 1e-10 of each spectrum's maximum, against the 1e-4 bar).
 """
 
 from __future__ import annotations
@@ -48,6 +51,7 @@ import synth  # noqa: E402
 from synth.fields import make_fields  # noqa: E402
 
 METRIC = "emissivity solves/s (cell×grain) at 1e-4 rel err; surrogate vs plain speedup"
+J_TOL = 1e-4                                 # end-to-end bar on j_lambda against the oracle
 EXP2_PEAK = 157.3e12 / 2 / 4                 # v_exp_f32 per second: a quarter of the FP32 FMA rate
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_c2_hbm_traffic.md")
 TUNE_CACHE = os.path.join(ROOT, "paper_1311_4627_amd", "tuned.json")
@@ -87,12 +91,14 @@ def _oracle_task(args):
     u = make_fields(w.lam_cm, w.field_recipe, w.n_cells, cells=np.asarray(cells))
     oracle.grain_setup(g, w.lam_cm)                       # one-time setup, not timed
     t0 = time.perf_counter()
-    for c in range(len(cells)):
-        oracle.solve_pair(u[c], g, w.lam_cm)
-    return time.perf_counter() - t0, len(cells)
+    js = [oracle.solve_pair(u[c], g, w.lam_cm)[1] for c in range(len(cells))]
+    return time.perf_counter() - t0, len(cells), gi, list(cells), np.stack(js)
 
 
-def cpu_baseline(name: str, cells_per_grain: int) -> dict:
+def cpu_baseline(name: str, cells_per_grain: int):
+    """The oracle timed over a seeded sample of the workload's pairs; returns
+    the baseline record and the oracle's spectra of the sample as
+    (grain index, cells, j [cells][L]) triples."""
     w = synth.workload(name)
     cores = min(16, os.cpu_count() or 1)
     rng = np.random.default_rng(4627)
@@ -109,9 +115,32 @@ def cpu_baseline(name: str, cells_per_grain: int) -> dict:
     pairs = sum(r[1] for r in res)
     # pairs per second of solve work on `cores` cores (setup excluded)
     rate = pairs / busy * cores
-    return {"value": rate, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{cells_per_grain} seeded cells x {len(w.grains)} radii of {name} "
-                      f"({pairs} pairs, {busy:.1f} core-s of solve work, {wall:.1f} s wall incl. per-grain setup)"}
+    rec = {"value": rate, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{cells_per_grain} seeded cells x {len(w.grains)} radii of {name} "
+                     f"({pairs} pairs, {busy:.1f} core-s of solve work, {wall:.1f} s wall incl. per-grain setup)"}
+    return rec, [(r[2], r[3], r[4]) for r in res]
+
+
+def j_rel_err(j: np.ndarray, jref: np.ndarray) -> float:
+    """Largest |j / j_ref - 1| over the wavelengths where j_ref is at least
+    1e-10 of the spectrum's maximum (the range the 1e-4 bar covers)."""
+    if jref.max() <= 0.0:
+        return 0.0 if np.all(j == 0.0) else math.inf
+    m = jref >= 1e-10 * jref.max()
+    return float(np.max(np.abs(j[m] / jref[m] - 1.0))) if np.any(m) else 0.0
+
+
+def oracle_error(j, samples) -> dict:
+    """Error of the timed run's last spectra against the oracle's, pair by pair."""
+    import torch
+    worst, n = 0.0, 0
+    for gi, cells, jr in samples:
+        idx = torch.tensor(cells, dtype=torch.long, device=j.device)
+        got = j[:, gi].index_select(0, idx).cpu().numpy().astype(np.float64)
+        for c in range(len(cells)):
+            worst = max(worst, j_rel_err(got[c], jr[c]))
+            n += 1
+    return {"pairs": n, "max_rel_err_j": worst, "tol": J_TOL, "within_tol": bool(worst <= J_TOL)}
 
 
 def count_rates(ctx_tables, lam, grain) -> int:
@@ -372,7 +401,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, args.cpu_cells)
+        cpu, samples = cpu_baseline(args.workload, args.cpu_cells)
         print(f"cpu baseline: {cpu['value']:.1f} solves/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     import torch
@@ -484,6 +513,9 @@ def main():
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu
+        # the same sampled pairs, solved in the timed run, against the oracle
+        line["oracle_error"] = oracle_error(j, samples)
+        print(f"oracle check: {line['oracle_error']}", file=sys.stderr, flush=True)
     print(json.dumps(line))
 
 
