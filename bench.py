@@ -172,77 +172,109 @@ def _band_error(jp, jr, lam):
     return np.where(m, np.abs(J / np.where(m, Jr, 1.0) - 1.0), 0.0).max(axis=1)
 
 
-def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log):
-    """Per composition: plain-solve the training cells, build inputs and
-    targets, fit the statistics and train; then the held-out band errors."""
+def radius_groups(grains, comp: str, n_groups: int):
+    """The composition's grains split into n_groups ranges of consecutive
+    radii (the workloads list radii in increasing order): (index, grain)
+    lists, one network each."""
+    sel = [(i, g) for i, g in enumerate(grains) if g.composition == comp]
+    G = len(sel)
+    return [sel[q * G // n_groups:(q + 1) * G // n_groups] for q in range(n_groups)]
+
+
+def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log, n_groups=4):
+    """Per composition and range of radii: plain-solve the training cells for
+    those radii, build inputs and targets, fit the statistics and train one
+    network; then the held-out band errors.  Returns the networks keyed by
+    grain index and a report per composition."""
     from synth import surrogate as ssur
     nets, report = {}, {}
+    u = torch.tensor(make_fields(w4.lam_cm, w4.field_recipe, w4.n_cells), device="cuda:0")
+    nh = w4.notes["heldout_cells"]
+    uh = torch.tensor(make_fields(w4.lam_cm, w4.notes["heldout_recipe"], nh), device="cuda:0")
     for comp in ("carbonaceous", "silicate"):
-        sel = [i for i, g in zip(ids, w4.grains) if g.composition == comp]
-        G = len(sel)
-        t0 = time.perf_counter()
-        u = torch.tensor(make_fields(w4.lam_cm, w4.field_recipe, w4.n_cells), device="cuda:0")
-        n = w4.n_cells * G
-        j = torch.empty((w4.n_cells, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
-        ctx.hsd_solve(u, sel, j, None)
-        X = torch.empty((n, 33), dtype=torch.float32, device="cuda:0")
-        A = torch.empty((n,), dtype=torch.float64, device="cuda:0")
-        ctx.hsd_sur_features(u, sel, X, A)
-        Y = torch.empty((n, ssur.n_outputs(w4.n_lambda)), dtype=torch.float32, device="cuda:0")
-        ctx.hsd_sur_targets(j.view(n, w4.n_lambda), A, Y)
-        ctx.hsd_sync()
-        del j, u
-        gen_s = time.perf_counter() - t0
-        sur = hsd.Surrogate(ctx)
-        sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(w4.n_lambda)))
-        sur.hsd_sur_fit_norm(X, Y)
-        t0 = time.perf_counter()
-        trace = sur.hsd_sur_train(X, Y, steps=steps, batch=batch, lr=lr)
-        torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
-        # held-out cells: plain vs surrogate
-        nh = w4.notes["heldout_cells"]
-        uh = torch.tensor(make_fields(w4.lam_cm, w4.notes["heldout_recipe"], nh), device="cuda:0")
-        jr = torch.empty((nh, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
-        jp = torch.empty_like(jr)
-        dr = torch.empty((nh, G, 4), dtype=torch.float32, device="cuda:0")
-        dp = torch.empty_like(dr)
-        ctx.hsd_solve(uh, sel, jr, dr)
-        sur.hsd_sur_predict(uh, sel, jp, dp)
-        ctx.hsd_sync()
-        err = _band_error(jp.cpu().numpy().reshape(-1, w4.n_lambda), jr.cpu().numpy().reshape(-1, w4.n_lambda),
-                          w4.lam_cm)
-        # the energy-ratio output against the plain model's emitted / absorbed
-        dr = dr.cpu().numpy().reshape(-1, 4).astype(np.float64)
-        dp = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
-        rerr = np.abs((dp[:, 2] / dp[:, 0]) / (dr[:, 1] / dr[:, 0]) - 1)
-        # the cheap method the surrogate replaces: a table of training spectra
-        # indexed by the field's total energy alone (nearest training cell, same
-        # grain), scaled by the pair's own absorbed power
-        Xh = torch.empty((nh * G, 33), dtype=torch.float32, device="cuda:0")
-        Ah = torch.empty((nh * G,), dtype=torch.float64, device="cuda:0")
-        ctx.hsd_sur_features(uh, sel, Xh, Ah)
-        etot_t = torch.log10((10.0 ** X.view(w4.n_cells, G, 33)[:, 0, :32].double()).sum(dim=1))
-        etot_h = torch.log10((10.0 ** Xh.view(nh, G, 33)[:, 0, :32].double()).sum(dim=1))
-        nn = torch.argmin((etot_h[:, None] - etot_t[None, :]).abs(), dim=1)
-        rows = (nn[:, None] * G + torch.arange(G, device="cuda:0")[None, :]).reshape(-1)
-        jt = (10.0 ** Y.index_select(0, rows)[:, :w4.n_lambda].double()) * Ah[:, None]
-        terr = _band_error(jt.cpu().numpy(), jr.cpu().numpy().reshape(-1, w4.n_lambda), w4.lam_cm)
-        del X, Y, A, Xh, Ah, jt
-        report[comp] = {"train_pairs": n, "heldout_pairs": nh * G, "steps": steps, "batch": batch,
-                        "data_s": round(gen_s, 2), "train_s": round(train_s, 2),
-                        "loss_first": float(np.mean(trace[:20])), "loss_last": float(np.mean(trace[-100:])),
+        errs, rerrs, terrs, groups = [], [], [], []
+        n_tot, gen_tot, train_tot, loss_first, loss_last = 0, 0.0, 0.0, [], []
+        for part in radius_groups(w4.grains, comp, n_groups):
+            sel = [ids[i] for i, _ in part]
+            G = len(sel)
+            t0 = time.perf_counter()
+            n = w4.n_cells * G
+            j = torch.empty((w4.n_cells, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+            ctx.hsd_solve(u, sel, j, None)
+            X = torch.empty((n, 33), dtype=torch.float32, device="cuda:0")
+            A = torch.empty((n,), dtype=torch.float64, device="cuda:0")
+            ctx.hsd_sur_features(u, sel, X, A)
+            Y = torch.empty((n, ssur.n_outputs(w4.n_lambda)), dtype=torch.float32, device="cuda:0")
+            ctx.hsd_sur_targets(j.view(n, w4.n_lambda), A, Y)
+            ctx.hsd_sync()
+            del j
+            gen_s = time.perf_counter() - t0
+            sur = hsd.Surrogate(ctx)
+            sur.hsd_sur_set_params(ssur.init_params(ssur.n_outputs(w4.n_lambda)))
+            sur.hsd_sur_fit_norm(X, Y)
+            t0 = time.perf_counter()
+            trace = sur.hsd_sur_train(X, Y, steps=steps, batch=batch, lr=lr)
+            torch.cuda.synchronize()
+            train_s = time.perf_counter() - t0
+            # held-out cells: plain vs surrogate
+            jr = torch.empty((nh, G, w4.n_lambda), dtype=torch.float32, device="cuda:0")
+            jp = torch.empty_like(jr)
+            dr = torch.empty((nh, G, 4), dtype=torch.float32, device="cuda:0")
+            dp = torch.empty_like(dr)
+            ctx.hsd_solve(uh, sel, jr, dr)
+            sur.hsd_sur_predict(uh, sel, jp, dp)
+            ctx.hsd_sync()
+            err = _band_error(jp.cpu().numpy().reshape(-1, w4.n_lambda), jr.cpu().numpy().reshape(-1, w4.n_lambda),
+                              w4.lam_cm)
+            # the energy-ratio output against the plain model's emitted / absorbed
+            drn = dr.cpu().numpy().reshape(-1, 4).astype(np.float64)
+            dpn = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
+            rerr = np.abs((dpn[:, 2] / dpn[:, 0]) / (drn[:, 1] / drn[:, 0]) - 1)
+            # the cheap method the surrogate replaces: a table of training spectra
+            # indexed by the field's total energy alone (nearest training cell, same
+            # grain), scaled by the pair's own absorbed power
+            Xh = torch.empty((nh * G, 33), dtype=torch.float32, device="cuda:0")
+            Ah = torch.empty((nh * G,), dtype=torch.float64, device="cuda:0")
+            ctx.hsd_sur_features(uh, sel, Xh, Ah)
+            etot_t = torch.log10((10.0 ** X.view(w4.n_cells, G, 33)[:, 0, :32].double()).sum(dim=1))
+            etot_h = torch.log10((10.0 ** Xh.view(nh, G, 33)[:, 0, :32].double()).sum(dim=1))
+            nn = torch.argmin((etot_h[:, None] - etot_t[None, :]).abs(), dim=1)
+            rows = (nn[:, None] * G + torch.arange(G, device="cuda:0")[None, :]).reshape(-1)
+            jt = (10.0 ** Y.index_select(0, rows)[:, :w4.n_lambda].double()) * Ah[:, None]
+            terr = _band_error(jt.cpu().numpy(), jr.cpu().numpy().reshape(-1, w4.n_lambda), w4.lam_cm)
+            del X, Y, A, Xh, Ah, jt, jr, jp, dr, dp
+            r0, r1 = part[0][1].radius_cm * 1e8, part[-1][1].radius_cm * 1e8
+            groups.append({"radii_A": [round(r0, 1), round(r1, 1)], "train_pairs": n,
+                           "heldout_band_err": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+                                                "max": float(err.max())}})
+            log(f"{comp} {r0:.1f}-{r1:.1f} A: trained {steps} steps in {train_s:.1f} s; held-out band error median "
+                f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}")
+            errs.append(err)
+            rerrs.append(rerr)
+            terrs.append(terr)
+            n_tot += n
+            gen_tot += gen_s
+            train_tot += train_s
+            loss_first.append(float(np.mean(trace[:20])))
+            loss_last.append(float(np.mean(trace[-100:])))
+            for i, _ in part:
+                nets[i] = sur
+        err, rerr, terr = np.concatenate(errs), np.concatenate(rerrs), np.concatenate(terrs)
+        report[comp] = {"train_pairs": n_tot, "heldout_pairs": int(err.size), "networks": len(groups),
+                        "steps": steps, "batch": batch, "data_s": round(gen_tot, 2), "train_s": round(train_tot, 2),
+                        "loss_first": float(np.mean(loss_first)), "loss_last": float(np.mean(loss_last)),
                         "heldout_band_err": {"median": float(np.median(err)), "p90": float(np.quantile(err, 0.9)),
                                              "p99": float(np.quantile(err, 0.99)), "max": float(err.max())},
                         "heldout_energy_ratio_err": {"median": float(np.median(rerr)),
                                                      "p99": float(np.quantile(rerr, 0.99)), "max": float(rerr.max())},
                         "table_baseline_band_err": {"median": float(np.median(terr)),
                                                     "p99": float(np.quantile(terr, 0.99)),
-                                                    "max": float(terr.max())}}
-        log(f"{comp}: trained {steps} steps in {train_s:.1f} s; held-out band error median "
-            f"{np.median(err):.4f} p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}; "
+                                                    "max": float(terr.max())},
+                        "per_radius_range": groups}
+        log(f"{comp}: {len(groups)} networks; held-out band error median {np.median(err):.4f} "
+            f"p99 {np.quantile(err, 0.99):.4f} max {err.max():.4f}; "
             f"table method median {np.median(terr):.4f} p99 {np.quantile(terr, 0.99):.4f}")
-        nets[comp] = sur
+    del u, uh
     return nets, report
 
 
@@ -256,23 +288,26 @@ def bench_surrogate(args):
     w4 = synth.workload("c4_train")
     ctx = hsd.Context(w4.lam_cm, device=0)
     ids = [ctx.add_grain(g) for g in w4.grains]
-    nets, report = train_surrogates(torch, hsd, ctx, w4, ids, args.train_steps, 4096, 4e-3, log)
+    nets, report = train_surrogates(torch, hsd, ctx, w4, ids, args.train_steps, 4096, 4e-3, log,
+                                    args.radius_groups)
     if args.workload == "c4_train":
         tot_pairs = sum(r["train_pairs"] for r in report.values())
         tot_s = sum(r["train_s"] for r in report.values())
+        n_nets = sum(r["networks"] for r in report.values())
         line = {"metric": "surrogate training: samples per second (held-out band errors reported)",
-                "value": args.train_steps * 4096 * len(report) / tot_s, "unit": "samples/s", "n_gpus": 1,
-                "steps": args.train_steps, "warmup": 0, "ms_per_step": 1e3 * tot_s / (args.train_steps * len(report)),
+                "value": args.train_steps * 4096 * n_nets / tot_s, "unit": "samples/s", "n_gpus": 1,
+                "steps": args.train_steps, "warmup": 0, "ms_per_step": 1e3 * tot_s / (args.train_steps * n_nets),
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 matmul, f32 master",
                 "data": "synthetic", "config": {"workload": "c4_train", "train_pairs": tot_pairs,
-                                                "net": "33-256-256-256-501 GELU"},
+                                                "net": "33-256-256-256-501 GELU",
+                                                "networks_per_composition": args.radius_groups},
                 "per_composition": report}
         print(json.dumps(line))
         return
     # c5: 262144 cells x 64 radii x 2 compositions, plain vs surrogate + fallback
     w5 = synth.workload("c5_surrogate")
-    assert [g.radius_cm for g in w5.grains] == [g.radius_cm for g in w4.grains]
-    surs = [nets[g.composition] for g in w5.grains]
+    assert [(g.composition, g.radius_cm) for g in w5.grains] == [(g.composition, g.radius_cm) for g in w4.grains]
+    surs = [nets[gi] for gi in range(len(w5.grains))]
     u = torch.tensor(make_fields(w5.lam_cm, w5.field_recipe, w5.n_cells), device="cuda:0")
     G = len(ids)
     jpl = torch.empty((w5.n_cells, G, w5.n_lambda), dtype=torch.float32, device="cuda:0")
@@ -311,11 +346,19 @@ def bench_surrogate(args):
     # the network alone (every pair), timed with HIP events around its kernels
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     carb = [i for i, g in zip(ids, w5.grains) if g.composition == "carbonaceous"]
-    jn = torch.empty((w5.n_cells, len(carb), w5.n_lambda), dtype=torch.float32, device="cuda:0")
-    nets["carbonaceous"].hsd_sur_predict(u, carb, jn, None)
+    parts = radius_groups(w5.grains, "carbonaceous", args.radius_groups)
+    jn = {len(p): torch.empty((w5.n_cells, len(p), w5.n_lambda), dtype=torch.float32, device="cuda:0")
+          for p in parts}
+
+    def net_pass():
+        # one composition: each range's network over its radii
+        for p in parts:
+            nets[p[0][0]].hsd_sur_predict(u, [ids[i] for i, _ in p], jn[len(p)], None, stream)
+
+    net_pass()
     torch.cuda.synchronize()
     ev0.record(stream)
-    nets["carbonaceous"].hsd_sur_predict(u, carb, jn, None, stream)
+    net_pass()
     ev1.record(stream)
     torch.cuda.synchronize()
     t_net = ev0.elapsed_time(ev1) * 1e-3
@@ -343,7 +386,8 @@ def bench_surrogate(args):
             "warmup": 1, "ms_per_step": t_sur * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "bf16 matmul + f32/f64 fallback", "data": "synthetic",
             "config": {"workload": "c5_surrogate", "cells": w5.n_cells, "grains": G, "n_lambda": w5.n_lambda,
-                       "tol": 0.01, "check": "emitted vs the predicted absorbed power of the plain model"},
+                       "tol": 0.01, "check": "emitted vs the predicted absorbed power of the plain model",
+                       "networks_per_composition": args.radius_groups},
             "plain_solves_per_s": n_pairs / t_plain, "speedup_vs_plain": t_plain / t_sur,
             "fallback_fraction": nfb / n_pairs,
             "check_against_absorbed": {"tol": 0.01, "solves_per_s": n_pairs / t_abs,
@@ -377,7 +421,9 @@ def main():
                     help="emission contraction: three BF16 products of split operands, or FP32")
     ap.add_argument("--no-persistent", action="store_true",
                     help="launch every class as an ordinary grid (what a concurrent plan launches; for counter runs)")
-    ap.add_argument("--train-steps", type=int, default=60000, help="surrogate training steps per composition")
+    ap.add_argument("--train-steps", type=int, default=60000, help="surrogate training steps per network")
+    ap.add_argument("--radius-groups", type=int, default=4,
+                    help="surrogate networks per composition, each for one range of consecutive radii")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
