@@ -1,0 +1,76 @@
+"""Host logic of the benchmark: how the surrogate's radius ranges are formed,
+and the error measures it reports (band errors, relative error of j against
+the oracle)."""
+
+import numpy as np
+import torch
+
+import bench
+import synth
+
+
+def test_radius_groups_partition_each_composition_in_order():
+    w = synth.workload("c4_train")
+    for comp in ("carbonaceous", "silicate"):
+        groups = bench.radius_groups(w.grains, comp, 4)
+        assert len(groups) == 4
+        idx = [i for g in groups for i, _ in g]
+        mine = [i for i, g in enumerate(w.grains) if g.composition == comp]
+        assert idx == mine                                   # every grain once, in order
+        assert all(len(g) == len(mine) // 4 for g in groups)
+        for g in groups:
+            assert all(gr.composition == comp for _, gr in g)
+            r = [gr.radius_cm for _, gr in g]
+            assert r == sorted(r)
+        # ranges do not overlap
+        assert all(groups[k][-1][1].radius_cm < groups[k + 1][0][1].radius_cm for k in range(3))
+
+
+def test_radius_groups_uneven_split_keeps_every_grain():
+    w = synth.workload("c4_train")
+    groups = bench.radius_groups(w.grains, "silicate", 5)
+    sizes = [len(g) for g in groups]
+    assert sum(sizes) == 64 and max(sizes) - min(sizes) <= 1
+
+
+def test_band_error_uniform_scale_is_exact():
+    lam = np.geomspace(1e-5, 1e-1, 500)
+    rng = np.random.default_rng(1)
+    jr = rng.uniform(0.5, 2.0, size=(3, 500))
+    err = bench._band_error(1.05 * jr, jr, lam)
+    assert np.allclose(err, 0.05, rtol=0, atol=1e-12)
+
+
+def test_band_error_ignores_bands_without_power():
+    lam = np.geomspace(1e-5, 1e-1, 500)
+    e1 = (1 * (500 - 1)) // 32                  # first node of band 1
+    jr = np.ones((1, 500))
+    jr[0, :e1 + 1] = 1e-12                       # band 0 holds ~1e-12 of the power
+    jp = jr.copy()
+    jp[0, :e1] *= 100.0                          # wrong by 99x, but only inside band 0
+    assert bench._band_error(jp, jr, lam)[0] < 1e-12        # up to the rounding of the band sums
+    jp[0, e1 + 2] *= 1.5                         # a change inside band 1 is seen
+    assert bench._band_error(jp, jr, lam)[0] > 1e-3
+
+
+def test_j_rel_err_masks_tiny_reference_values():
+    jr = np.array([1.0, 0.5, 1e-12, 0.0])
+    j = np.array([1.0 + 2e-5, 0.5 * (1 - 3e-5), 5e-12, 1.0])
+    assert abs(bench.j_rel_err(j, jr) - 3e-5) < 1e-12
+    assert bench.j_rel_err(np.zeros(3), np.zeros(3)) == 0.0
+    assert bench.j_rel_err(np.ones(3), np.zeros(3)) == float("inf")
+
+
+def test_oracle_error_compares_the_sampled_pairs():
+    L = 7
+    j = torch.ones((5, 3, L), dtype=torch.float32)
+    ref = np.ones((2, L))
+    samples = [(1, [0, 4], ref.copy()), (2, [3], ref[:1].copy())]
+    j[4, 1, 2] = 1.0 + 2.0 ** -10                # the largest error, on a sampled pair
+    j[2, 1, 0] = 10.0                            # not sampled: ignored
+    rep = bench.oracle_error(j, samples)
+    assert rep["pairs"] == 3
+    assert abs(rep["max_rel_err_j"] - 2.0 ** -10) < 1e-12
+    assert rep["within_tol"] is False and rep["tol"] == bench.J_TOL
+    j[4, 1, 2] = 1.0
+    assert bench.oracle_error(j, samples)["within_tol"] is True
