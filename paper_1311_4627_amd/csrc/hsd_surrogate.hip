@@ -100,9 +100,10 @@ __global__ void __launch_bounds__(256) k_wc(const double* const* cabs, const dou
 // the inputs either raw (X, 33 floats) or normalised as the first layer reads
 // them (xb, 96 BF16: hi terms of the 33 inputs, their lo terms, zeros).
 // A[cell][s] = sum_j u[cell][j] wcT[j][s] is a small FP64 matrix product: a
-// block takes 8 cells x 64 selected grains and stages 64-wavelength slices of
-// both operands in LDS; each thread sums two cells of one grain in wavelength
-// order.
+// block takes S selected grains (64, or 32 or 16 for smaller selections) and
+// 512 / S cells, and stages 64-wavelength slices of both operands in LDS;
+// each thread sums two cells of one grain in wavelength order (the same order
+// for every S).
 struct PairArgs {
     const double* u;
     const float* bands;        // [n_cells][32]
@@ -117,13 +118,15 @@ struct PairArgs {
     const float* xm; const float* xs;   // input statistics (xb)
 };
 
-constexpr int kPairCells = 8, kPairSlots = 64, kPairLam = 64;
+constexpr int kPairLam = 64;
 
+template <int kPairSlots>
 __global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
+    constexpr int kPairCells = 512 / kPairSlots;     // two per thread
     __shared__ double us[kPairCells][kPairLam];
     __shared__ double ws[kPairLam][kPairSlots];
     const int tid = threadIdx.x;
-    const int sl = tid & 63, cg = tid >> 6;
+    const int sl = tid % kPairSlots, cg = tid / kPairSlots;
     const long long c0 = a.cell0 + static_cast<long long>(blockIdx.x) * kPairCells;
     const int s0 = blockIdx.y * kPairSlots;
     const int ns = min(kPairSlots, a.n_sel - s0);
@@ -161,15 +164,17 @@ __global__ void __launch_bounds__(256) k_pairs(PairArgs a) {
     __shared__ float braw[kPairCells][kBands], araw[kPairSlots];
     __shared__ unsigned short bnorm[kPairCells][2][kBands], anorm[kPairSlots][2];
     {
-        const int cc = tid / kBands, k = tid % kBands;   // 256 threads = 8 cells x 32 bands
-        if (cc < nc) {
-            const float v = a.bands[(c0 + cc) * kBands + k];
-            braw[cc][k] = v;
-            if (a.xb) {
-                const float x = (v - a.xm[k]) / a.xs[k];
-                const unsigned short hi = to_bf16(x);
-                bnorm[cc][0][k] = hi;
-                bnorm[cc][1][k] = to_bf16(x - from_bf16(hi));
+        for (int e = tid; e < kPairCells * kBands; e += 256) {
+            const int cc = e / kBands, k = e % kBands;
+            if (cc < nc) {
+                const float v = a.bands[(c0 + cc) * kBands + k];
+                braw[cc][k] = v;
+                if (a.xb) {
+                    const float x = (v - a.xm[k]) / a.xs[k];
+                    const unsigned short hi = to_bf16(x);
+                    bnorm[cc][0][k] = hi;
+                    bnorm[cc][1][k] = to_bf16(x - from_bf16(hi));
+                }
             }
         }
         if (tid < ns) {
@@ -948,9 +953,14 @@ hipError_t sur_pairs(const Ctx& c, const double* u, const float* bands, const do
     const long long cell0 = row0 / n_sel;
     const long long cell1 = (row0 + n_rows - 1) / n_sel;
     PairArgs p{u, bands, wcT, loga, row0, n_rows, cell0, cell1 - cell0 + 1, n_sel, c.L, X, A, xb, xm, xs};
-    const dim3 grid(static_cast<unsigned>((p.n_cells + kPairCells - 1) / kPairCells),
-                    static_cast<unsigned>((n_sel + kPairSlots - 1) / kPairSlots));
-    hipLaunchKernelGGL(k_pairs, grid, dim3(256), 0, st, p);
+    // grain slots per block: the smallest of 16 / 32 / 64 that holds the
+    // selection (64 and several blocks across it beyond that)
+    const int S = n_sel <= 16 ? 16 : n_sel <= 32 ? 32 : 64;
+    const int C = 512 / S;
+    const dim3 grid(static_cast<unsigned>((p.n_cells + C - 1) / C), static_cast<unsigned>((n_sel + S - 1) / S));
+    if (S == 16) hipLaunchKernelGGL(k_pairs<16>, grid, dim3(256), 0, st, p);
+    else if (S == 32) hipLaunchKernelGGL(k_pairs<32>, grid, dim3(256), 0, st, p);
+    else hipLaunchKernelGGL(k_pairs<64>, grid, dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

@@ -85,6 +85,25 @@ def test_features_and_targets_match_reference(hsd, small):
             assert np.max(np.abs(Y[c, g] - yr)) < 1e-5
 
 
+def test_features_do_not_depend_on_the_selection(hsd, small):
+    # selections of 16 or fewer, 17..32 and more grains take differently
+    # shaped blocks; every pair's inputs and absorbed power stay bit-identical
+    d = small
+    G = len(d["ids"])
+    X = d["X"].cpu().numpy().reshape(-1, G, 33)
+    A = d["A"].cpu().numpy().reshape(-1, G)
+    n = X.shape[0]
+    for cols in (list(range(16)), [3, 9, 40, 41, 63], list(range(20, 40)), list(range(0, 64, 2))):
+        ids = [d["ids"][c] for c in cols]
+        Xs = torch.empty((n * len(cols), 33), dtype=torch.float32, device="cuda")
+        As = torch.empty((n * len(cols),), dtype=torch.float64, device="cuda")
+        d["ctx"].hsd_sur_features(d["ud"], ids, Xs, As)
+        d["ctx"].hsd_sync()
+        print(f"selection of {len(cols)} grains", flush=True)
+        assert np.array_equal(Xs.cpu().numpy().reshape(n, len(cols), 33), X[:, cols])
+        assert np.array_equal(As.cpu().numpy().reshape(n, len(cols)), A[:, cols])
+
+
 def test_loss_and_gradient_match_bf16_reference(hsd, small):
     d = small
     sur = hsd.Surrogate(d["ctx"])
