@@ -243,3 +243,60 @@ def test_power_law_size_weights_integrate_the_distribution():
     w = synth.size_weights(r, q=3.5, per_H=1.0)
     exact = (r[0] ** -2.5 - r[-1] ** -2.5) / 2.5
     assert abs(w.sum() / exact - 1) < 2e-3
+
+
+def test_coarse_bin_energy_balance_across_the_batched_radii():
+    # The batched workload's 14..48 A grains (528..288 bins) at strong fields:
+    # the steady state balances exactly (discrete heating = cooling), the
+    # spectrum carries the cooling power, and yet emitted / A_rep ranges over
+    # about 0.92..1.04.  The whole difference sits in the heating rates'
+    # photon-energy sum: for one lower bin i the discrete heating power
+    # H_i = sum_f A_fi (E_f - E_i) is a sum over the upper bins' photon energies
+    # with weights dE_f (eq:heating), a quadrature of the absorbed power per
+    # unit photon energy with nodes several eV apart once the bins are that
+    # wide; where the field's power ends at the grid's short end (13.8 eV) such
+    # a sum miscounts by up to half a node spacing times the power there.
+    # It goes away as the bins are refined.
+    w = synth.workload("c2_batched", n_cells=1)
+    lam = w.lam_cm
+    radii = synth.radii_cm(3.5, 250.0, 32)
+    ratios = []
+    for ai in range(10, 20):
+        g = synth.make_grain("carbonaceous", radii[ai], lam)
+        s = oracle.grain_setup(g, lam)
+        for U in (1e3, 2e4, 1e5):
+            u = make_fields(lam, FieldRecipe(1, (U, U), 0.0, None), 1)[0]
+            A = om.heating_matrix(u, s)
+            P, _, _ = om.recursion(om.b_matrix_recurrence(A), s.cool)
+            j = om.emission(P, s)
+            d = om.diagnostics(u, s, P, j, A)
+            assert abs(d["heat"] / d["cool"] - 1.0) < 1e-12
+            assert abs(d["emitted"] / d["cool"] - 1.0) < 1e-3
+            assert abs(d["A_rep"] / d["absorbed"] - 1.0) < 1e-6
+            # per lower bin: discrete heating power vs representable absorbed power
+            dEm = s.E[:, None] - s.E[None, :]
+            H = np.sum(A * np.where(dEm > 0, dEm, 0.0), axis=0)
+            cum = om.absorbed_cumulative(u, s)
+            edge = s.E[-1] + 0.5 * s.dE[-1] - s.E
+            jrep = np.searchsorted(lam, HC / edge, side="left")
+            R = np.append(cum, 0.0)[np.minimum(jrep, lam.shape[0])]
+            quad = float(np.sum(P * H) / np.sum(P * R))
+            ratio = d["emitted"] / d["A_rep"]
+            assert abs(ratio / quad - 1.0) < 1e-3
+            # bins far narrower than the field's photon energies hold no such error
+            spacing = np.append(np.diff(s.E), np.inf)
+            fine = (spacing < 0.05 * oracle.EV) & (R > 0)
+            if np.any(fine):
+                assert np.max(np.abs(H[fine] / R[fine] - 1.0)) < 0.01
+            ratios.append(ratio)
+    ratios = np.array(ratios)
+    assert ratios.min() < 0.95 and ratios.max() > 1.01          # the imbalance is real on these bins
+    assert 0.9 < ratios.min() and ratios.max() < 1.05
+    # refinement: the 18.3 A grain at U = 2e4, 464 -> 1856 bins
+    u = make_fields(lam, FieldRecipe(1, (2e4, 2e4), 0.0, None), 1)[0]
+    out = []
+    for n in (464, 1856):
+        g = synth.make_grain("carbonaceous", radii[12], lam, n_bins=n)
+        _, _, d = oracle.solve_pair(u, g, lam, with_diag=True)
+        out.append(d["emitted"] / d["A_rep"])
+    assert abs(out[0] - 1.0) > 0.02 and abs(out[1] - 1.0) < 1e-3
