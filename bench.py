@@ -476,7 +476,6 @@ def main():
     if args.no_persistent or not args.eager:
         for c in launched:
             c["persistent"] = 0
-    if args.no_persistent:
         for cls, c in enumerate(launched):
             ctx.hsd_set_class_cfg(cls, **c)
 

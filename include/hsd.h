@@ -251,10 +251,11 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
  *          hsd_plan_phase_ms waits for the last launch and writes the phases'
  *          milliseconds to ms_host[0..2].
  *          HSD_PLAN_CONCURRENT: the solver classes run as parallel branches
- *          of the graph, so one class's tail overlaps the next class; the
- *          classes then launch as ordinary grids whatever their persistent
- *          setting (a persistent grid takes every workgroup slot of the
- *          device and would hold the other branches off it).
+ *          of the graph, so one class's tail overlaps the next class.  Every
+ *          class must then be configured with persistent = 0, else the call
+ *          fails with HSD_ERR_INVALID_ARG (a persistent grid takes every
+ *          workgroup slot of the device and would hold the other branches
+ *          off it).
  * The buffers must stay allocated, and the grains registered, while the plan
  * lives.  A plan is used by one thread at a time; replays of one plan on
  * different streams must not overlap (they share its workspace).
@@ -340,6 +341,32 @@ hsd_status hsd_sur_loss_grad(hsd_sur* sur, int32_t n, const float* X_dev, const 
  * from the parameters at the call).  Synchronous. */
 hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps,
                          int32_t batch, float lr, uint64_t seed, float* loss_host);
+/* Checkpoint and resume (the paper's library is configured once and reused
+ * across runs, appendix on the library interface; a trained network is kept
+ * the same way).  hsd_surrogate_save writes, synchronously, to the file
+ * `path` (created or truncated):
+ *   line 1   "HSDSUR 1"
+ *   line 2   a one-line JSON header: "widths" (33, 256, 256, 256, L + 1),
+ *            "n_params", "step" (Adam steps taken, which is also the position
+ *            of the minibatch generator), "optimizer" (true when the Adam
+ *            moments follow), "byte_order" "little", and "sections": name,
+ *            element type "f32" and count of each array below, in order;
+ *   then     the arrays, raw little-endian FP32, back to back: params
+ *            [n_params] (layout of hsd_sur_set_params), x_mean [33], x_std
+ *            [33], y_mean [L + 1], y_std [L + 1], and unless flags has
+ *            HSD_SAVE_WEIGHTS_ONLY, adam_m [n_params] and adam_v [n_params].
+ * The network needs its statistics (HSD_ERR_STATE otherwise).
+ * hsd_surrogate_load reads such a file into a network of the same widths
+ * (HSD_ERR_INVALID_ARG for another shape, a truncated or foreign file): the
+ * parameters, the statistics, and either the saved Adam moments and step or,
+ * for a weights-only file, zero moments and step 0.  A network resumed from a
+ * checkpoint trains on exactly as the saved one would: hsd_sur_train calls
+ * after hsd_surrogate_load give the same bits as the same calls made on the
+ * network that was saved.  Both wait for the device; file errors give
+ * HSD_ERR_INVALID_ARG with the reason in hsd_last_error. */
+#define HSD_SAVE_WEIGHTS_ONLY 1
+hsd_status hsd_surrogate_save(hsd_sur* sur, const char* path, int32_t flags);
+hsd_status hsd_surrogate_load(hsd_sur* sur, const char* path);
 /* Energy checks of hsd_solve_surrogate.  With E the surrogate's emitted
  * power (4 pi int j dlambda on the grid) and A the pair's absorbed power:
  *   HSD_CHECK_ABSORBED  flag the pair when |E / A - 1| > tol;

@@ -203,6 +203,41 @@ def loss_and_grad(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.
     return loss, pack(grads)
 
 
+def grad_abs_terms(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """For every parameter, the sum of the absolute values of the terms whose
+    sum is its gradient in the BF16-operand backward pass of loss_and_grad
+    (same layout as the gradient): sum_n |bf16(dz_n,o)| |bf16(h_n,i)| for a
+    weight, sum_n |dz_n,o| for a bias.  The scale of the rounding error of a
+    gradient computed with other accumulation orders or an occasional operand
+    rounded to the other BF16 neighbour (such a flip moves one term by at most
+    one BF16 spacing, 2^-7 of the term)."""
+    layers = unpack(flat, widths)
+    yhat, (hs, zs) = forward(flat, widths, X, bf16=True)
+    n, m = yhat.shape
+    dz = 2.0 * (yhat - Y) / (n * m)
+    out = [None] * len(layers)
+    for i in range(len(layers) - 1, -1, -1):
+        W, _ = layers[i]
+        out[i] = (np.abs(bf16_round(dz)).T @ np.abs(bf16_round(hs[i])), np.abs(dz).sum(axis=0))
+        if i > 0:
+            dz = _mm(dz, W, True) * gelu_grad(zs[i - 1])
+    return pack(out)
+
+
+def output_abs_terms(flat: np.ndarray, widths: Sequence[int], X: np.ndarray) -> np.ndarray:
+    """Per sample and output, the sum of the absolute values of the terms of
+    the last layer's BF16 product (hi and lo terms of its split input) plus
+    |bias|: the scale of the rounding error of an output computed with other
+    accumulation orders or an occasional operand rounded the other way."""
+    layers = unpack(flat, widths)
+    _, (hs, _) = forward(flat, widths, X, bf16=True)
+    W, b = layers[-1]
+    h = hs[-2]
+    hi = bf16_round(h)
+    lo = bf16_round(np.asarray(h, dtype=np.float32) - hi.astype(np.float32))
+    return (np.abs(hi) + np.abs(lo)) @ np.abs(bf16_round(W)).T + np.abs(b)
+
+
 def adam_step(flat, grad, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
     """One Adam update (Kingma & Ba), step number t >= 1.  Returns new
     (params, m, v)."""

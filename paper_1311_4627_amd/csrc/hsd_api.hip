@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -279,6 +280,26 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
     return HSD_OK;
 }
 
+// Copy the batch's host description into the device buffers d and enqueue
+// its launches (eager solves: hsd_solve, hsd_solve_P, hsd_solve_noalloc).
+hsd_status run_batch(hsd_ctx* ctx, const Bufs& d, int32_t n_cells, const double* u, int32_t n_grains,
+                     const int32_t* ids, float* j, float* diag, double* P64, hipStream_t s) {
+    Ctx& c = ctx->c;
+    const Batch& b = ctx->batch;
+    HSD_HIP(ctx, hipMemcpyAsync(d.views, b.views.data(), sizeof(hsd::GrainView) * n_grains,
+                                hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(d.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
+    if (!b.items.empty())
+        HSD_HIP(ctx, hipMemcpyAsync(d.items, b.items.data(), sizeof(int2) * b.items.size(),
+                                    hipMemcpyHostToDevice, s));
+    Events t{{nullptr, nullptr, nullptr, nullptr}};
+    if (c.timing)
+        for (int i = 0; i < 4; ++i) t.ev[i] = c.ev[i];
+    hsd_status st = enqueue(ctx, b, d, n_cells, u, n_grains, ids, j, diag, P64, s, t, nullptr, nullptr);
+    if (st == HSD_OK && c.timing) c.timed = true;
+    return st;
+}
+
 // Eager solve on the context's workspace (hsd_solve and hsd_solve_P).
 hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_grains, const int32_t* ids,
                      float* j, float* diag, double* P64, hipStream_t s, bool keep_pt = false) {
@@ -291,20 +312,10 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
-    HSD_HIP(ctx, hipMemcpyAsync(c.views, b.views.data(), sizeof(hsd::GrainView) * n_grains,
-                                hipMemcpyHostToDevice, s));
-    HSD_HIP(ctx, hipMemcpyAsync(c.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
-    if (!b.items.empty())
-        HSD_HIP(ctx, hipMemcpyAsync(c.items, b.items.data(), sizeof(int2) * b.items.size(),
-                                    hipMemcpyHostToDevice, s));
     Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue};
-    Events t{{nullptr, nullptr, nullptr, nullptr}};
-    if (c.timing)
-        for (int i = 0; i < 4; ++i) t.ev[i] = c.ev[i];
-    hsd_status st = enqueue(ctx, b, d, n_cells, u, n_grains, ids, j, diag, P64, s, t, nullptr, nullptr);
-    if (st == HSD_OK && c.timing) c.timed = true;
-    return st;
+    return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s);
 }
+
 
 }  // namespace
 
@@ -637,6 +648,14 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
     for (int g = 0; g < n_grains; ++g)
         if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
     Ctx& c = ctx->c;
+    if (flags & HSD_PLAN_CONCURRENT) {
+        // a persistent grid takes every workgroup slot of the device and would
+        // hold the other branches off it: the two do not combine
+        for (int ci = 0; ci < hsd::kClasses; ++ci)
+            if (c.cfg[ci].persistent)
+                return fail(ctx, HSD_ERR_INVALID_ARG,
+                            "HSD_PLAN_CONCURRENT needs every class configured with persistent = 0");
+    }
     HSD_HIP(ctx, hipSetDevice(c.device));
     hsd_plan* p = new (std::nothrow) hsd_plan();
     if (!p) return fail(ctx, HSD_ERR_OOM, "host allocation");
@@ -646,21 +665,6 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
     p->ids.assign(grain_ids_host, grain_ids_host + n_grains);
     p->timing = (flags & HSD_PLAN_TIMING) != 0;
     const bool conc = (flags & HSD_PLAN_CONCURRENT) != 0;
-    // concurrent branches launch ordinary grids: the context's persistent
-    // settings are set aside while the plan is built and restored on return
-    struct KeepCfg {
-        Ctx& c;
-        hsd::ClassCfg saved[hsd::kClasses];
-        KeepCfg(Ctx& cc, bool off) : c(cc) {
-            for (int i = 0; i < hsd::kClasses; ++i) {
-                saved[i] = c.cfg[i];
-                if (off) c.cfg[i].persistent = 0;
-            }
-        }
-        ~KeepCfg() {
-            for (int i = 0; i < hsd::kClasses; ++i) c.cfg[i] = saved[i];
-        }
-    } keep_cfg(c, conc);
     plan_batch(c, n_cells, n_grains, p->ids.data(), p->b);
     hipError_t e = hipSuccess;
     auto al = [&](auto*& ptr, size_t count) {
@@ -925,6 +929,162 @@ hsd_status hsd_sur_get_norm(hsd_sur* p, double* x_mean, double* x_std, double* y
         y_mean[k] = c[k];
         y_std[k] = d[k];
     }
+    return HSD_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoint files of a network ----
+
+namespace {
+
+bool host_is_little_endian() {
+    const uint32_t one = 1;
+    unsigned char b[4];
+    std::memcpy(b, &one, 4);
+    return b[0] == 1;
+}
+
+// The number after "key": in a one-line JSON header, or false.
+bool json_number(const std::string& h, const char* key, long long& out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = h.find(k);
+    if (at == std::string::npos) return false;
+    const char* p = h.c_str() + at + k.size();
+    char* end = nullptr;
+    out = std::strtoll(p, &end, 10);
+    return end != p;
+}
+
+bool json_bool(const std::string& h, const char* key, bool& out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = h.find(k);
+    if (at == std::string::npos) return false;
+    size_t q = at + k.size();
+    while (q < h.size() && h[q] == ' ') ++q;
+    if (h.compare(q, 4, "true") == 0) out = true;
+    else if (h.compare(q, 5, "false") == 0) out = false;
+    else return false;
+    return true;
+}
+
+struct SurSection {
+    const char* name;
+    float* dev;
+    long long n;
+};
+
+std::vector<SurSection> sur_sections(hsd::Sur& s, bool optimizer) {
+    std::vector<SurSection> v = {{"params", s.w, s.n_params}, {"x_mean", s.xm, 33}, {"x_std", s.xs, 33},
+                                 {"y_mean", s.ym, s.n_out}, {"y_std", s.ys, s.n_out}};
+    if (optimizer) {
+        v.push_back({"adam_m", s.m, s.n_params});
+        v.push_back({"adam_v", s.v, s.n_params});
+    }
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+hsd_status hsd_surrogate_save(hsd_sur* p, const char* path, int32_t flags) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!path) return fail(ctx, HSD_ERR_INVALID_ARG, "null path");
+    if (flags & ~HSD_SAVE_WEIGHTS_ONLY) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown flag");
+    if (!host_is_little_endian()) return fail(ctx, HSD_ERR_STATE, "checkpoints are written on little-endian hosts only");
+    hsd::Sur& s = p->s;
+    if (!s.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipDeviceSynchronize());
+    const bool opt = (flags & HSD_SAVE_WEIGHTS_ONLY) == 0;
+    const std::vector<SurSection> secs = sur_sections(s, opt);
+    std::string h = "{\"format\": \"hsd-surrogate\", \"widths\": [";
+    for (int i = 0; i < 5; ++i) h += std::to_string(s.widths[i]) + (i < 4 ? ", " : "]");
+    h += ", \"n_params\": " + std::to_string(s.n_params) + ", \"step\": " + std::to_string(s.t) +
+         ", \"optimizer\": " + (opt ? "true" : "false") + ", \"byte_order\": \"little\", \"sections\": [";
+    for (size_t i = 0; i < secs.size(); ++i)
+        h += std::string(i ? ", " : "") + "{\"name\": \"" + secs[i].name + "\", \"dtype\": \"f32\", \"count\": " +
+             std::to_string(secs[i].n) + "}";
+    h += "]}";
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    bool ok = std::fputs("HSDSUR 1\n", f) >= 0 && std::fputs(h.c_str(), f) >= 0 && std::fputc('\n', f) != EOF;
+    std::vector<float> buf;
+    for (const SurSection& sec : secs) {
+        if (!ok) break;
+        buf.resize(static_cast<size_t>(sec.n));
+        const hipError_t e = hipMemcpy(buf.data(), sec.dev, sizeof(float) * sec.n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            std::fclose(f);
+            return hip_fail(ctx, e, "hsd_surrogate_save");
+        }
+        ok = std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    return HSD_OK;
+}
+
+hsd_status hsd_surrogate_load(hsd_sur* p, const char* path) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    hsd_ctx* ctx = p->ctx;
+    if (!path) return fail(ctx, HSD_ERR_INVALID_ARG, "null path");
+    if (!host_is_little_endian()) return fail(ctx, HSD_ERR_STATE, "checkpoints are read on little-endian hosts only");
+    hsd::Sur& s = p->s;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("cannot open: ") + path);
+    std::string data;
+    char chunk[65536];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) data.append(chunk, got);
+    const bool read_err = std::ferror(f) != 0;
+    std::fclose(f);
+    if (read_err) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("read failed: ") + path);
+    const std::string magic = "HSDSUR 1\n";
+    if (data.compare(0, magic.size(), magic) != 0) return fail(ctx, HSD_ERR_INVALID_ARG, "not a surrogate checkpoint");
+    const size_t eol = data.find('\n', magic.size());
+    if (eol == std::string::npos) return fail(ctx, HSD_ERR_INVALID_ARG, "truncated header");
+    const std::string h = data.substr(magic.size(), eol - magic.size());
+    long long np = 0, step = 0;
+    bool opt = false;
+    if (!json_number(h, "n_params", np) || !json_number(h, "step", step) || !json_bool(h, "optimizer", opt) ||
+        h.find("\"byte_order\": \"little\"") == std::string::npos)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "malformed header");
+    std::string want = "\"widths\": [";
+    for (int i = 0; i < 5; ++i) want += std::to_string(s.widths[i]) + (i < 4 ? ", " : "]");
+    if (h.find(want) == std::string::npos || np != s.n_params)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "checkpoint of a network of another shape");
+    if (step < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative step count");
+    const std::vector<SurSection> secs = sur_sections(s, opt);
+    size_t need = 0;
+    for (const SurSection& sec : secs) need += sizeof(float) * static_cast<size_t>(sec.n);
+    const size_t off0 = eol + 1;
+    if (data.size() != off0 + need) return fail(ctx, HSD_ERR_INVALID_ARG, "checkpoint size does not match its header");
+    std::vector<std::vector<float>> host(secs.size());
+    size_t off = off0;
+    for (size_t i = 0; i < secs.size(); ++i) {
+        host[i].resize(static_cast<size_t>(secs[i].n));
+        std::memcpy(host[i].data(), data.data() + off, sizeof(float) * secs[i].n);
+        off += sizeof(float) * secs[i].n;
+        for (float v : host[i])
+            if (!std::isfinite(v)) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("non-finite value in ") + secs[i].name);
+    }
+    for (int k : {2, 4})
+        for (float v : host[k])
+            if (!(v > 0.f)) return fail(ctx, HSD_ERR_INVALID_ARG, "standard deviations must be > 0");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hipDeviceSynchronize());
+    for (size_t i = 0; i < secs.size(); ++i)
+        HSD_HIP(ctx, hipMemcpy(secs[i].dev, host[i].data(), sizeof(float) * secs[i].n, hipMemcpyHostToDevice));
+    if (!opt) {
+        HSD_HIP(ctx, hipMemset(s.m, 0, sizeof(float) * s.n_params));
+        HSD_HIP(ctx, hipMemset(s.v, 0, sizeof(float) * s.n_params));
+    }
+    s.t = opt ? step : 0;
+    s.have_norm = true;
+    s.wb_fresh = false;
     return HSD_OK;
 }
 

@@ -215,7 +215,7 @@ struct Sur {
     int cap_B = 0;
     float *Xb = nullptr, *Yb = nullptr, *Z[3] = {}, *H[3] = {}, *Yh = nullptr, *dY = nullptr, *dZ[2] = {};
     long long* idx = nullptr;
-    double* loss = nullptr;
+    double* loss = nullptr;    // the minibatch loss, then the loss reduction's per-block partials
     int splits = 1;            // K splits of the weight-gradient products
     float* split_work = nullptr;
     unsigned short* wb = nullptr;   // BF16 weights for inference (W1 padded to 64 inputs)

@@ -26,6 +26,7 @@ namespace hsd {
 namespace {
 
 constexpr int kBands = 32;
+constexpr int kLossBlocks = 1024;   // blocks of the loss reduction (one FP64 partial each)
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -250,10 +251,12 @@ __global__ void __launch_bounds__(256) k_targets(const float* j, const double* A
     if (lane == 0) yr[L] = static_cast<float>(log10(4.0 * kPi * em / a));
 }
 
-// Column sums and sums of squares in FP64 (one thread per column, blocks of
-// rows accumulated with double atomics).
+// Column sums and sums of squares in FP64, first stage: one thread per
+// column and block of rows, each block's partial written to its own slot
+// (part[block][2 w]: sums, then squares); k_colstats_sum adds the blocks in
+// order, so the statistics do not depend on scheduling.
 __global__ void __launch_bounds__(256) k_colstats(const float* Xm, long long n, int w, long long rows_per_block,
-                                                  double* sum, double* sq) {
+                                                  double* part) {
     const int col = blockIdx.y * 256 + threadIdx.x;
     if (col >= w) return;
     const long long r0 = static_cast<long long>(blockIdx.x) * rows_per_block;
@@ -264,8 +267,18 @@ __global__ void __launch_bounds__(256) k_colstats(const float* Xm, long long n, 
         s += v;
         q += v * v;
     }
-    atomicAdd(sum + col, s);
-    atomicAdd(sq + col, q);
+    double* p = part + static_cast<long long>(blockIdx.x) * 2 * w;
+    p[col] = s;
+    p[w + col] = q;
+}
+
+// Second stage: out[c] = sum over blocks b = 0, 1, ... of part[b][c], c < 2 w.
+__global__ void __launch_bounds__(256) k_colstats_sum(const double* part, int n_blocks, int w2, double* out) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= w2) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += part[static_cast<long long>(b) * w2 + c];
+    out[c] = s;
 }
 
 // Gather a minibatch and z-score it: rows idx[b] of X (33 wide) and Y (L wide).
@@ -299,9 +312,10 @@ __global__ void k_batch_idx(unsigned long long seed, long long step, int B, long
 
 // Loss and its gradient with respect to the network output:
 // L = mean (yhat - y)^2, dL/dyhat = 2 (yhat - y) / (B L).  A fixed grid walks
-// the elements; each block adds its FP64 partial sum of squares once.
+// the elements; each block writes its FP64 partial sum of squares to its own
+// slot, and k_loss_sum adds the slots in order.
 __global__ void __launch_bounds__(256) k_loss(const float* yhat, const float* y, long long n, float scale,
-                                              float* dy, double* loss) {
+                                              float* dy, double* part) {
     __shared__ double red[4];
     double l = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < n;
@@ -314,7 +328,14 @@ __global__ void __launch_bounds__(256) k_loss(const float* yhat, const float* y,
     for (int m = 1; m < 64; m <<= 1) l += __shfl_xor(l, m, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_loss_sum(const double* part, int n, double* loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < n; ++b) s += part[b];
+    *loss = s;
 }
 
 // Bias gradient, first stage: column sums of dZ [B][N] over chunks of 32
@@ -865,7 +886,7 @@ hipError_t sur_alloc(Sur& s) {
         if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
     };
     al(s.w, s.n_params); al(s.g, s.n_params); al(s.m, s.n_params); al(s.v, s.n_params); al(s.we, s.n_params);
-    al(s.xm, 33); al(s.xs, 33); al(s.ym, s.n_out); al(s.ys, s.n_out); al(s.wq, s.n_out); al(s.loss, 1);
+    al(s.xm, 33); al(s.xs, 33); al(s.ym, s.n_out); al(s.ys, s.n_out); al(s.wq, s.n_out); al(s.loss, 1 + kLossBlocks);
     if (e == hipSuccess) e = hipMemset(s.m, 0, sizeof(float) * s.n_params);
     if (e == hipSuccess) e = hipMemset(s.v, 0, sizeof(float) * s.n_params);
     if (e == hipSuccess) {
@@ -971,19 +992,25 @@ hipError_t sur_targets(const float* j, const double* A, const double* lam, long 
     return hipGetLastError();
 }
 
-// Column means and standard deviations of a [n][w] FP32 matrix (FP64 sums).
+// Column means and standard deviations of a [n][w] FP32 matrix (FP64 sums in
+// a fixed order: the same bits on every run).
 hipError_t sur_colstats(const float* Xm, long long n, int w, std::vector<double>& mean, std::vector<double>& sd) {
-    double* d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(double) * 2 * w);
-    if (e == hipSuccess) e = hipMemset(d, 0, sizeof(double) * 2 * w);
     const long long rpb = 1024;
+    const int nblk = static_cast<int>((n + rpb - 1) / rpb);
+    double* d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(double) * 2 * w * (static_cast<size_t>(nblk) + 1));
+    double* tot = d + static_cast<size_t>(nblk) * 2 * w;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_colstats, dim3(static_cast<unsigned>((n + rpb - 1) / rpb), (w + 255) / 256), dim3(256),
-                           0, nullptr, Xm, n, w, rpb, d, d + w);
+        hipLaunchKernelGGL(k_colstats, dim3(static_cast<unsigned>(nblk), (w + 255) / 256), dim3(256), 0, nullptr, Xm,
+                           n, w, rpb, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_colstats_sum, dim3((2 * w + 255) / 256), dim3(256), 0, nullptr, d, nblk, 2 * w, tot);
         e = hipGetLastError();
     }
     std::vector<double> h(2 * w);
-    if (e == hipSuccess) e = hipMemcpy(h.data(), d, sizeof(double) * 2 * w, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), tot, sizeof(double) * 2 * w, hipMemcpyDeviceToHost);
     (void)hipFree(d);
     if (e != hipSuccess) return e;
     mean.resize(w);
@@ -1076,11 +1103,12 @@ hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st) {
 
 hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
     const long long n = static_cast<long long>(B) * s.n_out;
-    hipError_t e = hipMemsetAsync(s.loss, 0, sizeof(double), st);
-    if (e != hipSuccess) return e;
-    const long long blocks = std::min<long long>(1024, (n + 255) / 256);
+    const int blocks = static_cast<int>(std::min<long long>(kLossBlocks, (n + 255) / 256));
     hipLaunchKernelGGL(k_loss, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, s.Yh, s.Yb, n,
-                       2.0f / static_cast<float>(n), s.dY, s.loss);
+                       2.0f / static_cast<float>(n), s.dY, s.loss + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, s.loss + 1, blocks, s.loss);
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ SYMBOLS = (
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
+    "hsd_surrogate_save", "hsd_surrogate_load",
 )
 
 N_CLASSES = 4
@@ -43,6 +44,7 @@ PLAN_TIMING = 1
 PLAN_CONCURRENT = 2
 CHECK_ABSORBED = 0      # surrogate energy check against the absorbed power A
 CHECK_MODEL = 1         # ... against rho A, rho the predicted energy ratio of the plain model
+SAVE_WEIGHTS_ONLY = 1   # checkpoint without the Adam moments
 
 
 class HsdError(RuntimeError):
@@ -143,6 +145,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).restype = ctypes.c_int
     lib.hsd_size_convolve.argtypes = [vp, i32, i32, vp, dp, i32, vp, vp]
     lib.hsd_size_convolve.restype = ctypes.c_int
+    lib.hsd_surrogate_save.argtypes = [vp, ctypes.c_char_p, i32]
+    lib.hsd_surrogate_save.restype = ctypes.c_int
+    lib.hsd_surrogate_load.argtypes = [vp, ctypes.c_char_p]
+    lib.hsd_surrogate_load.restype = ctypes.c_int
     return lib
 
 
@@ -528,6 +534,13 @@ class Surrogate:
         self._check(self._lib.hsd_sur_train(self._h, n, X.data_ptr(), Y.data_ptr(), int(steps), int(batch),
                                             float(lr), int(seed), _fptr(trace)), "hsd_sur_train")
         return trace[:int(steps)]
+
+    def hsd_surrogate_save(self, path: str, weights_only: bool = False):
+        self._check(self._lib.hsd_surrogate_save(self._h, os.fsencode(path), SAVE_WEIGHTS_ONLY if weights_only else 0),
+                    "hsd_surrogate_save")
+
+    def hsd_surrogate_load(self, path: str):
+        self._check(self._lib.hsd_surrogate_load(self._h, os.fsencode(path)), "hsd_surrogate_load")
 
     def hsd_sur_predict(self, u, grain_ids: Sequence[int], j, diag=None, stream=None):
         import torch

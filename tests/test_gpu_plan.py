@@ -101,7 +101,7 @@ def test_class_config_rejects_bad_values(hsd, c2_small):
     assert ctx.hsd_get_class_cfg(0) == {"kg": 2, "wide": 0, "persistent": 0}
 
 
-@pytest.mark.parametrize("flags,pers", [(0, 0), (1, 1), (3, 1), (2, 0)])
+@pytest.mark.parametrize("flags,pers", [(0, 0), (1, 1), (0, 1), (3, 0), (2, 0)])
 def test_plan_replays_match_eager(hsd, c2_small, flags, pers):
     w, ctx, ids, u0 = c2_small
     u = u0.clone()
@@ -139,11 +139,21 @@ def test_plan_rejects_bad_arguments(hsd, c2_small):
         ctx.hsd_plan_create(u, ids, j, flags=8)
     with pytest.raises(hsd.HsdError):
         ctx.hsd_plan_create(u, [999] + ids[1:], j)
+    # a persistent class in a concurrent plan is an error, not silently dropped
+    ctx.hsd_set_class_cfg(1, kg=2, wide=0, persistent=1)
+    try:
+        with pytest.raises(hsd.HsdError, match="persistent"):
+            ctx.hsd_plan_create(u, ids, j, flags=hsd.PLAN_CONCURRENT)
+    finally:
+        ctx.hsd_set_class_cfg(1, kg=2, wide=0, persistent=0)
 
 
-def test_c3_uneven_full_plan_sampled_pairs(hsd):
+@pytest.mark.parametrize("mode", ["persistent", "concurrent"])
+def test_c3_uneven_full_plan_sampled_pairs(hsd, mode):
     # the full uneven workload (65536 attenuated cells x 2 compositions x 64
-    # radii = 8.4M pairs, bins 1024..128) as one persistent, concurrent plan
+    # radii = 8.4M pairs, bins 1024..128) as one plan: either every class as a
+    # persistent grid fed longest-first from its atomic queue, the classes one
+    # after another, or the classes as ordinary grids in parallel graph branches
     w = synth.workload("c3_uneven")
     ctx = hsd.Context(w.lam_cm)
     ids = [ctx.add_grain(g) for g in w.grains]
@@ -152,16 +162,21 @@ def test_c3_uneven_full_plan_sampled_pairs(hsd):
     ud = torch.tensor(u, device="cuda")
     j = torch.empty((w.n_cells, len(ids), w.n_lambda), dtype=torch.float32, device="cuda")
     d = torch.empty((w.n_cells, len(ids), 4), dtype=torch.float32, device="cuda")
+    pers = 1 if mode == "persistent" else 0
     for c in range(hsd.N_CLASSES):
-        ctx.hsd_set_class_cfg(c, kg=2, wide=0, persistent=1)
-    plan = ctx.hsd_plan_create(ud, ids, j, d, flags=hsd.PLAN_CONCURRENT)
+        ctx.hsd_set_class_cfg(c, kg=2, wide=0, persistent=pers)
+    assert all(ctx.hsd_get_class_cfg(c)["persistent"] == pers for c in range(hsd.N_CLASSES))
+    plan = ctx.hsd_plan_create(ud, ids, j, d, flags=hsd.PLAN_CONCURRENT if mode == "concurrent" else 0)
     plan.hsd_plan_launch()
     torch.cuda.synchronize()
     ctx.hsd_sync()
-    print("c3 solved on the GPU", flush=True)
+    print(f"c3 solved on the GPU ({mode} plan)", flush=True)
     dall = d.cpu().numpy()
-    cells = [0, 30011, 65535]
-    grains = [0, 20, 63, 64, 104, 127]           # both compositions; 1024, ~370, 128 bins
+    # both compositions, 1024 .. 128 bins; the two modes sample different pairs
+    if mode == "concurrent":
+        cells, grains = [0, 30011, 65535], [0, 20, 63, 64, 104, 127]
+    else:
+        cells, grains = [7, 12345, 41000, 65534], [1, 5, 31, 47, 66, 70, 90, 120]
     jj = j[cells].cpu().numpy().astype(np.float64)
     worst = 0.0
     for gi in grains:

@@ -172,3 +172,52 @@ def test_zscore_stats():
     mu, sd = mlp.target_stats(Y)
     assert np.allclose(mu, [1.0, 2.0, 1.25])
     assert np.allclose(sd, [np.sqrt((1.0 + 4.0) / 2)] * 2 + [0.25 * mlp.RATIO_SCALE])
+
+
+def test_absolute_term_sums_by_brute_force():
+    # the error scales the GPU parity bounds use: sums of |term| of every
+    # gradient element and of every output, by explicit loops on a tiny net
+    flat, X, Y = _small_problem(seed=8)
+    T = mlp.grad_abs_terms(flat, SMALL, X, Y)
+    _, g = mlp.loss_and_grad(flat, SMALL, X, Y, bf16=True)
+    assert np.all(np.abs(g) <= T * (1 + 1e-12))               # triangle inequality
+    layers = mlp.unpack(flat, SMALL)
+    yhat, (hs, zs) = mlp.forward(flat, SMALL, X, bf16=True)
+    n, m = yhat.shape
+    dz = 2.0 * (yhat - Y) / (n * m)
+    ref = []
+    for i in range(len(layers) - 1, -1, -1):
+        W, _ = layers[i]
+        n_out, n_in = W.shape
+        tw = np.zeros((n_out, n_in))
+        tb = np.zeros(n_out)
+        for o in range(n_out):
+            for k in range(n_in):
+                for s in range(n):
+                    tw[o, k] += abs(mlp.bf16_round(dz[s, o])) * abs(mlp.bf16_round(hs[i][s, k]))
+            for s in range(n):
+                tb[o] += abs(dz[s, o])
+        ref.insert(0, (tw, tb))
+        if i > 0:
+            nz = np.zeros((n, n_in))
+            for s in range(n):
+                for k in range(n_in):
+                    acc = 0.0
+                    for o in range(n_out):
+                        acc += mlp.bf16_round(dz[s, o]) * mlp.bf16_round(W[o, k])
+                    nz[s, k] = acc * mlp.gelu_grad(zs[i - 1][s, k])
+            dz = nz
+    assert np.allclose(T, mlp.pack(ref), rtol=1e-12, atol=0)
+    # outputs: last layer with its input split into hi and lo terms
+    Yabs = mlp.output_abs_terms(flat, SMALL, X)
+    assert np.all(np.abs(yhat) <= Yabs * (1 + 1e-12))
+    W, b = layers[-1]
+    for s in range(n):
+        for o in range(W.shape[0]):
+            acc = abs(b[o])
+            for k in range(W.shape[1]):
+                x = hs[-2][s, k]
+                hi = mlp.bf16_round(x)
+                lo = mlp.bf16_round(np.float32(x) - np.float32(hi))
+                acc += (abs(hi) + abs(lo)) * abs(mlp.bf16_round(W[o, k]))
+            assert Yabs[s, o] == pytest.approx(acc, rel=1e-12)
