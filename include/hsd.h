@@ -127,6 +127,23 @@ hsd_status hsd_grain_tables(hsd_ctx* ctx, int32_t grain_id, double* E_host, doub
 hsd_status hsd_solve(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
                      const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream);
 
+/* hsd_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels, arguments, results and asynchrony, but the solve's workspace
+ * (grain views, work items, per-pair scales and the scaled-P rows: 256-byte
+ * aligned pieces, 4 bytes per bin per pair for the rows) lives in a fixed
+ * 64 MiB device array inside the library, one per GPU, held until the
+ * process ends.  A batch that needs more than that fails with
+ * HSD_ERR_INVALID_ARG (the message gives the bytes it needs; the batched
+ * workload's 13,968 bins per cell allow about 1,100 cells per call).  The call
+ * makes no hipMalloc / hipFree; it copies the batch's small description
+ * (views, offsets, work items) host to device on `stream`.  Every context on
+ * a GPU shares that GPU's array and it keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other threads or contexts)
+ * race on it and must be serialised by the caller. */
+hsd_status hsd_solve_noalloc(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                             const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream);
+
 /* Same solve for one grain, returning the bin probabilities in double
  * precision instead of the spectrum: P_dev [n_cells][n_bins] double.
  * Asynchronous on `stream`. */

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -316,6 +317,35 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s);
 }
 
+// ---- fixed device scratch for hsd_solve_noalloc ----
+// The whole workspace of one solve (grain views, row offsets, work items,
+// per-pair scales and the scaled-P rows) carved out of one file-scope device
+// array, so that the call allocates nothing.  Each device holds its own copy
+// of the array; host code uses only its device address (from
+// hipGetSymbolAddress, looked up once per device when a context is created),
+// never the array's name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The device address of `scratch` on the current device `dev` (looked up on
+// the first call per device).
+hipError_t scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
@@ -339,10 +369,13 @@ hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambd
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HSD_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return HSD_ERR_HIP;
+    void* scr = nullptr;
+    if (scratch_address(device, &scr) != hipSuccess) return HSD_ERR_HIP;
     hsd_ctx* ctx = new (std::nothrow) hsd_ctx();
     if (!ctx) return HSD_ERR_OOM;
     Ctx& c = ctx->c;
     c.device = device;
+    c.scratch = static_cast<unsigned char*>(scr);
     c.L = n_lambda;
     c.Lp = (n_lambda + 63) / 64 * 64;
     c.lnlam0 = ln0;
@@ -470,6 +503,37 @@ hsd_status hsd_solve(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t
         if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
     return run_solve(ctx, n_cells, u_dev, n_grains, grain_ids_host, j_dev, diag_dev, nullptr,
+                     static_cast<hipStream_t>(stream));
+}
+
+hsd_status hsd_solve_noalloc(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                             const int32_t* grain_ids_host, float* j_dev, float* diag_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (n_cells == 0 || n_grains == 0) return HSD_OK;
+    if (!u_dev || !grain_ids_host || !j_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    Batch& b = ctx->batch;
+    plan_batch(c, n_cells, n_grains, grain_ids_host, b);
+    // scratch layout: views | offs | items | pscale | P~ rows, each 256-byte aligned
+    const size_t o_views = 0;
+    const size_t o_offs = o_views + align256(sizeof(hsd::GrainView) * n_grains);
+    const size_t o_items = o_offs + align256(sizeof(long long) * n_grains);
+    const size_t o_pscale = o_items + align256(sizeof(int2) * std::max<size_t>(b.items.size(), 1));
+    const size_t o_pt = o_pscale + align256(sizeof(float) * static_cast<size_t>(n_cells) * n_grains);
+    const size_t need = o_pt + sizeof(float) * static_cast<size_t>(b.rows);
+    if (need > kScratchBytes)
+        return fail(ctx, HSD_ERR_INVALID_ARG,
+                    "hsd_solve_noalloc: the batch needs " + std::to_string(need) + " bytes of scratch, more than its " +
+                        std::to_string(kScratchBytes) + " (use hsd_solve, or fewer cells per call)");
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    unsigned char* base = c.scratch;
+    Bufs d{reinterpret_cast<float*>(base + o_pt), reinterpret_cast<float*>(base + o_pscale),
+           reinterpret_cast<hsd::GrainView*>(base + o_views), reinterpret_cast<long long*>(base + o_offs),
+           reinterpret_cast<int2*>(base + o_items), c.queue};
+    return run_batch(ctx, d, n_cells, u_dev, n_grains, grain_ids_host, j_dev, diag_dev, nullptr,
                      static_cast<hipStream_t>(stream));
 }
 

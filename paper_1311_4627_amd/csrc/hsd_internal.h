@@ -109,6 +109,7 @@ struct Ctx {
     unsigned* queue = nullptr;    // [kClasses] item counters of persistent launches
     double* sizew = nullptr;      size_t sizew_cap = 0;   // size-distribution weights
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
+    unsigned char* scratch = nullptr;   // device address of the library's fixed scratch array on this device
     int contract = 1;             // emission contraction: 0 FP32 products, 1 three BF16 products (hi/lo split)
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded

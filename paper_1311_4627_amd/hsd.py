@@ -33,7 +33,7 @@ SYMBOLS = (
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
-    "hsd_surrogate_save", "hsd_surrogate_load",
+    "hsd_surrogate_save", "hsd_surrogate_load", "hsd_solve_noalloc",
 )
 
 N_CLASSES = 4
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_grain_tables.restype = ctypes.c_int
     lib.hsd_solve.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
     lib.hsd_solve.restype = ctypes.c_int
+    lib.hsd_solve_noalloc.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
+    lib.hsd_solve_noalloc.restype = ctypes.c_int
     lib.hsd_solve_P.argtypes = [vp, i32, vp, i32, vp, vp]
     lib.hsd_solve_P.restype = ctypes.c_int
     lib.hsd_solve_from_rates.argtypes = [vp, i32, i32, vp, vp, vp, vp]
@@ -257,6 +259,20 @@ class Context:
                                  diag.data_ptr() if diag is not None else None, _stream_ptr(stream))
         if st != HSD_OK:
             self._raise(st, "hsd_solve")
+
+    def hsd_solve_noalloc(self, u, grain_ids: Sequence[int], j, diag=None, stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(j, torch.float32, (n_cells, ids.shape[0], self.L), "j")
+        if diag is not None:
+            _check_dev(diag, torch.float32, (n_cells, ids.shape[0], 4), "diag")
+        st = self._lib.hsd_solve_noalloc(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+                                         ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), j.data_ptr(),
+                                         diag.data_ptr() if diag is not None else None, _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_solve_noalloc")
 
     def hsd_solve_P(self, u, gid: int, P, stream=None):
         import torch
