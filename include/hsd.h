@@ -175,6 +175,37 @@ hsd_status hsd_sync(hsd_ctx* ctx);
 hsd_status hsd_set_timing(hsd_ctx* ctx, int32_t enable);
 hsd_status hsd_phase_ms(hsd_ctx* ctx, double* ms_host);
 
+/* ---- The table method (the yardstick of the learned surrogate) ----
+ * The paper's introduction names precomputed emissivity tables as the cheap
+ * alternative to the full solve that other codes use.  Here such a table
+ * holds, per grain, the plain solve (hsd_solve) of one reference field shape
+ * u_ref scaled to n_nodes field strengths U_k = 10^(log10U_lo + k (log10U_hi
+ * - log10U_lo) / (n_nodes - 1)), stored as y_k(lambda) = log2(j / A), A the
+ * pair's absorbed power (trapezoid of c u C_abs); a value without emission is
+ * stored as -1e30.  A cell is looked up by U = int u dlambda / int u_ref
+ * dlambda alone (clamped to the node range): its spectrum is
+ * A_cell 2^((1 - w) y_k + w y_(k+1)), k and w from log10 U on the node grid
+ * (zero where a node it draws on has no emission), so each looked-up
+ * spectrum carries the cell's own absorbed power and the reference field's
+ * shape.
+ *   u_ref_dev  [n_lambda] double, the reference field at U = 1;
+ *   table_dev  [n_grains][n_nodes][n_lambda] float (the caller's).
+ * hsd_table_build solves n_nodes x n_grains pairs (grows the workspace,
+ * synchronises once); hsd_table_eval writes j_dev [n_cells][n_grains][n_lambda]
+ * like hsd_solve.  Both asynchronous on `stream`. */
+hsd_status hsd_table_build(hsd_ctx* ctx, int32_t n_grains, const int32_t* grain_ids_host, const double* u_ref_dev,
+                           int32_t n_nodes, double log10U_lo, double log10U_hi, float* table_dev, void* stream);
+hsd_status hsd_table_eval(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                          const int32_t* grain_ids_host, const double* u_ref_dev, int32_t n_nodes, double log10U_lo,
+                          double log10U_hi, const float* table_dev, float* j_dev, void* stream);
+
+/* Measurement aid: the number of single-precision exponentials per second
+ * the context's device issues (one per heating rate in the solver; the
+ * benchmark quotes it beside the solver's roofline).  Runs a calibration
+ * kernel of independent exponential chains on an internal stream, ten timed
+ * launches after a warm-up.  Synchronous; allocates 2 MB for the duration. */
+hsd_status hsd_measure_exp2(hsd_ctx* ctx, double* per_second_host);
+
 /* The emissivity of a whole size distribution (Sec. 2.3, eq:convolution on
  * the discrete size grid): out[c][l] = sum_g w_g j[c][g][l], multiplied by
  * lambda_l when lambda_weighted != 0 (lambda j_lambda = nu j_nu, the form the
@@ -322,6 +353,18 @@ hsd_status hsd_sur_n_params(hsd_sur* sur, int64_t* n_params_host);
 /* Set (and reset the optimiser state) / read the FP32 parameter vector.  Synchronous. */
 hsd_status hsd_sur_set_params(hsd_sur* sur, const float* params_host);
 hsd_status hsd_sur_get_params(hsd_sur* sur, float* params_host);
+/* Training loss.  band_weight = 0 (the default) is the mean squared error
+ * over the normalised outputs.  With 0 < band_weight <= 1 each spectrum
+ * element k of a training row is weighted by W_k = (1 - band_weight) +
+ * band_weight L rho_k, where rho_k is element k's share of the bands the
+ * accuracy metric counts: over the 32 bands (as for the inputs) whose
+ * trapezoid integral of j = A 10^y holds at least 1e-3 of the row's total,
+ * rho_k = sum_b j_k q_kb / J_b / n_bands, q_kb node k's trapezoid weight in
+ * band b, J_b the band's integral (an error d in log10 j_k moves band b by
+ * ln 10 d j_k q_kb / J_b); the ratio output keeps weight 1.  The loss is the
+ * mean of W (yhat - y)^2.  Weights come from each row's raw targets.  Kept
+ * in checkpoints. */
+hsd_status hsd_sur_set_loss(hsd_sur* sur, float band_weight);
 /* Column means and standard deviations (> 0) of raw inputs [33] and targets
  * [L + 1].  Synchronous. */
 hsd_status hsd_sur_set_norm(hsd_sur* sur, const double* x_mean_host, const double* x_std_host,
@@ -365,7 +408,8 @@ hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const floa
  *   line 1   "HSDSUR 1"
  *   line 2   a one-line JSON header: "widths" (33, 256, 256, 256, L + 1),
  *            "n_params", "step" (Adam steps taken, which is also the position
- *            of the minibatch generator), "optimizer" (true when the Adam
+ *            of the minibatch generator), "loss_band_weight" (the setting of
+ *            hsd_sur_set_loss), "optimizer" (true when the Adam
  *            moments follow), "byte_order" "little", and "sections": name,
  *            element type "f32" and count of each array below, in order;
  *   then     the arrays, raw little-endian FP32, back to back: params
@@ -375,7 +419,7 @@ hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const floa
  * The network needs its statistics (HSD_ERR_STATE otherwise).
  * hsd_surrogate_load reads such a file into a network of the same widths
  * (HSD_ERR_INVALID_ARG for another shape, a truncated or foreign file): the
- * parameters, the statistics, and either the saved Adam moments and step or,
+ * parameters, the statistics, the loss setting, and either the saved Adam moments and step or,
  * for a weights-only file, zero moments and step 0.  A network resumed from a
  * checkpoint trains on exactly as the saved one would: hsd_sur_train calls
  * after hsd_surrogate_load give the same bits as the same calls made on the

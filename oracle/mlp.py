@@ -110,6 +110,41 @@ def band_rel_error(j: np.ndarray, jref: np.ndarray, lam: np.ndarray, min_share: 
     return err.max(axis=-1)
 
 
+def band_node_weights(lam: np.ndarray) -> np.ndarray:
+    """q [32, L]: the trapezoid weight of grid node k in band b, so that
+    band_integrals(f) = q @ f."""
+    L = lam.shape[0]
+    e = band_edges(L)
+    q = np.zeros((N_BANDS, L))
+    for b in range(N_BANDS):
+        for k in range(e[b], e[b + 1]):          # segment k .. k+1 lies in band b
+            h = 0.5 * (lam[k + 1] - lam[k])
+            q[b, k] += h
+            q[b, k + 1] += h
+    return q
+
+
+def loss_weights(Y: np.ndarray, lam: np.ndarray, band_weight: float) -> np.ndarray:
+    """Per-element weights W [n, L + 1] of the band-weighted loss from raw
+    targets Y (log10 of j / A, then the ratio): with j_k = 10^y_k and J_b the
+    band integrals, the bands counted are those with J_b >= 1e-3 sum J;
+    rho_k = sum over counted b of j_k q_kb / J_b, divided by their number;
+    W_k = (1 - band_weight) + band_weight L rho_k, and 1 for the ratio output.
+    (An error d_k in log10 j_k changes J_b by ln 10 sum_k d_k j_k q_kb, so
+    these weights put the loss where the band-integrated metric looks.)"""
+    Y = np.atleast_2d(np.asarray(Y, dtype=np.float64))
+    L = lam.shape[0]
+    q = band_node_weights(lam)
+    j = 10.0 ** (Y[:, :L] - Y[:, :L].max(axis=1, keepdims=True))
+    J = j @ q.T                                                   # [n, 32]
+    on = J >= 1e-3 * J.sum(axis=1, keepdims=True)
+    share = np.where(on, 1.0 / np.where(on, J, 1.0), 0.0)        # 1 / J_b on counted bands
+    rho = j * (share @ q) / on.sum(axis=1, keepdims=True)
+    W = np.ones_like(Y)
+    W[:, :L] = (1.0 - band_weight) + band_weight * L * rho
+    return W
+
+
 # ---- network ----------------------------------------------------------------------
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
@@ -182,15 +217,17 @@ def forward(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, bf16: bool =
     return h, (hs, zs)
 
 
-def loss_and_grad(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray, bf16: bool = False):
-    """L = mean over samples and outputs of (yhat - y)^2 and dL/dparams
-    (flat, same layout)."""
+def loss_and_grad(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray, bf16: bool = False,
+                  weights: np.ndarray = None):
+    """L = mean over samples and outputs of W (yhat - y)^2 (W = 1 unless
+    per-element weights are given) and dL/dparams (flat, same layout)."""
     layers = unpack(flat, widths)
     yhat, (hs, zs) = forward(flat, widths, X, bf16)
     n, m = yhat.shape
     r = yhat - Y
-    loss = float(np.mean(r * r))
-    dz = 2.0 * r / (n * m)
+    W = np.ones_like(r) if weights is None else np.asarray(weights, dtype=np.float64)
+    loss = float(np.mean(W * r * r))
+    dz = 2.0 * W * r / (n * m)
     grads = [None] * len(layers)
     for i in range(len(layers) - 1, -1, -1):
         W, _ = layers[i]
@@ -203,7 +240,8 @@ def loss_and_grad(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.
     return loss, pack(grads)
 
 
-def grad_abs_terms(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+def grad_abs_terms(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np.ndarray,
+                   weights: np.ndarray = None) -> np.ndarray:
     """For every parameter, the sum of the absolute values of the terms whose
     sum is its gradient in the BF16-operand backward pass of loss_and_grad
     (same layout as the gradient): sum_n |bf16(dz_n,o)| |bf16(h_n,i)| for a
@@ -214,7 +252,8 @@ def grad_abs_terms(flat: np.ndarray, widths: Sequence[int], X: np.ndarray, Y: np
     layers = unpack(flat, widths)
     yhat, (hs, zs) = forward(flat, widths, X, bf16=True)
     n, m = yhat.shape
-    dz = 2.0 * (yhat - Y) / (n * m)
+    W = np.ones_like(yhat) if weights is None else np.asarray(weights, dtype=np.float64)
+    dz = 2.0 * W * (yhat - Y) / (n * m)
     out = [None] * len(layers)
     for i in range(len(layers) - 1, -1, -1):
         W, _ = layers[i]

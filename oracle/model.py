@@ -129,12 +129,21 @@ def planck_table(T: np.ndarray, E: np.ndarray, lam: np.ndarray) -> np.ndarray:
 _SETUP_CACHE: Dict[tuple, GrainSetup] = {}
 
 
+def _setup_key(grain, lam: np.ndarray) -> tuple:
+    return (grain.composition, grain.radius_cm, grain.n_bins, grain.E_lo_erg, grain.E_hi_erg,
+            grain.theta_K, grain.n_atoms, lam.shape[0], float(lam[0]), float(lam[-1]),
+            float(grain.cabs_cm2[0]), float(grain.cabs_cm2[-1]), grain.longwave_index)
+
+
+def preload_setup(grain, lam: np.ndarray, setup: GrainSetup) -> None:
+    """Put a setup computed elsewhere (another process) into the cache."""
+    _SETUP_CACHE[_setup_key(grain, lam)] = setup
+
+
 def grain_setup(grain, lam: np.ndarray) -> GrainSetup:
     """Per-grain precompute: enthalpy grid, bin temperatures from the Debye
     heat capacity, cooling rates and the Planck table.  Cached per grain."""
-    key = (grain.composition, grain.radius_cm, grain.n_bins, grain.E_lo_erg, grain.E_hi_erg,
-           grain.theta_K, grain.n_atoms, lam.shape[0], float(lam[0]), float(lam[-1]),
-           float(grain.cabs_cm2[0]), float(grain.cabs_cm2[-1]), grain.longwave_index)
+    key = _setup_key(grain, lam)
     hit = _SETUP_CACHE.get(key)
     if hit is not None:
         return hit

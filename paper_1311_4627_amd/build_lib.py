@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libhsd.so")
 
-SOURCES = ["hsd_api.hip", "hsd_precompute.hip", "hsd_solve.hip", "hsd_contract.hip", "hsd_surrogate.hip"]
+SOURCES = ["hsd_api.hip", "hsd_precompute.hip", "hsd_solve.hip", "hsd_contract.hip", "hsd_surrogate.hip",
+           "hsd_measure.hip", "hsd_table.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

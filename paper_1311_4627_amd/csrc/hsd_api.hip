@@ -46,10 +46,20 @@ struct SurWork {
     long long* pairs = nullptr;   size_t pairs_cap = 0;
 };
 
+// Workspace of the table method (grown on demand).
+struct TableWork {
+    double* u = nullptr;          size_t u_cap = 0;       // node fields [K][L]
+    float* j = nullptr;           size_t j_cap = 0;       // node spectra [K][G][L]
+    double* A = nullptr;          size_t A_cap = 0;       // absorbed powers [rows][G]
+    double* energy = nullptr;     size_t energy_cap = 0;  // field energies [cells], then the reference's
+    const double** cabs = nullptr; size_t cabs_cap = 0;   // C_abs table of each listed grain
+};
+
 struct hsd_ctx {
     Ctx c;
     Batch batch;     // host description of the last eager solve
     SurWork sw;
+    TableWork tw;
 };
 
 struct hsd_sur {
@@ -418,6 +428,8 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(w.xb); hipFree(w.wcT);
     hipFree(w.sel); hipFree(w.cabs); hipFree(w.loga); hipFree(w.cnt); hipFree(w.seg_off); hipFree(w.seg_cnt);
     hipFree(w.cellmap); hipFree(w.pairs);
+    TableWork& tw = ctx->tw;
+    hipFree(tw.u); hipFree(tw.j); hipFree(tw.A); hipFree(tw.energy); hipFree(tw.cabs);
     hipFree(c.Pt);
     hipFree(c.pscale);
     hipFree(c.diag_tmp);
@@ -870,6 +882,90 @@ hsd_status hsd_phase_ms(hsd_ctx* ctx, double* ms) {
     return HSD_OK;
 }
 
+namespace {
+
+// C_abs tables of the listed grains, on the device, for the energy kernel.
+hsd_status table_cabs(hsd_ctx* ctx, int32_t n_grains, const int32_t* ids, hipStream_t s) {
+    TableWork& tw = ctx->tw;
+    std::vector<const double*> p(n_grains);
+    for (int g = 0; g < n_grains; ++g) p[g] = ctx->c.grains[ids[g]].cabs;
+    HSD_HIP(ctx, grow(tw.cabs, tw.cabs_cap, static_cast<size_t>(n_grains)));
+    HSD_HIP(ctx, hipMemcpyAsync(tw.cabs, p.data(), sizeof(double*) * n_grains, hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipStreamSynchronize(s));      // the host vector goes out of scope
+    return HSD_OK;
+}
+
+hsd_status table_args(hsd_ctx* ctx, int32_t n_grains, const int32_t* ids, int32_t n_nodes, double lo, double hi) {
+    if (n_grains <= 0 || !ids) return fail(ctx, HSD_ERR_INVALID_ARG, "need n_grains > 0 and grain ids");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, ids[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    if (n_nodes < 2 || n_nodes > 4096) return fail(ctx, HSD_ERR_INVALID_ARG, "need 2 <= n_nodes <= 4096");
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "need finite log10U_lo < log10U_hi");
+    return HSD_OK;
+}
+
+}  // namespace
+
+hsd_status hsd_table_build(hsd_ctx* ctx, int32_t n_grains, const int32_t* grain_ids_host, const double* u_ref_dev,
+                           int32_t n_nodes, double log10U_lo, double log10U_hi, float* table_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    hsd_status st = table_args(ctx, n_grains, grain_ids_host, n_nodes, log10U_lo, log10U_hi);
+    if (st != HSD_OK) return st;
+    if (!u_ref_dev || !table_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    Ctx& c = ctx->c;
+    TableWork& tw = ctx->tw;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    const size_t K = static_cast<size_t>(n_nodes), G = static_cast<size_t>(n_grains);
+    HSD_HIP(ctx, grow(tw.u, tw.u_cap, K * c.L));
+    HSD_HIP(ctx, grow(tw.j, tw.j_cap, K * G * c.L));
+    HSD_HIP(ctx, grow(tw.A, tw.A_cap, K * G));
+    st = table_cabs(ctx, n_grains, grain_ids_host, s);
+    if (st != HSD_OK) return st;
+    const double step = (log10U_hi - log10U_lo) / (n_nodes - 1);
+    HSD_HIP(ctx, hsd::launch_node_fields(u_ref_dev, log10U_lo, step, n_nodes, c.L, tw.u, s));
+    st = run_solve(ctx, n_nodes, tw.u, n_grains, grain_ids_host, tw.j, nullptr, nullptr, s);
+    if (st != HSD_OK) return st;
+    HSD_HIP(ctx, hsd::launch_cell_energies(tw.u, c.lam, n_nodes, c.L, n_grains, tw.cabs, nullptr, tw.A, s));
+    HSD_HIP(ctx, hsd::launch_table_logs(tw.j, tw.A, n_nodes, n_grains, c.L, table_dev, s));
+    return HSD_OK;
+}
+
+hsd_status hsd_table_eval(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                          const int32_t* grain_ids_host, const double* u_ref_dev, int32_t n_nodes, double log10U_lo,
+                          double log10U_hi, const float* table_dev, float* j_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    hsd_status st = table_args(ctx, n_grains, grain_ids_host, n_nodes, log10U_lo, log10U_hi);
+    if (st != HSD_OK) return st;
+    if (n_cells == 0) return HSD_OK;
+    if (!u_dev || !u_ref_dev || !table_dev || !j_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    Ctx& c = ctx->c;
+    TableWork& tw = ctx->tw;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    const size_t G = static_cast<size_t>(n_grains);
+    HSD_HIP(ctx, grow(tw.A, tw.A_cap, static_cast<size_t>(n_cells) * G));
+    HSD_HIP(ctx, grow(tw.energy, tw.energy_cap, static_cast<size_t>(n_cells) + 1));
+    st = table_cabs(ctx, n_grains, grain_ids_host, s);
+    if (st != HSD_OK) return st;
+    HSD_HIP(ctx, hsd::launch_cell_energies(u_dev, c.lam, n_cells, c.L, n_grains, tw.cabs, tw.energy, tw.A, s));
+    HSD_HIP(ctx, hsd::launch_cell_energies(u_ref_dev, c.lam, 1, c.L, 0, tw.cabs, tw.energy + n_cells, nullptr, s));
+    const double step = (log10U_hi - log10U_lo) / (n_nodes - 1);
+    HSD_HIP(ctx, hsd::launch_table_eval(tw.energy, tw.energy + n_cells, tw.A, table_dev, n_nodes, log10U_lo, step,
+                                        n_cells, n_grains, c.L, j_dev, s));
+    return HSD_OK;
+}
+
+hsd_status hsd_measure_exp2(hsd_ctx* ctx, double* per_second_host) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!per_second_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    HSD_HIP(ctx, hipSetDevice(ctx->c.device));
+    HSD_HIP(ctx, hsd::measure_exp2(per_second_host));
+    return HSD_OK;
+}
+
 hsd_status hsd_sync(hsd_ctx* ctx) {
     if (!ctx) return HSD_ERR_INVALID_ARG;
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
@@ -947,6 +1043,13 @@ hsd_status hsd_sur_get_params(hsd_sur* p, float* params_host) {
     return HSD_OK;
 }
 
+hsd_status hsd_sur_set_loss(hsd_sur* p, float band_weight) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    if (!(band_weight >= 0.f && band_weight <= 1.f)) return fail(p->ctx, HSD_ERR_INVALID_ARG, "band_weight must be in [0, 1]");
+    p->s.band_weight = band_weight;
+    return HSD_OK;
+}
+
 hsd_status hsd_sur_set_norm(hsd_sur* p, const double* x_mean, const double* x_std, const double* y_mean,
                             const double* y_std) {
     if (!p) return HSD_ERR_INVALID_ARG;
@@ -1020,6 +1123,16 @@ bool json_number(const std::string& h, const char* key, long long& out) {
     return end != p;
 }
 
+bool json_real(const std::string& h, const char* key, double& out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = h.find(k);
+    if (at == std::string::npos) return false;
+    const char* p = h.c_str() + at + k.size();
+    char* end = nullptr;
+    out = std::strtod(p, &end);
+    return end != p;
+}
+
 bool json_bool(const std::string& h, const char* key, bool& out) {
     const std::string k = std::string("\"") + key + "\":";
     const size_t at = h.find(k);
@@ -1066,7 +1179,10 @@ hsd_status hsd_surrogate_save(hsd_sur* p, const char* path, int32_t flags) {
     const std::vector<SurSection> secs = sur_sections(s, opt);
     std::string h = "{\"format\": \"hsd-surrogate\", \"widths\": [";
     for (int i = 0; i < 5; ++i) h += std::to_string(s.widths[i]) + (i < 4 ? ", " : "]");
+    char bw[32];
+    std::snprintf(bw, sizeof(bw), "%.9g", static_cast<double>(s.band_weight));
     h += ", \"n_params\": " + std::to_string(s.n_params) + ", \"step\": " + std::to_string(s.t) +
+         ", \"loss_band_weight\": " + bw +
          ", \"optimizer\": " + (opt ? "true" : "false") + ", \"byte_order\": \"little\", \"sections\": [";
     for (size_t i = 0; i < secs.size(); ++i)
         h += std::string(i ? ", " : "") + "{\"name\": \"" + secs[i].name + "\", \"dtype\": \"f32\", \"count\": " +
@@ -1113,9 +1229,11 @@ hsd_status hsd_surrogate_load(hsd_sur* p, const char* path) {
     const std::string h = data.substr(magic.size(), eol - magic.size());
     long long np = 0, step = 0;
     bool opt = false;
+    double bw = 0.0;
     if (!json_number(h, "n_params", np) || !json_number(h, "step", step) || !json_bool(h, "optimizer", opt) ||
-        h.find("\"byte_order\": \"little\"") == std::string::npos)
+        !json_real(h, "loss_band_weight", bw) || h.find("\"byte_order\": \"little\"") == std::string::npos)
         return fail(ctx, HSD_ERR_INVALID_ARG, "malformed header");
+    if (!(bw >= 0.0 && bw <= 1.0)) return fail(ctx, HSD_ERR_INVALID_ARG, "loss_band_weight outside [0, 1]");
     std::string want = "\"widths\": [";
     for (int i = 0; i < 5; ++i) want += std::to_string(s.widths[i]) + (i < 4 ? ", " : "]");
     if (h.find(want) == std::string::npos || np != s.n_params)
@@ -1147,6 +1265,7 @@ hsd_status hsd_surrogate_load(hsd_sur* p, const char* path) {
         HSD_HIP(ctx, hipMemset(s.v, 0, sizeof(float) * s.n_params));
     }
     s.t = opt ? step : 0;
+    s.band_weight = static_cast<float>(bw);
     s.have_norm = true;
     s.wb_fresh = false;
     return HSD_OK;

@@ -182,6 +182,16 @@ struct DiagLaunch {
     long long n_list = 0;
 };
 hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
+// The table method (hsd_table.hip).
+hipError_t launch_node_fields(const double* u_ref, double lo, double step, int n_nodes, int L, double* u_out,
+                              hipStream_t s);
+hipError_t launch_cell_energies(const double* u, const double* lam, int n_cells, int L, int G,
+                                const double* const* cabs, double* energy, double* A, hipStream_t s);
+hipError_t launch_table_logs(const float* j, const double* A, int n_nodes, int G, int L, float* table, hipStream_t s);
+hipError_t launch_table_eval(const double* energy, const double* ref_energy, const double* A, const float* table,
+                             int n_nodes, double lo, double step, int n_cells, int G, int L, float* j, hipStream_t s);
+// Exponentials per second that the device issues (hsd_measure.hip).
+hipError_t measure_exp2(double* per_s);
 hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int lw,
                            double* out, hipStream_t s);
 
@@ -211,10 +221,16 @@ struct Sur {
     float* ym = nullptr;       // [n_out] target means / stds
     float* ys = nullptr;
     float* wq = nullptr;       // [n_out] 4 pi x trapezoid weights (0 for the ratio output)
+    float band_weight = 0.f;   // bw of the band-weighted loss (0: plain mean squared error)
+    float* bw_l = nullptr;     // [L] trapezoid half-segment of each node to its left / right
+    float* bw_r = nullptr;
+    int* segband = nullptr;    // [L - 1] band of each grid segment
+    int* bedge = nullptr;      // [33] first segment of each band, then L - 1
     bool have_norm = false;
     // training workspace (grown on demand)
     int cap_B = 0;
     float *Xb = nullptr, *Yb = nullptr, *Z[3] = {}, *H[3] = {}, *Yh = nullptr, *dY = nullptr, *dZ[2] = {};
+    float* Wb = nullptr;       // [B][n_out] loss weights of the minibatch (band-weighted loss)
     long long* idx = nullptr;
     double* loss = nullptr;    // the minibatch loss, then the loss reduction's per-block partials
     int splits = 1;            // K splits of the weight-gradient products

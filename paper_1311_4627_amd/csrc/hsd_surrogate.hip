@@ -294,6 +294,67 @@ __global__ void __launch_bounds__(256) k_gather(const float* X, const float* Y, 
             Yb[static_cast<long long>(b) * L + k] = (Y[r * L + k] - ym[k]) / ys[k];
 }
 
+// Band-weighted loss: per-element weights of each minibatch row from its raw
+// targets y_k = log10(j_k / A).  The accuracy that matters is that of the
+// spectrum integrated over the 32 bands (band b: grid nodes e_b .. e_(b+1),
+// trapezoid rule) that hold at least 1e-3 of the row's emitted power; an
+// error d_k in log10 j_k moves band b by ln 10 sum_k d_k j_k q_kb / J_b, so
+// the loss weights element k by rho_k = sum over such bands b of
+// j_k q_kb / J_b / n_bands (q_kb: node k's trapezoid weight inside band b;
+// sum_k rho_k = 1):  W_k = (1 - bw) + bw L rho_k, and 1 for the ratio output.
+// One block per row; the band sums run in a fixed order.
+__global__ void __launch_bounds__(256) k_loss_weights(const float* Y, const long long* idx, int L, int n_out,
+                                                      const float* wl, const float* wr, const int* segband,
+                                                      const int* bedge, float bw, float* W) {
+    __shared__ float f[kMaxLambda];
+    __shared__ float seg[kMaxLambda];
+    __shared__ double J[kBands];
+    __shared__ float red[4];
+    __shared__ float inv_n;
+    const int b = blockIdx.x;
+    const float* y = Y + idx[b] * n_out;
+    float mx = -INFINITY;
+    for (int k = threadIdx.x; k < L; k += 256) mx = fmaxf(mx, y[k]);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    for (int k = threadIdx.x; k < L; k += 256) f[k] = exp2f((y[k] - mx) * 3.32192809488736234787f);
+    __syncthreads();
+    for (int k = threadIdx.x; k + 1 < L; k += 256) seg[k] = wr[k] * f[k] + wl[k + 1] * f[k + 1];
+    __syncthreads();
+    if (threadIdx.x < kBands) {
+        double t = 0.0;
+        for (int k = bedge[threadIdx.x]; k < bedge[threadIdx.x + 1]; ++k) t += seg[k];
+        J[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < kBands; ++q) tot += J[q];
+        int nc = 0;
+        for (int q = 0; q < kBands; ++q) {
+            const bool on = J[q] >= 1e-3 * tot && J[q] > 0.0;
+            nc += on ? 1 : 0;
+            if (!on) J[q] = 0.0;          // 0 marks a band outside the metric
+        }
+        inv_n = nc > 0 ? 1.f / static_cast<float>(nc) : 0.f;
+    }
+    __syncthreads();
+    float* w = W + static_cast<long long>(b) * n_out;
+    for (int k = threadIdx.x; k < n_out; k += 256) {
+        float wk = 1.f;
+        if (k < L) {
+            double rho = 0.0;
+            if (k + 1 < L && J[segband[k]] > 0.0) rho += wr[k] * f[k] / J[segband[k]];
+            if (k > 0 && J[segband[k - 1]] > 0.0) rho += wl[k] * f[k] / J[segband[k - 1]];
+            wk = (1.f - bw) + bw * static_cast<float>(L) * static_cast<float>(rho) * inv_n;
+        }
+        w[k] = wk;
+    }
+}
+
 // Minibatch indices from a counter-based generator (SplitMix64 of seed and
 // position; uniform enough for sampling with replacement).
 __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
@@ -311,18 +372,20 @@ __global__ void k_batch_idx(unsigned long long seed, long long step, int B, long
 }
 
 // Loss and its gradient with respect to the network output:
-// L = mean (yhat - y)^2, dL/dyhat = 2 (yhat - y) / (B L).  A fixed grid walks
+// L = mean W (yhat - y)^2 (W = 1 without band weighting),
+// dL/dyhat = 2 W (yhat - y) / (B L).  A fixed grid walks
 // the elements; each block writes its FP64 partial sum of squares to its own
 // slot, and k_loss_sum adds the slots in order.
-__global__ void __launch_bounds__(256) k_loss(const float* yhat, const float* y, long long n, float scale,
-                                              float* dy, double* part) {
+__global__ void __launch_bounds__(256) k_loss(const float* yhat, const float* y, const float* wt, long long n,
+                                              float scale, float* dy, double* part) {
     __shared__ double red[4];
     double l = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * 256) {
         const float r = yhat[i] - y[i];
-        dy[i] = scale * r;
-        l += static_cast<double>(r) * r;
+        const float wr = wt ? wt[i] * r : r;
+        dy[i] = scale * wr;
+        l += static_cast<double>(wr) * r;
     }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) l += __shfl_xor(l, m, 64);
@@ -899,11 +962,35 @@ hipError_t sur_alloc(Sur& s) {
         }
         e = hipMemcpy(s.wq, wq.data(), sizeof(float) * s.n_out, hipMemcpyHostToDevice);
     }
+    // trapezoid half-segments of every node (to its left and right) and the
+    // band of every segment, for the band-weighted loss
+    al(s.bw_l, s.L); al(s.bw_r, s.L); al(s.segband, std::max(s.L - 1, 1)); al(s.bedge, kBands + 1);
+    if (e == hipSuccess) {
+        const std::vector<double>& lam = s.c->lam_host;
+        const int L = s.L;
+        std::vector<float> l(L, 0.f), r(L, 0.f);
+        std::vector<int> sb(std::max(L - 1, 1), 0), be(kBands + 1);
+        for (int k = 0; k < L; ++k) {
+            if (k > 0) l[k] = static_cast<float>(0.5 * (lam[k] - lam[k - 1]));
+            if (k + 1 < L) r[k] = static_cast<float>(0.5 * (lam[k + 1] - lam[k]));
+        }
+        for (int q = 0; q <= kBands; ++q) be[q] = static_cast<int>((static_cast<long long>(q) * (L - 1)) / kBands);
+        for (int q = 0; q < kBands; ++q)
+            for (int k = be[q]; k < be[q + 1]; ++k) sb[k] = q;
+        e = hipMemcpy(s.bw_l, l.data(), sizeof(float) * L, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s.bw_r, r.data(), sizeof(float) * L, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s.segband, sb.data(), sizeof(int) * sb.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s.bedge, be.data(), sizeof(int) * be.size(), hipMemcpyHostToDevice);
+    }
     return e;
 }
 
 void sur_free(Sur& s) {
-    for (float* p : {s.w, s.g, s.m, s.v, s.we, s.xm, s.xs, s.ym, s.ys, s.wq, s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
+    for (float* p : {s.w, s.g, s.m, s.v, s.we, s.xm, s.xs, s.ym, s.ys, s.wq, s.Xb, s.Yb, s.Yh, s.dY, s.Wb, s.bw_l,
+                     s.bw_r})
+        (void)hipFree(p);
+    (void)hipFree(s.segband);
+    (void)hipFree(s.bedge);
     for (int i = 0; i < 3; ++i) {
         (void)hipFree(s.Z[i]);
         (void)hipFree(s.H[i]);
@@ -918,7 +1005,7 @@ void sur_free(Sur& s) {
 hipError_t sur_grow(Sur& s, int B) {
     if (B <= s.cap_B) return hipSuccess;
     hipError_t e = hipDeviceSynchronize();
-    for (float* p : {s.Xb, s.Yb, s.Yh, s.dY}) (void)hipFree(p);
+    for (float* p : {s.Xb, s.Yb, s.Yh, s.dY, s.Wb}) (void)hipFree(p);
     for (int i = 0; i < 3; ++i) {
         (void)hipFree(s.Z[i]);
         (void)hipFree(s.H[i]);
@@ -929,14 +1016,14 @@ hipError_t sur_grow(Sur& s, int B) {
         s.dZ[i] = nullptr;
     }
     (void)hipFree(s.idx);
-    s.Xb = s.Yb = s.Yh = s.dY = nullptr;
+    s.Xb = s.Yb = s.Yh = s.dY = s.Wb = nullptr;
     s.idx = nullptr;
     s.cap_B = 0;
     auto al = [&](auto*& p, size_t n) {
         if (e == hipSuccess) e = hipMalloc(&p, n * sizeof(*p));
     };
     const size_t b = static_cast<size_t>(B);
-    al(s.Xb, b * 33); al(s.Yb, b * s.n_out); al(s.Yh, b * s.n_out); al(s.dY, b * s.n_out);
+    al(s.Xb, b * 33); al(s.Yb, b * s.n_out); al(s.Yh, b * s.n_out); al(s.dY, b * s.n_out); al(s.Wb, b * s.n_out);
     for (int i = 0; i < 3; ++i) {
         al(s.Z[i], b * 256);
         al(s.H[i], b * 256);
@@ -1104,8 +1191,8 @@ hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st) {
 hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
     const long long n = static_cast<long long>(B) * s.n_out;
     const int blocks = static_cast<int>(std::min<long long>(kLossBlocks, (n + 255) / 256));
-    hipLaunchKernelGGL(k_loss, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, s.Yh, s.Yb, n,
-                       2.0f / static_cast<float>(n), s.dY, s.loss + 1);
+    hipLaunchKernelGGL(k_loss, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, s.Yh, s.Yb,
+                       s.band_weight > 0.f ? s.Wb : nullptr, n, 2.0f / static_cast<float>(n), s.dY, s.loss + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, st, s.loss + 1, blocks, s.loss);
@@ -1114,7 +1201,13 @@ hipError_t sur_loss(Sur& s, int B, hipStream_t st) {
 
 hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st) {
     hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, st, X, Y, s.idx, B, s.n_out, s.xm, s.xs, s.ym, s.ys, s.Xb, s.Yb);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && Y && s.band_weight > 0.f) {
+        hipLaunchKernelGGL(k_loss_weights, dim3(B), dim3(256), 0, st, Y, s.idx, s.L, s.n_out, s.bw_l, s.bw_r,
+                           s.segband, s.bedge, s.band_weight, s.Wb);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st) {

@@ -33,7 +33,8 @@ SYMBOLS = (
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
-    "hsd_surrogate_save", "hsd_surrogate_load", "hsd_solve_noalloc",
+    "hsd_surrogate_save", "hsd_surrogate_load", "hsd_solve_noalloc", "hsd_sur_set_loss", "hsd_measure_exp2",
+    "hsd_table_build", "hsd_table_eval",
 )
 
 N_CLASSES = 4
@@ -149,6 +150,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_size_convolve.restype = ctypes.c_int
     lib.hsd_surrogate_save.argtypes = [vp, ctypes.c_char_p, i32]
     lib.hsd_surrogate_save.restype = ctypes.c_int
+    lib.hsd_table_build.argtypes = [vp, i32, ctypes.POINTER(i32), vp, i32, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.hsd_table_build.restype = ctypes.c_int
+    lib.hsd_table_eval.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, i32, ctypes.c_double, ctypes.c_double,
+                                   vp, vp, vp]
+    lib.hsd_table_eval.restype = ctypes.c_int
+    lib.hsd_measure_exp2.argtypes = [vp, dp]
+    lib.hsd_measure_exp2.restype = ctypes.c_int
+    lib.hsd_sur_set_loss.argtypes = [vp, ctypes.c_float]
+    lib.hsd_sur_set_loss.restype = ctypes.c_int
     lib.hsd_surrogate_load.argtypes = [vp, ctypes.c_char_p]
     lib.hsd_surrogate_load.restype = ctypes.c_int
     return lib
@@ -426,6 +436,40 @@ class Context:
         if st != HSD_OK:
             self._raise(st, "hsd_size_convolve")
 
+    def hsd_table_build(self, grain_ids: Sequence[int], u_ref, log10U_lo: float, log10U_hi: float, table, stream=None):
+        import torch
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        G, K = int(ids.shape[0]), int(table.shape[1])
+        _check_dev(u_ref, torch.float64, (self.L,), "u_ref")
+        _check_dev(table, torch.float32, (G, K, self.L), "table")
+        st = self._lib.hsd_table_build(self._h, G, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), u_ref.data_ptr(),
+                                       K, float(log10U_lo), float(log10U_hi), table.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_table_build")
+
+    def hsd_table_eval(self, u, grain_ids: Sequence[int], u_ref, log10U_lo: float, log10U_hi: float, table, j,
+                       stream=None):
+        import torch
+        n_cells = int(u.shape[0])
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        G, K = int(ids.shape[0]), int(table.shape[1])
+        _check_dev(u, torch.float64, (n_cells, self.L), "u")
+        _check_dev(u_ref, torch.float64, (self.L,), "u_ref")
+        _check_dev(table, torch.float32, (G, K, self.L), "table")
+        _check_dev(j, torch.float32, (n_cells, G, self.L), "j")
+        st = self._lib.hsd_table_eval(self._h, n_cells, u.data_ptr(), G, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      u_ref.data_ptr(), K, float(log10U_lo), float(log10U_hi), table.data_ptr(),
+                                      j.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_table_eval")
+
+    def hsd_measure_exp2(self) -> float:
+        r = ctypes.c_double()
+        st = self._lib.hsd_measure_exp2(self._h, ctypes.byref(r))
+        if st != HSD_OK:
+            self._raise(st, "hsd_measure_exp2")
+        return float(r.value)
+
     def hsd_sync(self):
         st = self._lib.hsd_sync(self._h)
         if st != HSD_OK:
@@ -550,6 +594,9 @@ class Surrogate:
         self._check(self._lib.hsd_sur_train(self._h, n, X.data_ptr(), Y.data_ptr(), int(steps), int(batch),
                                             float(lr), int(seed), _fptr(trace)), "hsd_sur_train")
         return trace[:int(steps)]
+
+    def hsd_sur_set_loss(self, band_weight: float):
+        self._check(self._lib.hsd_sur_set_loss(self._h, float(band_weight)), "hsd_sur_set_loss")
 
     def hsd_surrogate_save(self, path: str, weights_only: bool = False):
         self._check(self._lib.hsd_surrogate_save(self._h, os.fsencode(path), SAVE_WEIGHTS_ONLY if weights_only else 0),

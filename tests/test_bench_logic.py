@@ -3,7 +3,6 @@ and the error measures it reports (band errors, relative error of j against
 the oracle)."""
 
 import numpy as np
-import torch
 
 import bench
 import synth
@@ -61,16 +60,25 @@ def test_j_rel_err_masks_tiny_reference_values():
     assert bench.j_rel_err(np.ones(3), np.zeros(3)) == float("inf")
 
 
-def test_oracle_error_compares_the_sampled_pairs():
-    L = 7
-    j = torch.ones((5, 3, L), dtype=torch.float32)
-    ref = np.ones((2, L))
-    samples = [(1, [0, 4], ref.copy()), (2, [3], ref[:1].copy())]
-    j[4, 1, 2] = 1.0 + 2.0 ** -10                # the largest error, on a sampled pair
-    j[2, 1, 0] = 10.0                            # not sampled: ignored
-    rep = bench.oracle_error(j, samples)
-    assert rep["pairs"] == 3
-    assert abs(rep["max_rel_err_j"] - 2.0 ** -10) < 1e-12
-    assert rep["within_tol"] is False and rep["tol"] == bench.J_TOL
-    j[4, 1, 2] = 1.0
-    assert bench.oracle_error(j, samples)["within_tol"] is True
+def test_roofline_accounting():
+    # nine lane-cycles per on-grid rate against 256 CUs x 64 lanes x 2.4 GHz;
+    # the exponential (one per rate) against half that lane rate
+    r = bench.roofline(rates=4.0e10, solve_ms=40.0, traffic=None)
+    assert r["bound"] == "alu" and r["peak"] == 256 * 64 * 2.4e9 / 1e12
+    assert abs(r["achieved"] - 4.0e10 * 9 / 0.040 / 1e12) < 1e-9
+    assert abs(r["frac"] - 4.0e10 * 9 / 0.040 / (256 * 64 * 2.4e9)) < 1e-12
+    assert abs(r["exp2"]["frac"] - 4.0e10 / 0.040 / (256 * 64 * 2.4e9 / 2)) < 1e-12
+
+
+def test_oracle_pairs_are_the_oracle_spectra():
+    # the CPU leg's pool (setups handed to the solving workers) returns what
+    # the oracle computes for each pair directly
+    import oracle
+    from synth.fields import make_fields
+    w = synth.workload("c1_tiny")
+    rec, spectra = bench.oracle_pairs("c1_tiny", w.n_cells, {0: [3, 40]})
+    assert set(spectra) == {(3, 0), (40, 0)}
+    u = make_fields(w.lam_cm, w.field_recipe, w.n_cells, cells=np.array([3, 40]))
+    for k, c in enumerate((3, 40)):
+        assert np.array_equal(spectra[(c, 0)], oracle.solve_pair(u[k], w.grains[0], w.lam_cm)[1])
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] == bench.CPU_PROCS

@@ -105,12 +105,14 @@ def test_features_do_not_depend_on_the_selection(hsd, small):
         assert np.array_equal(As.cpu().numpy().reshape(n, len(cols)), A[:, cols])
 
 
-def test_loss_and_gradient_match_bf16_reference(hsd, small):
+@pytest.mark.parametrize("band_weight", [0.0, 0.8])
+def test_loss_and_gradient_match_bf16_reference(hsd, small, band_weight):
     d = small
     sur = hsd.Surrogate(d["ctx"])
     flat = ssur.init_params(ssur.n_outputs(d["w"].n_lambda), seed=99)
     sur.hsd_sur_set_params(flat)
     sur.hsd_sur_fit_norm(d["X"], d["Y"])
+    sur.hsd_sur_set_loss(band_weight)
     xm, xs, ym, ys = sur.hsd_sur_get_norm()
     Xr, Yr = d["X"].cpu().numpy().astype(np.float64), d["Y"].cpu().numpy().astype(np.float64)
     mu, sd = mlp.zscore_stats(Xr)
@@ -126,15 +128,17 @@ def test_loss_and_gradient_match_bf16_reference(hsd, small):
     Xn = (Xr[rows] - xm) / xs
     Yn = (Yr[rows] - ym) / ys
     widths = ssur.widths(ssur.n_outputs(d["w"].n_lambda))
-    lref, gref = mlp.loss_and_grad(flat.astype(np.float64), widths, Xn, Yn, bf16=True)
+    Wt = mlp.loss_weights(Yr[rows], d["w"].lam_cm, band_weight)      # from the raw targets
+    lref, gref = mlp.loss_and_grad(flat.astype(np.float64), widths, Xn, Yn, bf16=True, weights=Wt)
     print(f"loss {loss:.6e} ref {lref:.6e}", flush=True)
     assert abs(loss / lref - 1) < 1e-3
     # element by element: every gradient entry within 2^-8 of the sum of the
     # absolute values of its terms (an operand rounded to the other BF16
     # neighbour moves one term by at most 2^-7 of itself; FP32 accumulation of
     # K = 512 terms adds at most 512 2^-24 of that sum; an emulation with FP32
-    # accumulation stays below 1.2e-3 of it)
-    T = mlp.grad_abs_terms(flat.astype(np.float64), widths, Xn, Yn)
+    # accumulation stays below 1.2e-3 of it; the device's FP32 loss weights
+    # differ from the reference's by ~1e-6 relative)
+    T = mlp.grad_abs_terms(flat.astype(np.float64), widths, Xn, Yn, weights=Wt)
     layers_g = mlp.unpack(g.astype(np.float64), widths)
     layers_r = mlp.unpack(gref, widths)
     layers_t = mlp.unpack(T, widths)

@@ -221,3 +221,54 @@ def test_absolute_term_sums_by_brute_force():
                 lo = mlp.bf16_round(np.float32(x) - np.float32(hi))
                 acc += (abs(hi) + abs(lo)) * abs(mlp.bf16_round(W[o, k]))
             assert Yabs[s, o] == pytest.approx(acc, rel=1e-12)
+
+
+def test_band_loss_weights():
+    # weights of the band-weighted loss: every row's spectrum weights average
+    # to 1, the ratio output keeps 1, band_weight 0 is the plain loss; the
+    # band error they target is first-order in the weighted log errors; and the
+    # node weights integrate like the band integrals
+    lam = synth.wavelength_grid_cm(500)
+    q = mlp.band_node_weights(lam)
+    rng = np.random.default_rng(12)
+    f = rng.random((3, 500))
+    assert np.allclose(f @ q.T, mlp.band_integrals(f, lam), rtol=1e-13)
+    assert np.allclose(q.sum(axis=0)[1:-1] * 2, (lam[2:] - lam[:-2]), rtol=1e-13)
+    # a smooth spectrum-like target: a blackbody-ish bump per row
+    x = np.log(lam / 1e-3)
+    Y = np.concatenate([(-3.0 * (x[None, :] - rng.normal(0, 1, (4, 1))) ** 2 / 4.0) / np.log(10) - 10.0,
+                        rng.normal(0, 0.01, (4, 1))], axis=1)
+    W0 = mlp.loss_weights(Y, lam, 0.0)
+    assert np.all(W0 == 1.0)
+    W = mlp.loss_weights(Y, lam, 0.9)
+    assert np.all(W[:, -1] == 1.0) and np.all(W > 0)
+    assert np.allclose(W[:, :-1].mean(axis=1), 1.0, rtol=1e-12)
+    # first order: a small log error d changes each band by
+    # ln10 sum_k d_k j_k q_kb / J_b, the sensitivity the weights are built from
+    j = 10.0 ** Y[:, :-1]
+    J = j @ q.T
+    d = 1e-6 * rng.normal(size=j.shape)
+    J2 = (10.0 ** (Y[:, :-1] + d)) @ q.T
+    on = J >= 1e-3 * J.sum(axis=1, keepdims=True)
+    pred = math.log(10) * (d * j) @ q.T / J
+    assert np.allclose((J2 / J - 1)[on], pred[on], rtol=1e-4, atol=1e-11)
+    # rho concentrates on the bands with power: zero weight share outside them
+    rho = (W[:, :-1] - 0.1) / (0.9 * 500)
+    dead = (q[~on[0]].sum(axis=0) > 0) & (q[on[0]].sum(axis=0) == 0)
+    assert np.allclose(rho[0][dead], 0.0, atol=1e-15)
+    assert abs(rho[0].sum() - 1.0) < 1e-12
+
+
+def test_weighted_loss_gradient_against_central_differences():
+    flat, X, Y = _small_problem(seed=21)
+    Wt = np.random.default_rng(2).uniform(0.1, 3.0, Y.shape)
+    loss, g = mlp.loss_and_grad(flat, SMALL, X, Y, weights=Wt)
+    h = 1e-6
+    for k in range(0, flat.shape[0], 7):
+        e = np.zeros_like(flat)
+        e[k] = h
+        fd = (mlp.loss_and_grad(flat + e, SMALL, X, Y, weights=Wt)[0]
+              - mlp.loss_and_grad(flat - e, SMALL, X, Y, weights=Wt)[0]) / (2 * h)
+        assert abs(g[k] - fd) < 1e-8 * max(1.0, abs(fd))
+    yhat, _ = mlp.forward(flat, SMALL, X)
+    assert loss == pytest.approx(np.mean(Wt * (yhat - Y) ** 2), rel=1e-15)

@@ -300,3 +300,43 @@ def test_coarse_bin_energy_balance_across_the_batched_radii():
         _, _, d = oracle.solve_pair(u, g, lam, with_diag=True)
         out.append(d["emitted"] / d["A_rep"])
     assert abs(out[0] - 1.0) > 0.02 and abs(out[1] - 1.0) < 1e-3
+
+
+def test_table_method_twin():
+    # the oracle's table method: exact at its nodes, exact for spectra that
+    # are power laws in U between nodes, clamped outside the node range, and
+    # without emission where a node it draws on has none
+    from oracle import table as otab
+    lam = synth.wavelength_grid_cm(400)
+    g = synth.make_grain("carbonaceous", 20e-8, lam, n_bins=128)
+    u_ref = make_fields(lam, FieldRecipe(0, (1.0, 1.0), 0.0, None), 1)[0]
+    lo, hi, K = -1.0, 3.0, 5
+    y = otab.build_table(g, lam, u_ref, lo, hi, K)
+    x = otab.node_log10U(lo, hi, K)
+    for k in (0, 2, 4):
+        u = 10.0 ** x[k] * u_ref
+        got = otab.lookup(y, lo, hi, u, u_ref, g.cabs_cm2, lam)
+        _, j = oracle.solve_pair(u, g, lam)
+        m = j > 0
+        assert np.all(got[~m] == 0.0) and np.allclose(got[m], j[m], rtol=1e-12, atol=0)
+    # a synthetic table that is a power law in U: j / A = 2^c U^p
+    rng = np.random.default_rng(3)
+    c = rng.normal(-20, 3, lam.shape[0])
+    p = 0.7
+    ypl = c[None, :] + p * np.log2(10.0 ** x)[:, None]
+    for U in (0.37, 1.0, 55.5, 999.0):
+        u = U * u_ref
+        A = otab.absorbed_power(u, g.cabs_cm2, lam)
+        got = otab.lookup(ypl, lo, hi, u, u_ref, g.cabs_cm2, lam)
+        assert np.allclose(got, A * 2.0 ** c * U ** p, rtol=1e-12)
+    # clamped: a field weaker than the first node takes that node's shape
+    u = 1e-3 * u_ref
+    got = otab.lookup(ypl, lo, hi, u, u_ref, g.cabs_cm2, lam)
+    assert np.allclose(got, otab.absorbed_power(u, g.cabs_cm2, lam) * 2.0 ** c * 0.1 ** p, rtol=1e-12)
+    # a node without emission at one wavelength: none between it and the next node
+    yz = ypl.copy()
+    yz[1, 7] = -np.inf
+    got = otab.lookup(yz, lo, hi, 3.0 * u_ref, u_ref, g.cabs_cm2, lam)      # between nodes 1 and 2
+    assert got[7] == 0.0 and got[8] > 0.0
+    got = otab.lookup(yz, lo, hi, 100.0 * u_ref, u_ref, g.cabs_cm2, lam)    # exactly node 3 (w = 0)
+    assert got[7] > 0.0
