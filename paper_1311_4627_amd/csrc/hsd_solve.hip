@@ -82,31 +82,6 @@ __device__ __forceinline__ ColPar load_colpar(const ColPar* p, int i) {
 // Two values of v, one from each 16-lane row of a pair of rows (ROW16) or
 // from each 32-lane half of the wave; their combination is the same on every
 // lane of the 32-lane (64-lane) group.
-// The same value on every lane (it is wave-uniform already): moves it to a
-// scalar register, so that everything derived from it is scalar too.
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// A work item and the grain view of its slot, read with wave-uniform
-// addresses through the constant address space (scalar loads).
-typedef const __attribute__((address_space(4))) int* ConstInt;
-typedef const __attribute__((address_space(4))) GrainView* ConstView;
-
-__device__ __forceinline__ GrainView load_view(const GrainView* p, int i) {
-    ConstView c = (ConstView)p + i;
-    GrainView v;
-    v.colpar = c->colpar;
-    v.dpar = c->dpar;
-    v.gam = c->gam;
-    v.invgap = c->invgap;
-    v.jstar = c->jstar;
-    v.jrep = c->jrep;
-    v.cabs = c->cabs;
-    v.rbin = c->rbin;
-    v.nb = c->nb;
-    v.pad = 0;
-    return v;
-}
-
 template <bool ROW16>
 __device__ __forceinline__ void swap_halves(double v, double& a, double& b) {
     const unsigned lo = static_cast<unsigned>(__double2loint(v));
@@ -207,7 +182,6 @@ struct Rec {
     double part;       // this lane's share of sum_{k >= f} G(k) for the next step
     double cf;         // 2^(gamma_f + off): the column's share of the rate factor
     int nres;          // rescales so far
-    int top;           // highest row position fed by any column so far
     ColPar cnext;      // prefetched parameters of the next column
 };
 
@@ -228,7 +202,6 @@ struct StepEnv {
 // Per-step values the slot groups need.
 struct StepState {
     int pf, l, kb, ke;     // column position pf = f + s0, lane of the diagonal, grid-resident rows (positions)
-    int top;           // highest position any column so far has fed (rows above it still hold G = 0)
     double Xg;         // X_f times the column's rate factor
     int cb;            // LDS byte address of table entry ia1 of the column
     float fa;
@@ -239,16 +212,6 @@ struct StepState {
 // share of the next suffix sum.  Straight-line, so the group's LDS reads are
 // in flight together; skipped by a wave-uniform test when none of its rows is
 // grid-resident for this column.
-// The group's share of the next suffix sum (rows above the diagonal).
-template <int P, int R, int RO, int R0, int NS>
-__device__ __forceinline__ void group_part(const Rec<R>& st, const StepState& ss, int q, double& part) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        if (R0 + s == RO) part += (q > ss.l) ? st.G[R0 + s] : 0.0;
-        else part += st.G[R0 + s];
-    }
-}
-
 template <int P, int R, int KG, bool GIVEN, int RO, int R0>
 __device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const StepState& ss, double& part) {
     constexpr int NS = (R - R0) < KG ? (R - R0) : KG;
@@ -294,13 +257,11 @@ __device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const S
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) st.G[R0 + s] = fma(A[s], ss.Xg, st.G[R0 + s]);
-        group_part<P, R, RO, R0, NS>(st, ss, q, part);
-    } else if (lo_pos <= ss.top) {
-        // a group wholly above every row fed so far holds zeros only and is
-        // skipped (adding them would change no bit); the empty statement keeps
-        // this a branch rather than a speculated sum
-        asm volatile("" ::);
-        group_part<P, R, RO, R0, NS>(st, ss, q, part);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (R0 + s == RO) part += (q > ss.l) ? st.G[R0 + s] : 0.0;
+        else part += st.G[R0 + s];
     }
 }
 
@@ -330,8 +291,7 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
     const int q = e.q, nb = e.nb, s0 = e.s0;
     if (RO * P + P - 1 < s0) return;          // only positions below row 0
 #pragma unroll 1
-    for (int li = 0; li < P; ++li) {
-        const int l = uniform(li);           // the column index is wave-uniform: keep it scalar
+    for (int l = 0; l < P; ++l) {
         const int pf = RO * P + l;
         const int f = pf - s0;
         if (f < 0) continue;
@@ -365,10 +325,7 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
             st.cf *= e.rbin;
         }
         double part = 0.0;
-        // rows fed so far: the grid-resident rows of every column up to f and
-        // the continuous-heating row f+1
-        st.top = max(st.top, max(ke, pf + 1));
-        StepState ss{pf, l, kb, ke, st.top, Xg, 4 * cc.ia + e.tlo + 4, cc.fa};
+        StepState ss{pf, l, kb, ke, Xg, 4 * cc.ia + e.tlo + 4, cc.fa};
         all_groups<P, R, KG, GIVEN, RO>(st, e, ss, part, std::make_integer_sequence<int, (R - RO + KG - 1) / KG>{});
         if constexpr (!GIVEN) {
             // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1)
@@ -471,12 +428,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         bool live;
         GrainView gv{};
         if constexpr (!GIVEN) {
-            item = uniform(item);
-            const ConstInt it = (ConstInt)a.items + 2 * item;
-            gslot = uniform(it[0]);
-            rowk = uniform(it[1]) + wave * PPW + seg;
-            gv = load_view(a.views, gslot);
-            nb = uniform(gv.nb);
+            const int2 it = a.items[item];
+            gslot = it.x;
+            rowk = it.y + wave * PPW + seg;
+            gv = a.views[gslot];
+            nb = gv.nb;
             if (a.cellmap) {
                 // a list of cells per slot (the surrogate's fallback pairs)
                 live = rowk < a.seg_cnt[gslot];
@@ -603,7 +559,6 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         for (int r = 0; r < R; ++r) st.G[r] = 0.0;
         st.part = 0.0;
         st.nres = 0;
-        st.top = 0;
         st.cf = cf0;
         StepEnv env;
         env.q = q;

@@ -64,6 +64,25 @@ __device__ __forceinline__ float erfc_fast(float x) {
     return x >= 0.f ? r : 2.0f - r;
 }
 __device__ __forceinline__ float phi_cdf(float z) { return 0.5f * erfc_fast(-z * 0.70710678118654752f); }
+
+// GELU of the inference kernels, x Phi(x) with Phi from the erf approximation
+// of Abramowitz & Stegun, formula 7.1.26: with s = |x| / sqrt(2) and
+// t = 1 / (1 + p s), 1 - erf(s) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^(-s^2),
+// |error| <= 1.5e-7 in erf, so <= 7.5e-8 in Phi.  The inference kernels store
+// activations as BF16 (relative spacing 2^-8), far coarser than that; this
+// form takes 15 instructions where erfc_fast's takes 23.
+__device__ __forceinline__ float gelu_infer(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, ax, 1.0f));
+    // half the polynomial: q = (1 - erf(s)) / 2 = Phi(-|x|)
+    float p = 0.5f * 1.061405429f;
+    p = fmaf(p, t, 0.5f * -1.453152027f);
+    p = fmaf(p, t, 0.5f * 1.421413741f);
+    p = fmaf(p, t, 0.5f * -0.284496736f);
+    p = fmaf(p, t, 0.5f * 0.254829592f);
+    const float q = p * t * __builtin_amdgcn_exp2f((x * x) * -0.72134752044448170f);   // e^(-x^2/2)
+    return x * (x >= 0.f ? 1.0f - q : q);
+}
 __device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
     return phi_cdf(z) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
@@ -703,6 +722,7 @@ struct DenseArgs {
     float* rho;                 // [M] predicted energy ratio 10^y_L
     long long cell0; int off0;  // row r is selection entry (off0 + r) of cells from cell0 on
     int n_sel, n_slots; const int* sel;
+    int sel_shift;              // log2(n_sel) when n_sel is a power of two, else -1
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -735,6 +755,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
     const int slice = kk % nsplit;
     const int grp = (kk / nsplit) * 8 + static_cast<int>(blockIdx.x & 7);
     const int n0 = slice * NB;
+    const bool has_ratio = SPECTRUM && n0 <= a.L && a.L < n0 + NB;   // wave-uniform
     // LDS row 16 c + m holds output column colof(c, m) of the slice, m the
     // MFMA column (lane l % 16) of subtile c = 0..7.  Hidden layers: column
     // 8 m + c, so a lane's 8 BF16 results are one 16-byte store and the 16
@@ -805,7 +826,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int i = 0; i < 4; ++i) {
                 const int r = t * TM + wave * 16 + 4 * q + i;
                 const unsigned rc = static_cast<unsigned>(a.off0 + (r < a.M ? r : a.M - 1));
-                slot4[i] = a.sel[rc % static_cast<unsigned>(a.n_sel)];
+                slot4[i] = a.sel[a.sel_shift >= 0 ? (rc & ((1u << a.sel_shift) - 1u))
+                                                  : rc % static_cast<unsigned>(a.n_sel)];
                 A4[i] = static_cast<float>(a.Arow[r < a.M ? r : a.M - 1]);
             }
         }
@@ -845,8 +867,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                         unsigned ph[4], pl[4];
 #pragma unroll
                         for (int c = 0; c < 8; c += 2) {
-                            const float x0 = gelu(acc[g][c][i] + b8[c]);
-                            const float x1 = gelu(acc[g][c + 1][i] + b8[c + 1]);
+                            const float x0 = gelu_infer(acc[g][c][i] + b8[c]);
+                            const float x1 = gelu_infer(acc[g][c + 1][i] + b8[c + 1]);
                             ph[c / 2] = pack_bf16(x0, x1);
                             pl[c / 2] = SPLIT ? pack_bf16(x0 - __uint_as_float(ph[c / 2] << 16),
                                                           x1 - __uint_as_float(ph[c / 2] & 0xFFFF0000u))
@@ -870,8 +892,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
                 } else {
                     float part = 0.f;
                     if (r < a.M) {
+                        const unsigned rc = static_cast<unsigned>(a.off0 + static_cast<int>(r));
                         const long long cell =
-                            a.cell0 + static_cast<unsigned>(a.off0 + static_cast<int>(r)) / static_cast<unsigned>(a.n_sel);
+                            a.cell0 + (a.sel_shift >= 0 ? rc >> a.sel_shift : rc / static_cast<unsigned>(a.n_sel));
                         float* jrow = a.j + (cell * a.n_slots + slot4[i]) * a.L;
                         const float Ar = A4[i];
                         float jv[8];
@@ -885,11 +908,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 #pragma unroll
                         for (int hh = 0; hh < 2; ++hh) {
                             const int cb = n0 + 64 * hh + 4 * rl;
+                            if (has_ratio) {        // only the slice that holds column L
 #pragma unroll
-                            for (int c = 0; c < 4; ++c)
-                                if (cb + c == a.L)
-                                    a.rho[r] = __builtin_amdgcn_exp2f(
-                                        fmaf(acc[g][4 * hh + c][i], e8[4 * hh + c], f8[4 * hh + c]));
+                                for (int c = 0; c < 4; ++c)
+                                    if (cb + c == a.L)
+                                        a.rho[r] = __builtin_amdgcn_exp2f(
+                                            fmaf(acc[g][4 * hh + c][i], e8[4 * hh + c], f8[4 * hh + c]));
+                            }
                             if (cb + 4 <= a.L) {
                                 float* dst = jrow + cb;
                                 if ((reinterpret_cast<size_t>(dst) & 15) == 0) {
@@ -1303,6 +1328,9 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
     // M + n_sel < 2^31 (one chunk), so the row arithmetic fits 32 bits
     o.cell0 = row0 / n_sel; o.off0 = static_cast<int>(row0 - o.cell0 * n_sel);
     o.n_sel = n_sel; o.n_slots = n_slots; o.sel = sel;
+    o.sel_shift = -1;
+    for (int b = 0; b < 31; ++b)
+        if (n_sel == (1 << b)) o.sel_shift = b;
     return dense<256, true, true>(o, st);
 }
 
