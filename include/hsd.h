@@ -169,6 +169,8 @@ hsd_status hsd_sync(hsd_ctx* ctx);
 /* Phase timing (profiling aid).  With enable != 0, every following hsd_solve
  * records HIP events on its stream around its three phases: the fused
  * rates/recursion kernels, the emission contraction, and the diagnostics.
+ * The contraction's epilogue writes the emitted power, so the diagnostics
+ * phase holds no launch of its own and reads (close to) 0 ms.
  * hsd_phase_ms waits for the last timed solve and writes the elapsed
  * milliseconds of the three phases to ms_host[0..2].  Timing adds no
  * synchronisation to hsd_solve itself. */
@@ -289,15 +291,16 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
  * batch whose shape and buffers do not change: hsd_plan_create records every
  * launch of one hsd_solve of (n_cells, u_dev, grain_ids_host, j_dev, diag_dev)
  * - the solver classes (fields are read directly by the solver, no separate
- * ingest pass), the contractions and the diagnostics - into one HIP graph,
+ * ingest pass) and the contraction with the diagnostics - into one HIP graph,
  * with its own workspace, using the class configurations current at creation.
  * hsd_plan_launch replays it on `stream`; each replay computes exactly what
  * hsd_solve would on the buffers' contents at that time.
- *   flags  HSD_PLAN_TIMING: each phase (solver, contraction, diagnostics)
- *          is captured as a graph of its own, and hsd_plan_launch records HIP
- *          events between the three graph launches on `stream`;
- *          hsd_plan_phase_ms waits for the last launch and writes the phases'
- *          milliseconds to ms_host[0..2].
+ *   flags  HSD_PLAN_TIMING: the solver and the contraction (with the
+ *          diagnostics in its epilogue) are captured as graphs of their own,
+ *          and hsd_plan_launch records HIP events around the two graph
+ *          launches on `stream`; hsd_plan_phase_ms waits for the last launch
+ *          and writes the milliseconds of the solver, the contraction and the
+ *          diagnostics (always 0, as for hsd_phase_ms) to ms_host[0..2].
  *          HSD_PLAN_CONCURRENT: the solver classes run as parallel branches
  *          of the graph, so one class's tail overlaps the next class.  Every
  *          class must then be configured with persistent = 0, else the call

@@ -34,9 +34,16 @@ CFLAGS = [
 ]
 
 
+# Per-source options.  The contraction's matrix products keep their
+# accumulators in ordinary VGPRs: in the accumulator-register form the
+# register allocator copies the 64 loop-carried accumulators of a wave
+# between registers on every step of the bin loop.
+SOURCE_FLAGS = {"hsd_contract.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

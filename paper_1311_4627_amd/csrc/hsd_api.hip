@@ -23,7 +23,33 @@ struct Batch {
     std::vector<int2> items;
     int cls_begin[hsd::kClasses + 1] = {0, 0, 0, 0, 0};
     long long rows = 0;
+    std::vector<hsd::ContractSlot> cslots;   // the grouped contraction's slots (those with rows)
+    int c_blocks = 0;                        // its workgroups
 };
+
+// The contraction slots of a batch whose slot g holds rows[g] P~ rows at
+// offs[g] (list_off[g] >= 0: a pair list starting there in the row map).
+void contract_slots(const Ctx& c, int32_t n_grains, const int32_t* ids, const std::vector<int>& rows,
+                    const std::vector<int>& list_off, Batch& b) {
+    b.cslots.clear();
+    for (int g = 0; g < n_grains; ++g) {
+        if (rows[g] <= 0) continue;
+        const Grain& gr = c.grains[ids[g]];
+        hsd::ContractSlot sl{};
+        sl.pt_off = b.offs[g];
+        sl.Bt = gr.Bt;
+        sl.Bh = gr.Bh;
+        sl.Bl = gr.Bl;
+        sl.bscale = gr.bscale;
+        sl.nb = gr.n_bins;
+        sl.nbp = gr.nbp;
+        sl.rows = rows[g];
+        sl.gslot = g;
+        sl.rowmap_off = list_off.empty() ? -1 : list_off[g];
+        b.cslots.push_back(sl);
+    }
+    b.c_blocks = hsd::contract_blocks(b.cslots);
+}
 
 // Workspace of surrogate solves (grown on demand, kept with the context).
 struct SurWork {
@@ -79,13 +105,14 @@ struct hsd_plan {
     long long* offs = nullptr;
     int2* items = nullptr;
     unsigned* queue = nullptr;
+    hsd::ContractSlot* cslots = nullptr;
     hipStream_t cap = nullptr;
     hipStream_t side[hsd::kClasses] = {};
     hipEvent_t sev[hsd::kClasses + 1] = {};
     hipEvent_t ev[4] = {};
     bool timing = false;
     bool launched = false;
-    int n_graphs = 0;                 // 1, or 3 (one per phase) with timing
+    int n_graphs = 0;                 // 1, or 2 with timing (solver; contraction with the diagnostics)
     hipGraph_t graph[3] = {};
     hipGraphExec_t exec[3] = {};
 };
@@ -185,10 +212,13 @@ void plan_batch(const Ctx& c, int32_t n_cells, int32_t n_grains, const int32_t* 
         }
     }
     b.cls_begin[hsd::kClasses] = static_cast<int>(b.items.size());
+    contract_slots(c, n_grains, ids, std::vector<int>(n_grains, n_cells), {}, b);
 }
 
-// Batch of per-slot pair lists (counts[g] pairs of slot g, in list order).
-void plan_batch_lists(const Ctx& c, const std::vector<int>& counts, int32_t n_grains, const int32_t* ids, Batch& b) {
+// Batch of per-slot pair lists (counts[g] pairs of slot g, in list order;
+// the list of slot g starts at list_off[g] in the row map).
+void plan_batch_lists(const Ctx& c, const std::vector<int>& counts, const std::vector<int>& list_off,
+                      int32_t n_grains, const int32_t* ids, Batch& b) {
     b.views.resize(n_grains);
     b.offs.resize(n_grains);
     b.items.clear();
@@ -212,6 +242,7 @@ void plan_batch_lists(const Ctx& c, const std::vector<int>& counts, int32_t n_gr
         }
     }
     b.cls_begin[hsd::kClasses] = static_cast<int>(b.items.size());
+    contract_slots(c, n_grains, ids, counts, list_off, b);
 }
 
 // Device buffers one batch runs on (the context's workspace, or a plan's own).
@@ -222,6 +253,7 @@ struct Bufs {
     long long* offs;
     int2* items;
     unsigned* queue;     // kClasses counters
+    hsd::ContractSlot* cslots;
 };
 
 struct Events {
@@ -234,9 +266,9 @@ hipError_t record(const Events& t, int i, hipStream_t s) {
 }
 
 // Enqueue the whole batch on stream s: the solver classes (on the side
-// streams, in parallel, when `side` is given), then the per-grain
-// contractions and the diagnostics.
-constexpr int kPhaseSolve = 1, kPhaseContract = 2, kPhaseDiag = 4, kPhaseAll = 7;
+// streams, in parallel, when `side` is given), then the contraction of every
+// grain's spectra, whose epilogue also writes the emitted power.
+constexpr int kPhaseSolve = 1, kPhaseContract = 2, kPhaseAll = 3;
 
 hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells, const double* u, int32_t n_grains,
                    const int32_t* ids, float* j, float* diag, double* P64, hipStream_t s, const Events& t,
@@ -274,19 +306,13 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
     }
     HSD_HIP(ctx, record(t, 1, s));
     if (j && (phases & kPhaseContract)) {
-        for (int g = 0; g < n_grains; ++g) {
-            const Grain& gr = c.grains[ids[g]];
-            hsd::ContractLaunch cl{d.Pt + b.offs[g], d.pscale, gr.Bt, gr.bscale, j, n_cells, gr.n_bins,
-                                   c.L, c.Lp, n_grains, g};
-            cl.Bh = gr.Bh; cl.Bl = gr.Bl; cl.nbp = gr.nbp; cl.mode = c.contract;
-            HSD_HIP(ctx, hsd::launch_contract(cl, s));
-        }
+        // every grain in one launch; its epilogue also writes the emitted
+        // power (diag entry 1), so the diagnostics phase has no work left
+        hsd::ContractLaunch cl{d.cslots, static_cast<int>(b.cslots.size()), b.c_blocks, d.Pt, d.pscale, nullptr,
+                               j, diag, c.wtrap, c.L, c.Lp, n_grains, c.contract};
+        HSD_HIP(ctx, hsd::launch_contract(cl, s));
     }
     HSD_HIP(ctx, record(t, 2, s));
-    if (diag && j && (phases & kPhaseDiag)) {
-        hsd::DiagLaunch dl{c.lam, j, diag, n_cells, c.L, n_grains};
-        HSD_HIP(ctx, hsd::launch_diag(dl, s));
-    }
     HSD_HIP(ctx, record(t, 3, s));
     return HSD_OK;
 }
@@ -302,6 +328,9 @@ hsd_status run_batch(hsd_ctx* ctx, const Bufs& d, int32_t n_cells, const double*
     HSD_HIP(ctx, hipMemcpyAsync(d.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
     if (!b.items.empty())
         HSD_HIP(ctx, hipMemcpyAsync(d.items, b.items.data(), sizeof(int2) * b.items.size(),
+                                    hipMemcpyHostToDevice, s));
+    if (!b.cslots.empty())
+        HSD_HIP(ctx, hipMemcpyAsync(d.cslots, b.cslots.data(), sizeof(hsd::ContractSlot) * b.cslots.size(),
                                     hipMemcpyHostToDevice, s));
     Events t{{nullptr, nullptr, nullptr, nullptr}};
     if (c.timing)
@@ -323,7 +352,8 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
-    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue};
+    HSD_HIP(ctx, grow(c.cslots, c.cslots_cap, std::max<size_t>(b.cslots.size(), 1)));
+    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue, c.cslots};
     return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s);
 }
 
@@ -391,12 +421,26 @@ hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambd
     c.lnlam0 = ln0;
     c.dlnlam = dl;
     c.lam_host.assign(lambda_host, lambda_host + n_lambda);
+    std::vector<double> wt(n_lambda, 0.0);       // 4 pi x trapezoid weights of the grid
+    for (int i = 0; i + 1 < n_lambda; ++i) {
+        const double h = 0.5 * (lambda_host[i + 1] - lambda_host[i]);
+        wt[i] += h;
+        wt[i + 1] += h;
+    }
+    for (double& x : wt) x *= 4.0 * hsd::kPi;
+    if (hipMalloc(&c.wtrap, sizeof(double) * n_lambda) != hipSuccess ||
+        hipMemcpy(c.wtrap, wt.data(), sizeof(double) * n_lambda, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(c.wtrap);
+        delete ctx;
+        return HSD_ERR_OOM;
+    }
     if (hipMalloc(&c.lam, sizeof(double) * n_lambda) != hipSuccess ||
         hipMalloc(&c.errword, sizeof(unsigned)) != hipSuccess ||
         hipMalloc(&c.queue, sizeof(unsigned) * hsd::kClasses) != hipSuccess) {
         hipFree(c.lam);
         hipFree(c.errword);
         hipFree(c.queue);
+        hipFree(c.wtrap);
         delete ctx;
         return HSD_ERR_OOM;
     }
@@ -406,6 +450,7 @@ hsd_status hsd_create(int32_t device, const double* lambda_host, int32_t n_lambd
         hipFree(c.lam);
         hipFree(c.errword);
         hipFree(c.queue);
+        hipFree(c.wtrap);
         delete ctx;
         return HSD_ERR_HIP;
     }
@@ -420,9 +465,11 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipDeviceSynchronize();
     for (auto& g : c.grains) free_grain(g);
     hipFree(c.lam);
+    hipFree(c.wtrap);
     hipFree(c.errword);
     hipFree(c.queue);
     hipFree(c.sizew);
+    hipFree(c.cslots);
     SurWork& w = ctx->sw;
     hipFree(w.bands); hipFree(w.A); hipFree(w.emit); hipFree(w.rho); hipFree(w.fblist); hipFree(w.h0); hipFree(w.h1);
     hipFree(w.xb); hipFree(w.wcT);
@@ -529,11 +576,12 @@ hsd_status hsd_solve_noalloc(hsd_ctx* ctx, int32_t n_cells, const double* u_dev,
     Ctx& c = ctx->c;
     Batch& b = ctx->batch;
     plan_batch(c, n_cells, n_grains, grain_ids_host, b);
-    // scratch layout: views | offs | items | pscale | P~ rows, each 256-byte aligned
+    // scratch layout: views | offs | items | contraction slots | pscale | P~ rows, each 256-byte aligned
     const size_t o_views = 0;
     const size_t o_offs = o_views + align256(sizeof(hsd::GrainView) * n_grains);
     const size_t o_items = o_offs + align256(sizeof(long long) * n_grains);
-    const size_t o_pscale = o_items + align256(sizeof(int2) * std::max<size_t>(b.items.size(), 1));
+    const size_t o_cslots = o_items + align256(sizeof(int2) * std::max<size_t>(b.items.size(), 1));
+    const size_t o_pscale = o_cslots + align256(sizeof(hsd::ContractSlot) * std::max<size_t>(b.cslots.size(), 1));
     const size_t o_pt = o_pscale + align256(sizeof(float) * static_cast<size_t>(n_cells) * n_grains);
     const size_t need = o_pt + sizeof(float) * static_cast<size_t>(b.rows);
     if (need > kScratchBytes)
@@ -544,7 +592,7 @@ hsd_status hsd_solve_noalloc(hsd_ctx* ctx, int32_t n_cells, const double* u_dev,
     unsigned char* base = c.scratch;
     Bufs d{reinterpret_cast<float*>(base + o_pt), reinterpret_cast<float*>(base + o_pscale),
            reinterpret_cast<hsd::GrainView*>(base + o_views), reinterpret_cast<long long*>(base + o_offs),
-           reinterpret_cast<int2*>(base + o_items), c.queue};
+           reinterpret_cast<int2*>(base + o_items), c.queue, reinterpret_cast<hsd::ContractSlot*>(base + o_cslots)};
     return run_batch(ctx, d, n_cells, u_dev, n_grains, grain_ids_host, j_dev, diag_dev, nullptr,
                      static_cast<hipStream_t>(stream));
 }
@@ -709,6 +757,7 @@ void hsd_plan_destroy(hsd_plan* p) {
     hipFree(p->offs);
     hipFree(p->items);
     hipFree(p->queue);
+    hipFree(p->cslots);
     delete p;
 }
 
@@ -752,12 +801,16 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
     al(p->offs, static_cast<size_t>(n_grains));
     al(p->items, p->b.items.size());
     al(p->queue, static_cast<size_t>(hsd::kClasses));
+    al(p->cslots, p->b.cslots.size());
     if (e == hipSuccess)
         e = hipMemcpy(p->views, p->b.views.data(), sizeof(hsd::GrainView) * n_grains, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->offs, p->b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice);
     if (e == hipSuccess && !p->b.items.empty())
         e = hipMemcpy(p->items, p->b.items.data(), sizeof(int2) * p->b.items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->b.cslots.empty())
+        e = hipMemcpy(p->cslots, p->b.cslots.data(), sizeof(hsd::ContractSlot) * p->b.cslots.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->queue, 0, sizeof(unsigned) * hsd::kClasses);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     for (int i = 0; conc && i < hsd::kClasses && e == hipSuccess; ++i)
@@ -772,14 +825,15 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
         hsd_plan_destroy(p);
         return hip_fail(ctx, e, "hsd_plan_create");
     }
-    Bufs d{p->Pt, p->pscale, p->views, p->offs, p->items, p->queue};
+    Bufs d{p->Pt, p->pscale, p->views, p->offs, p->items, p->queue, p->cslots};
     const Events none{{nullptr, nullptr, nullptr, nullptr}};
-    // Without timing the whole batch is one graph.  With timing, each phase
-    // is a graph of its own and the launch records the phase events between
-    // them on the caller's stream.
+    // Without timing the whole batch is one graph.  With timing, the solver
+    // and the contraction (whose epilogue writes the diagnostics) are graphs
+    // of their own and the launch records the phase events between them on
+    // the caller's stream.
     static const int whole[1] = {kPhaseAll};
-    static const int split[3] = {kPhaseSolve, kPhaseContract, kPhaseDiag};
-    p->n_graphs = p->timing ? 3 : 1;
+    static const int split[2] = {kPhaseSolve, kPhaseContract};
+    p->n_graphs = p->timing ? 2 : 1;
     for (int gi = 0; gi < p->n_graphs; ++gi) {
         e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -812,11 +866,12 @@ hsd_status hsd_plan_launch(hsd_plan* p, void* stream) {
     const hipStream_t s = static_cast<hipStream_t>(stream);
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
     if (p->timing) {
-        for (int gi = 0; gi < 3; ++gi) {
+        for (int gi = 0; gi < 2; ++gi) {
             HSD_HIP(ctx, hipEventRecord(p->ev[gi], s));
             HSD_HIP(ctx, hipGraphLaunch(p->exec[gi], s));
         }
-        HSD_HIP(ctx, hipEventRecord(p->ev[3], s));
+        HSD_HIP(ctx, hipEventRecord(p->ev[2], s));
+        HSD_HIP(ctx, hipEventRecord(p->ev[3], s));     // the diagnostics run inside the contraction
     } else {
         HSD_HIP(ctx, hipGraphLaunch(p->exec[0], s));
     }
@@ -1562,15 +1617,18 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
         HSD_HIP(ctx, hsd::sur_fb_scatter(diag_dev, static_cast<long long>(n_cells) * n_grains, n_grains, w.seg_off,
                                          w.cnt, w.cellmap, w.pairs, s));
     Batch& b = ctx->batch;
-    plan_batch_lists(c, counts, n_grains, grain_ids_host, b);
+    plan_batch_lists(c, counts, off, n_grains, grain_ids_host, b);
     HSD_HIP(ctx, grow(c.Pt, c.Pt_cap, static_cast<size_t>(std::max(b.rows, 1LL))));
     HSD_HIP(ctx, grow(c.pscale, c.pscale_cap, static_cast<size_t>(n_cells) * n_grains));
     HSD_HIP(ctx, grow(c.views, c.views_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
+    HSD_HIP(ctx, grow(c.cslots, c.cslots_cap, std::max<size_t>(b.cslots.size(), 1)));
     HSD_HIP(ctx, hipMemcpyAsync(c.views, b.views.data(), sizeof(hsd::GrainView) * n_grains, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(c.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(c.items, b.items.data(), sizeof(int2) * b.items.size(), hipMemcpyHostToDevice, s));
+    HSD_HIP(ctx, hipMemcpyAsync(c.cslots, b.cslots.data(), sizeof(hsd::ContractSlot) * b.cslots.size(),
+                                hipMemcpyHostToDevice, s));
     hsd::SolveLaunch sl{};
     sl.u = u_dev;
     sl.n_cells = n_cells;
@@ -1589,16 +1647,10 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
         if (n_it == 0) continue;
         HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, c.items + b.cls_begin[ci], n_it, c.queue + ci, s));
     }
-    for (int g = 0; g < n_grains; ++g) {
-        if (counts[g] == 0) continue;
-        const Grain& gr = c.grains[grain_ids_host[g]];
-        hsd::ContractLaunch cl{c.Pt + b.offs[g], c.pscale, gr.Bt, gr.bscale, j_dev, counts[g], gr.n_bins,
-                               c.L, c.Lp, n_grains, g, w.cellmap + off[g]};
-        cl.Bh = gr.Bh; cl.Bl = gr.Bl; cl.nbp = gr.nbp; cl.mode = c.contract;
-        HSD_HIP(ctx, hsd::launch_contract(cl, s));
-    }
-    hsd::DiagLaunch dl{c.lam, j_dev, diag_dev, n_cells, c.L, n_grains, w.pairs, nfb};
-    HSD_HIP(ctx, hsd::launch_diag(dl, s));
+    // the flagged pairs' spectra and emitted power, every slot in one launch
+    hsd::ContractLaunch cl{c.cslots, static_cast<int>(b.cslots.size()), b.c_blocks, c.Pt, c.pscale, w.cellmap,
+                           j_dev, diag_dev, c.wtrap, c.L, c.Lp, n_grains, c.contract};
+    HSD_HIP(ctx, hsd::launch_contract(cl, s));
     return HSD_OK;
 }
 

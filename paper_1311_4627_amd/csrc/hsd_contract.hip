@@ -5,10 +5,14 @@
 // cells, a dense product (cells x bins) . (bins x wavelengths).  The solver
 // stores P~ = P / max P in single precision and the grain table holds
 // B~ = C_abs B_lambda(T_i) [..] / s_lambda with s_lambda its column maximum, so
-// both operands lie in [0, 1]; the product runs on the FP32 matrix cores
-// (v_mfma_f32_16x16x4_f32) with FP32 accumulation and the epilogue restores
-// j = (P~ B~) * maxP * s_lambda.
+// both operands lie in [0, 1]; the product runs on the matrix cores with FP32
+// accumulation and the epilogue restores j = (P~ B~) * maxP * s_lambda.  All
+// grains of a batch run as one launch (a workgroup per grain slot and 64-row
+// tile, each walking every wavelength tile), and the epilogue also integrates
+// the emitted power 4 pi int j dlambda of every pair it completes, so j is
+// written once and never read back.
 #include <cmath>
+#include <vector>
 
 #include "hsd_internal.h"
 
@@ -16,220 +20,309 @@ namespace hsd {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4c __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8c __attribute__((ext_vector_type(8)));
+
+// 16-byte loads through global (not flat) addressing
+typedef const __attribute__((address_space(1))) u32x4c* GlobalU32x4;
+__device__ __forceinline__ u32x4c load16(const unsigned short* p) { return *(GlobalU32x4)(p); }
 
 constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int APAD = 1, BPAD = 4;
-constexpr int BK3 = 64, LK3 = BK3 + 8;      // split-BF16 kernel: k per step, LDS row length (ushorts)
 
-// One 256-thread block computes a 64 (cells) x 64 (wavelengths) tile; each of
-// its four waves owns a 32 x 32 quarter as 2 x 2 MFMA 16x16 blocks.
-// Operand layout of v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; accumulator register i of lane l is
-// D[4 (l / 16) + i][l % 16].
-__global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
-    __shared__ float As[BM][BK + APAD];
-    __shared__ float Bs[BK][BN + BPAD];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    // Workgroup b runs on XCD b % 8; each XCD takes whole row tiles with all
-    // their wavelength tiles in a row, so a tile's P~ rows are read from HBM
-    // once and then served by that XCD's L2.
-    const int nlt = a.Lp / BN;
-    const int b = blockIdx.x;
-    const int m = b / 8;
-    const int rt = 8 * (m / nlt) + (b % 8);
-    if (rt * BM >= a.n_cells) return;          // padding tile: the whole block leaves before any barrier
-    const int row0 = rt * BM;                  // first cell of the tile
-    const int col0 = (m % nlt) * BN;           // first wavelength of the tile
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int ar = tid >> 2, ak = (tid & 3) * 4;      // A tile loader: row, k offset
-    const int bk = tid >> 4, bc = (tid & 15) * 4;     // B tile loader: k row, column offset
-    const bool arow_ok = (row0 + ar) < a.n_cells;
-    const float* Arow = a.Pt + static_cast<size_t>(row0 + ar) * a.nb;
-
-    for (int k0 = 0; k0 < a.nb; k0 += BK) {
-        float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (arow_ok) av = *reinterpret_cast<const float4*>(Arow + k0 + ak);
-        const float4 bv = *reinterpret_cast<const float4*>(a.Bt + static_cast<size_t>(k0 + bk) * a.Lp + col0 + bc);
-        As[ar][ak + 0] = av.x;
-        As[ar][ak + 1] = av.y;
-        As[ar][ak + 2] = av.z;
-        As[ar][ak + 3] = av.w;
-        *reinterpret_cast<float4*>(&Bs[bk][bc]) = bv;
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            float af[2], bf[2];
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi) af[bi] = As[wr + bi * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) bf[bj] = Bs[kk + (lane >> 4)][wc + bj * 16 + (lane & 15)];
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[bi], bf[bj], acc[bi][bj], 0, 0, 0);
-        }
-        __syncthreads();
+// The workgroup's slot: the last slot whose first workgroup is <= b (the
+// same on every lane).
+__device__ __forceinline__ int find_slot(const ContractSlot* sl, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sl[mid].tile0 <= b) lo = mid;
+        else hi = mid - 1;
     }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// The eight rows a lane's accumulators belong to (each wave a 32 x 32
+// quarter of the 64 x 64 tile as 2 x 2 blocks of 16 x 16; accumulator
+// register i of lane l lies in row 4 (l / 16) + i of its block): their j rows
+// (null beyond the slot's rows), their max P, and their pair index.
+struct RowInfo {
+    float* jrow[2][4];
+    float ps[2][4];
+    long long pair[2][4];
+};
+
+__device__ __forceinline__ RowInfo row_info(const ContractLaunch& a, const ContractSlot& sl, int row0, int wr,
+                                            int lane) {
+    RowInfo ri;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = row0 + wr + bi * 16 + 4 * (lane >> 4) + i;
-            if (row >= a.n_cells) continue;
-            const size_t cell = a.rowmap ? static_cast<size_t>(a.rowmap[row]) : static_cast<size_t>(row);
-            const float ps = a.pscale[cell * a.n_gslots + a.gslot];
-            float* jrow = a.j + (cell * a.n_gslots + a.gslot) * a.L;
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                const int col = col0 + wc + bj * 16 + (lane & 15);
-                if (col < a.L) jrow[col] = acc[bi][bj][i] * ps * a.bscale[col];
+            ri.jrow[bi][i] = nullptr;
+            ri.ps[bi][i] = 0.f;
+            ri.pair[bi][i] = -1;
+            if (row < sl.rows) {
+                const long long cell = sl.rowmap_off >= 0 ? a.rowmap[sl.rowmap_off + row] : row;
+                const long long pair = cell * a.n_gslots + sl.gslot;
+                ri.pair[bi][i] = pair;
+                ri.ps[bi][i] = a.pscale[pair];
+                ri.jrow[bi][i] = a.j + pair * a.L;
             }
         }
     }
+    return ri;
+}
+
+// Epilogue of one 64 x 64 tile: j = acc * maxP * s_lambda, and the tile's
+// share of each row's emitted power added to em in FP64 (columns in order).
+__device__ __forceinline__ void tile_epilogue(const ContractLaunch& a, const ContractSlot& sl, const RowInfo& ri,
+                                              const f32x4 (&acc)[2][2], int col0, int wc, int lane,
+                                              double (&em)[2][4]) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float* jrow = ri.jrow[bi][i];
+            if (!jrow) continue;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                const int col = col0 + wc + bj * 16 + (lane & 15);
+                if (col < a.L) {
+                    const float v = acc[bi][bj][i] * ri.ps[bi][i] * sl.bscale[col];
+                    jrow[col] = v;
+                    em[bi][i] = fma(a.wtrap[col], static_cast<double>(v), em[bi][i]);
+                }
+            }
+        }
+    }
+}
+
+// After the last tile: each row's emitted power summed over the 16 lanes that
+// hold its columns (a fixed tree), then over the two waves that share its
+// rows (through LDS), written to diag entry 1.
+__device__ __forceinline__ void finish_emitted(const ContractLaunch& a, const RowInfo& ri, double (&em)[2][4],
+                                               int wave, int lane, double (*red)[32]) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) em[bi][i] += __shfl_xor(em[bi][i], m, 16);
+    if ((lane & 15) == 0 && (wave & 1)) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave >> 1][bi * 16 + 4 * (lane >> 4) + i] = em[bi][i];
+    }
+    __syncthreads();
+    if ((lane & 15) == 0 && !(wave & 1) && a.diag) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (ri.pair[bi][i] >= 0)
+                    a.diag[ri.pair[bi][i] * 4 + 1] =
+                        static_cast<float>(em[bi][i] + red[wave >> 1][bi * 16 + 4 * (lane >> 4) + i]);
+    }
+}
+
+// FP32 products (v_mfma_f32_16x16x4_f32; lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]).  One 256-thread workgroup per (slot, 64-row tile)
+// walks every 64-wavelength tile; its P~ rows stay in the L2 of the XCD that
+// runs it between tiles.
+__global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
+    __shared__ float As[BM][BK + APAD];
+    __shared__ float Bs[BK][BN + BPAD];
+    __shared__ double red[2][32];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int b = static_cast<int>(blockIdx.x);
+    const ContractSlot sl = a.slots[find_slot(a.slots, a.n_slots, b)];
+    const int row0 = (b - sl.tile0) * BM;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int ar = tid >> 2, ak = (tid & 3) * 4;      // A tile loader: row, k offset
+    const int bk = tid >> 4, bc = (tid & 15) * 4;     // B tile loader: k row, column offset
+    const bool arow_ok = (row0 + ar) < sl.rows;
+    const float* Arow = a.Pt + sl.pt_off + static_cast<size_t>(row0 + ar) * sl.nb;
+    const RowInfo ri = row_info(a, sl, row0, wr, lane);
+    double em[2][4] = {};
+    for (int col0 = 0; col0 < a.Lp; col0 += BN) {
+        f32x4 acc[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < sl.nb; k0 += BK) {
+            float4 av = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (arow_ok) av = *reinterpret_cast<const float4*>(Arow + k0 + ak);
+            const float4 bv = *reinterpret_cast<const float4*>(sl.Bt + static_cast<size_t>(k0 + bk) * a.Lp + col0 + bc);
+            As[ar][ak + 0] = av.x;
+            As[ar][ak + 1] = av.y;
+            As[ar][ak + 2] = av.z;
+            As[ar][ak + 3] = av.w;
+            *reinterpret_cast<float4*>(&Bs[bk][bc]) = bv;
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                float af[2], bf[2];
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi) af[bi] = As[wr + bi * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) bf[bj] = Bs[kk + (lane >> 4)][wc + bj * 16 + (lane & 15)];
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[bi], bf[bj], acc[bi][bj], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        tile_epilogue(a, sl, ri, acc, col0, wc, lane, em);
+    }
+    finish_emitted(a, ri, em, wave, lane, red);
 }
 
 // The same product with each operand split into two BF16 terms, x = hi + lo
 // (hi = bf16(x), lo = bf16(x - hi)), and hi hi + hi lo + lo hi accumulated in
 // FP32 on v_mfma_f32_16x16x32_bf16 (16 times the FP32 matrix-core rate; the
 // dropped lo lo term and the split's remainders keep every product within
-// 3 2^-16 of exact).  P~ is split as it is staged in LDS; the grain's table
-// comes pre-split and transposed (Bh, Bl: [Lp][nbp], nbp a multiple of 64).  Same tiles, XCD order
-// and epilogue as k_contract; in step s lane l supplies row l % 16 of its A
-// block with k = 8 (l / 16) + 0..7 and column l % 16 of its B block with the
-// same k, so every product still sums over each k once.
-typedef unsigned int u32x4c __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8c __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ unsigned pack_hi2(float x0, float x1, unsigned& lo) {
-    const __bf16 h0 = static_cast<__bf16>(x0), h1 = static_cast<__bf16>(x1);
-    const __bf16 l0 = static_cast<__bf16>(x0 - static_cast<float>(h0));
-    const __bf16 l1 = static_cast<__bf16>(x1 - static_cast<float>(h1));
-    lo = __builtin_bit_cast(unsigned short, l0) | (static_cast<unsigned>(__builtin_bit_cast(unsigned short, l1)) << 16);
-    return __builtin_bit_cast(unsigned short, h0) | (static_cast<unsigned>(__builtin_bit_cast(unsigned short, h1)) << 16);
-}
+// 3 2^-16 of exact).  The solver writes P~ already split (each row: nb hi
+// values, then nb lo values, in the row's nb floats of space) and the grain's
+// table comes split and transposed (Bh, Bl: [Lp][nbp], zero beyond nb), so the
+// loop holds no conversions.
+//
+// A workgroup (four waves) takes 64 rows of one slot and walks the wavelengths
+// in panels of 256; each wave owns 64 x 64 of a panel as 4 x 4 blocks of
+// 16 x 16.  The P~ rows go through LDS (double buffered, one barrier per step
+// of 32 bins), since all four waves use them; each wave reads its own
+// columns of the table straight from global memory (L2: one grain's table
+// serves every row tile), each block's next step as soon as its products of
+// this step have issued.  In
+// a step, lane l supplies row (column) l % 16 of a block with bins
+// 8 (l / 16) + 0..7 of the step.
+constexpr int KS = 32, LKA = KS + 8;        // bins per step; LDS row length of each P~ plane (ushorts)
+constexpr int PW = 256;                     // wavelengths per panel
 
 __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
-    __shared__ __align__(16) unsigned short Ah[BM][LK3];
-    __shared__ __align__(16) unsigned short Al[BM][LK3];
-    __shared__ __align__(16) unsigned short Bhs[BN][LK3];
-    __shared__ __align__(16) unsigned short Bls[BN][LK3];
+    __shared__ __align__(16) unsigned short Ah[2][BM][LKA];
+    __shared__ __align__(16) unsigned short Al[2][BM][LKA];
+    __shared__ double emsh[4][BM];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int nlt = a.Lp / BN;
-    const int b = blockIdx.x;
-    const int m = b / 8;
-    const int rt = 8 * (m / nlt) + (b % 8);
-    if (rt * BM >= a.n_cells) return;          // padding tile: the whole block leaves before any barrier
-    const int row0 = rt * BM;
-    const int col0 = (m % nlt) * BN;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // loaders: thread t stages row (or column) t / 4, k = 16 (t % 4) + 0..15
-    const int lr = tid >> 2, lk = (tid & 3) * 16;
-    const bool arow_ok = (row0 + lr) < a.n_cells;
-    const float* Arow = a.Pt + static_cast<size_t>(row0 + lr) * a.nb;
-    const size_t boff = static_cast<size_t>(col0 + lr) * a.nbp + lk;
+    const int b = static_cast<int>(blockIdx.x);
+    const ContractSlot sl = a.slots[find_slot(a.slots, a.n_slots, b)];
+    const int row0 = (b - sl.tile0) * BM;
     const int rl = lane & 15, q = lane >> 4;
-    // the next step's operands are loaded into registers while this step's
-    // products run
-    float4 v[4];
-    u32x4c bh[2], bl[2];
-    auto fetch = [&](int k0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (k0 < a.nbp) {
-            if (arow_ok && k0 + lk < a.nb) {      // nb is a multiple of 16: a chunk is wholly inside or outside
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v[c] = *reinterpret_cast<const float4*>(Arow + k0 + lk + 4 * c);
-            }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                bh[c] = *reinterpret_cast<const u32x4c*>(a.Bh + boff + k0 + 8 * c);
-                bl[c] = *reinterpret_cast<const u32x4c*>(a.Bl + boff + k0 + 8 * c);
-            }
-        }
+    const int kend = (sl.nb + KS - 1) / KS * KS;
+    // P~ loader: thread t stages row t / 4, bins 8 (t % 4) + 0..7 of a step, both planes
+    // (rows past the slot's last, and bins past nb, load an in-range chunk and
+    // zero it: nb is a multiple of 16, so a chunk of 8 is wholly inside or outside)
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    const bool arow_ok = (row0 + lr) < sl.rows;
+    const unsigned short* Arow = reinterpret_cast<const unsigned short*>(
+        a.Pt + sl.pt_off + static_cast<size_t>(min(row0 + lr, sl.rows - 1)) * sl.nb);
+    auto fetch_a = [&](int k0, u32x4c& h, u32x4c& l) {
+        const bool ok = arow_ok && k0 + lk < sl.nb;
+        const int k = ok ? k0 + lk : 0;
+        h = load16(Arow + k);
+        l = load16(Arow + sl.nb + k);
+        const u32x4c z = {0u, 0u, 0u, 0u};
+        h = ok ? h : z;
+        l = ok ? l : z;
     };
-    fetch(0);
-    for (int k0 = 0; k0 < a.nbp; k0 += BK3) {
+    for (int r = tid; r < 4 * BM; r += 256) emsh[r / BM][r % BM] = 0.0;
+    for (int p0 = 0; p0 < a.Lp; p0 += PW) {
+        const int wc = p0 + wave * 64;           // the wave's first column
+        const bool wact = wc < a.Lp;             // wave-uniform
+        // the wave's table columns: column wc + 16 cb + rl, bins from 8 q
+        const size_t bo = static_cast<size_t>(min(wc, a.Lp - 64) + rl) * sl.nbp + 8 * q;
+        auto fetch_b = [&](int k0, int cb, u32x4c& h, u32x4c& l) {
+            h = load16(sl.Bh + bo + static_cast<size_t>(16 * cb) * sl.nbp + k0);
+            l = load16(sl.Bl + bo + static_cast<size_t>(16 * cb) * sl.nbp + k0);
+        };
+        f32x4 acc[4][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            unsigned l0, l1, l2, l3;
-            const unsigned h0 = pack_hi2(v[2 * c].x, v[2 * c].y, l0), h1 = pack_hi2(v[2 * c].z, v[2 * c].w, l1);
-            const unsigned h2 = pack_hi2(v[2 * c + 1].x, v[2 * c + 1].y, l2);
-            const unsigned h3 = pack_hi2(v[2 * c + 1].z, v[2 * c + 1].w, l3);
-            const u32x4c ahv = {h0, h1, h2, h3}, alv = {l0, l1, l2, l3};
-            *reinterpret_cast<u32x4c*>(&Ah[lr][lk + 8 * c]) = ahv;
-            *reinterpret_cast<u32x4c*>(&Al[lr][lk + 8 * c]) = alv;
-            *reinterpret_cast<u32x4c*>(&Bhs[lr][lk + 8 * c]) = bh[c];
-            *reinterpret_cast<u32x4c*>(&Bls[lr][lk + 8 * c]) = bl[c];
-        }
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[bi][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        u32x4c ah, al, bh[4], bl[4];
+        fetch_a(0, ah, al);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) fetch_b(0, cb, bh[cb], bl[cb]);
+        __syncthreads();                         // the previous panel's readers are done with buffer 0
+        *reinterpret_cast<u32x4c*>(&Ah[0][lr][lk]) = ah;
+        *reinterpret_cast<u32x4c*>(&Al[0][lr][lk]) = al;
         __syncthreads();
-        fetch(k0 + BK3);
+        // Straight-line steps: a wave past the last column computes on an
+        // in-range column and writes nothing; the last step fetches its own
+        // operands again instead of the (absent) next ones.
+        for (int k0 = 0, cur = 0; k0 < kend; k0 += KS, cur ^= 1) {
+            const int kn = min(k0 + KS, kend - KS);
+            fetch_a(kn, ah, al);
+            bf16x8c fh[4], fl[4];
 #pragma unroll
-        for (int ks = 0; ks < BK3; ks += 32) {
-            bf16x8c ah[2], al[2], bhf[2], blf[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                ah[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[wr + 16 * t + rl][ks + 8 * q]));
-                al[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[wr + 16 * t + rl][ks + 8 * q]));
-                bhf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bhs[wc + 16 * t + rl][ks + 8 * q]));
-                blf[t] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Bls[wc + 16 * t + rl][ks + 8 * q]));
+            for (int bi = 0; bi < 4; ++bi) {
+                fh[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[cur][16 * bi + rl][8 * q]));
+                fl[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[cur][16 * bi + rl][8 * q]));
             }
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int cb = 0; cb < 4; ++cb) {
+                const bf16x8c gh = __builtin_bit_cast(bf16x8c, bh[cb]), gl = __builtin_bit_cast(bf16x8c, bl[cb]);
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[bi], blf[bj], acc[bi][bj], 0, 0, 0);
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[bi], bhf[bj], acc[bi][bj], 0, 0, 0);
+                for (int bi = 0; bi < 4; ++bi) {
+                    acc[bi][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[bi], gh, acc[bi][cb], 0, 0, 0);
+                    acc[bi][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fh[bi], gl, acc[bi][cb], 0, 0, 0);
+                    acc[bi][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fl[bi], gh, acc[bi][cb], 0, 0, 0);
                 }
+                fetch_b(kn, cb, bh[cb], bl[cb]);     // in flight during the other blocks' products
+            }
+            // buffer cur ^ 1 was last read before the previous step's barrier
+            *reinterpret_cast<u32x4c*>(&Ah[cur ^ 1][lr][lk]) = ah;
+            *reinterpret_cast<u32x4c*>(&Al[cur ^ 1][lr][lk]) = al;
+            __syncthreads();
         }
-        __syncthreads();
-    }
+        if (!wact) continue;
+        // epilogue: j = acc * maxP * s_lambda; each row's share of the emitted
+        // power over the wave's 64 columns (lanes of one quarter hold one
+        // row's columns: a fixed tree over them), added to the row's running
+        // sum for this wave
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
+        for (int bi = 0; bi < 4; ++bi) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = row0 + wr + bi * 16 + 4 * (lane >> 4) + i;
-            if (row >= a.n_cells) continue;
-            const size_t cell = a.rowmap ? static_cast<size_t>(a.rowmap[row]) : static_cast<size_t>(row);
-            const float ps = a.pscale[cell * a.n_gslots + a.gslot];
-            float* jrow = a.j + (cell * a.n_gslots + a.gslot) * a.L;
-            for (int bj = 0; bj < 2; ++bj) {
-                const int col = col0 + wc + bj * 16 + (lane & 15);
-                if (col < a.L) jrow[col] = acc[bi][bj][i] * ps * a.bscale[col];
+            for (int i = 0; i < 4; ++i) {
+                const int rt = 16 * bi + 4 * q + i;          // row in the tile
+                const int row = row0 + rt;
+                double em = 0.0;
+                if (row < sl.rows) {
+                    const long long cell = sl.rowmap_off >= 0 ? a.rowmap[sl.rowmap_off + row] : row;
+                    const long long pair = cell * a.n_gslots + sl.gslot;
+                    const float ps = a.pscale[pair];
+                    float* jrow = a.j + pair * a.L;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        const int col = wc + 16 * cb + rl;
+                        if (col < a.L) {
+                            const float v = acc[bi][cb][i] * ps * sl.bscale[col];
+                            jrow[col] = v;
+                            em = fma(a.wtrap[col], static_cast<double>(v), em);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) em += __shfl_xor(em, m, 16);
+                if (rl == 0) emsh[wave][rt] += em;
             }
         }
     }
-}
-
-// Emitted power of each pair, 4 pi int j dlambda (trapezoid, FP64 sum), one
-// 16-lane segment per pair; the other diagnostics come from the solver.
-__global__ void __launch_bounds__(256) k_diag(DiagLaunch a) {
-    const int lane = threadIdx.x & 15;
-    const size_t k = static_cast<size_t>(blockIdx.x) * 16 + (threadIdx.x >> 4);
-    const size_t n_k = a.pairs ? static_cast<size_t>(a.n_list) : static_cast<size_t>(a.n_cells) * a.n_gslots;
-    const bool valid = k < n_k;
-    const size_t pair = !valid ? 0 : (a.pairs ? static_cast<size_t>(a.pairs[k]) : k);
-    const float* jr = a.j + (valid ? pair : 0) * a.L;
-    double em = 0.0;
-    for (int j = lane; j + 1 < a.L; j += 16)
-        em += 0.5 * (static_cast<double>(jr[j]) + jr[j + 1]) * (a.lam[j + 1] - a.lam[j]);
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) em += __shfl_xor(em, m, 16);
-    if (lane == 0 && valid) a.diag[pair * 4 + 1] = static_cast<float>(4.0 * kPi * em);
+    __syncthreads();
+    if (tid < BM && a.diag && row0 + tid < sl.rows) {
+        const int row = row0 + tid;
+        const long long cell = sl.rowmap_off >= 0 ? a.rowmap[sl.rowmap_off + row] : row;
+        const long long pair = cell * a.n_gslots + sl.gslot;
+        a.diag[pair * 4 + 1] = static_cast<float>((emsh[0][tid] + emsh[1][tid]) + (emsh[2][tid] + emsh[3][tid]));
+    }
 }
 
 // Size-distribution convolution (Sec. 2.3, eq:convolution on the size grid):
@@ -249,22 +342,20 @@ __global__ void __launch_bounds__(256) k_sizedist(const float* j, const double* 
 
 }  // namespace
 
-hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
-    if (a.n_cells <= 0) return hipSuccess;
-    const int nrt8 = ((a.n_cells + BM - 1) / BM + 7) / 8 * 8;
-    if (a.mode == 1) {
-        if (!a.Bh || !a.Bl || a.nbp < a.nb || a.nbp % BK3 != 0 || a.nb % 16 != 0) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_contract3, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
-        return hipGetLastError();
+int contract_blocks(std::vector<ContractSlot>& slots) {
+    int t = 0;
+    for (ContractSlot& s : slots) {
+        s.tile0 = t;
+        t += (s.rows + BM - 1) / BM;
     }
-    hipLaunchKernelGGL(k_contract, dim3(nrt8 * (a.Lp / BN)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return t;
 }
 
-hipError_t launch_diag(const DiagLaunch& a, hipStream_t s) {
-    const size_t n_pairs = a.pairs ? static_cast<size_t>(a.n_list) : static_cast<size_t>(a.n_cells) * a.n_gslots;
-    if (n_pairs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag, dim3(static_cast<unsigned>((n_pairs + 15) / 16)), dim3(256), 0, s, a);
+hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
+    if (a.n_blocks <= 0 || a.n_slots <= 0) return hipSuccess;
+    if (a.Lp % BN != 0) return hipErrorInvalidValue;
+    if (a.mode == 1) hipLaunchKernelGGL(k_contract3, dim3(a.n_blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_contract, dim3(a.n_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -90,12 +90,25 @@ struct ClassCfg {
     int persistent = 0;  // 1 = persistent grid fed by an atomic item counter
 };
 
+// One grain slot of a batch for the grouped emission contraction.
+struct ContractSlot {
+    long long pt_off;         // first element of the slot's P~ rows [rows][nb] in the workspace
+    const float* Bt;          // [nb][Lp]           (FP32 mode)
+    const unsigned short* Bh; // [Lp][nbp] hi / lo  (split-BF16 mode)
+    const unsigned short* Bl;
+    const float* bscale;      // [Lp]
+    int nb, nbp, rows, gslot;
+    int tile0;                // first workgroup of the slot in the grid
+    int rowmap_off;           // cell of row r: rowmap[rowmap_off + r]; -1: row r is cell r
+};
+
 struct Ctx {
     int device = 0;
     ClassCfg cfg[kClasses];
     int L = 0, Lp = 0;
     double lnlam0 = 0, dlnlam = 0;
     double* lam = nullptr;        // [L] device copy of the grid
+    double* wtrap = nullptr;      // [L] 4 pi x trapezoid weights of the grid
     std::vector<double> lam_host;
     std::vector<Grain> grains;
     std::string err;
@@ -106,6 +119,7 @@ struct Ctx {
     GrainView* views = nullptr;   size_t views_cap = 0;
     long long* offs = nullptr;    size_t offs_cap = 0;
     int2* items = nullptr;        size_t items_cap = 0;
+    ContractSlot* cslots = nullptr; size_t cslots_cap = 0;
     unsigned* queue = nullptr;    // [kClasses] item counters of persistent launches
     double* sizew = nullptr;      size_t sizew_cap = 0;   // size-distribution weights
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
@@ -158,30 +172,24 @@ int solve_capacity(const Ctx& c, int cls);
 hipError_t launch_from_rates(const Ctx& c, int nb, int n_pairs, const double* A, const double* cool,
                              double* P, hipStream_t s);
 
+// Every slot of a batch in one launch: one workgroup per (slot, 64-row tile),
+// looping over the wavelength tiles; with diag, the epilogue also sums the
+// pair's emitted power 4 pi int j dlambda (FP64) and writes diag entry 1.
 struct ContractLaunch {
-    const float* Pt;          // rows of the slot: [n_cells][nb]
-    const float* pscale;      // [n_cells * n_gslots] (stride n_gslots)
-    const float* Bt;          // [nb][Lp]
-    const float* bscale;      // [Lp]
-    float* j;                 // [n_cells][n_gslots][L]
-    int n_cells, nb, L, Lp, n_gslots, gslot;   // n_cells: rows of the slot's P~ block
-    const int* rowmap = nullptr;              // optional: cell of each row (pair lists)
-    const unsigned short* Bh = nullptr;       // split-BF16 mode: the grain's hi / lo tables [Lp][nbp]
-    const unsigned short* Bl = nullptr;
-    int nbp = 0;
-    int mode = 0;                             // 0 FP32 products, 1 split BF16
+    const ContractSlot* slots;   // device [n_slots]
+    int n_slots, n_blocks;
+    const float* Pt;             // workspace base
+    const float* pscale;         // [cells * n_gslots]
+    const int* rowmap;           // pair lists, or null
+    float* j;                    // [cells][n_gslots][L]
+    float* diag;                 // [cells][n_gslots][4] or null
+    const double* wtrap;         // [L] 4 pi x trapezoid weight of each grid wavelength
+    int L, Lp, n_gslots, mode;   // mode 0 FP32 products, 1 split BF16
 };
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
-
-struct DiagLaunch {
-    const double* lam;
-    const float* j;           // [n_cells][n_gslots][L]
-    float* diag;              // [n_cells][n_gslots][4]; writes entry 1
-    int n_cells, L, n_gslots;
-    const long long* pairs = nullptr;   // optional: only these pair indices (cell * n_gslots + slot)
-    long long n_list = 0;
-};
-hipError_t launch_diag(const DiagLaunch& a, hipStream_t s);
+// Host side: the slot descriptors of a batch (rows[g] P~ rows of slot g at
+// offs[g]; lists: rowmap_off[g] or -1) and the grid size.
+int contract_blocks(std::vector<ContractSlot>& slots);
 // The table method (hsd_table.hip).
 hipError_t launch_node_fields(const double* u_ref, double lo, double step, int n_nodes, int L, double* u_out,
                               hipStream_t s);

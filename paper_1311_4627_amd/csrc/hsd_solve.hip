@@ -146,19 +146,6 @@ __device__ __forceinline__ float seg_maxf(float v) {
     return v;
 }
 
-// Sum of v over the lanes q' > q of the segment (no subtraction).
-template <int P>
-__device__ __forceinline__ double seg_suffix_exclusive(double v, int q) {
-    double s = __shfl_down(v, 1, P);
-    if (q + 1 >= P) s = 0.0;
-#pragma unroll
-    for (int m = 1; m < P; m <<= 1) {
-        const double o = __shfl_down(s, m, P);
-        if (q + m < P) s += o;
-    }
-    return s;
-}
-
 __device__ __forceinline__ double clean_field(double u, bool& bad) {
     if (!(u >= 0.0) || !(u < INFINITY)) {
         bad = true;
@@ -375,6 +362,7 @@ struct KArgs {
     const GrainView* views;
     const long long* offs;
     float* Pt;
+    int psplit;                // P~ rows as two BF16 planes (hi, then lo) instead of FP32
     float* pscale;
     float* diag;
     double* P64;
@@ -476,35 +464,36 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             }
 
             // Pass 1: absorbed-power suffix integrals Cum_j = int_{lambda_j} c u C_abs dlambda
-            // (trapezoid), FP64, chunked over the segment's lanes; kept normalised by
-            // the total in FP32.
+            // (trapezoid), FP64, kept normalised by the total in FP32.  The
+            // segment reads P consecutive wavelengths at a time (coalesced), from
+            // the top of the grid down; interval j's trapezoid t_j takes rho_(j+1)
+            // from the next lane (the last lane: from the block above).  A first
+            // sweep sums the t_j for the total; the second adds, per block, the
+            // suffix sums across the lanes to the sum of the blocks above.
             const double* uc = a.u + static_cast<size_t>(cellc) * L;
-            const int cs = (L + P - 1) / P;
-            const int j0 = q * cs;
-            const int j1 = min(j0 + cs, L);
-            double csum = 0.0;
-            if (j0 < j1) {
-                double rho_n = kLight * clean_field(uc[j0], bad) * gv.cabs[j0];
-                for (int j = j0; j < j1; ++j) {
-                    const double rho = rho_n;
-                    if (j + 1 < L) {
-                        rho_n = kLight * clean_field(uc[j + 1], bad) * gv.cabs[j + 1];
-                        csum += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
-                    }
-                }
-            }
-            const double carry = seg_suffix_exclusive<P>(csum, q);
+            const int jtop = (L - 1) / P * P;
+            auto interval = [&](int j, double& rho_up) {
+                const double rho = j < L ? kLight * clean_field(uc[j], bad) * gv.cabs[j] : 0.0;
+                double rn = __shfl_down(rho, 1, P);
+                if (q == P - 1) rn = rho_up;
+                rho_up = __shfl(rho, 0, P);
+                return (j + 1 < L) ? 0.5 * (rho + rn) * (a.lam[j + 1] - a.lam[j]) : 0.0;
+            };
+            double csum = 0.0, rho_up = 0.0;
+            for (int j0 = jtop; j0 >= 0; j0 -= P) csum += interval(j0 + q, rho_up);
             total = seg_sum<P>(csum);
             const double inv_total = total > 0.0 ? 1.0 / total : 0.0;
-            if (j0 < j1) {
-                double c = carry;
-                double rho_n = (j1 < L) ? kLight * clean_field(uc[j1], bad) * gv.cabs[j1] : 0.0;
-                for (int j = j1 - 1; j >= j0; --j) {
-                    const double rho = kLight * clean_field(uc[j], bad) * gv.cabs[j];
-                    if (j + 1 < L) c += 0.5 * (rho + rho_n) * (a.lam[j + 1] - a.lam[j]);
-                    rho_n = rho;
-                    cum[j] = static_cast<float>(c * inv_total);
+            double above = 0.0;
+            rho_up = 0.0;
+            for (int j0 = jtop; j0 >= 0; j0 -= P) {
+                double sfx = interval(j0 + q, rho_up);
+#pragma unroll
+                for (int m = 1; m < P; m <<= 1) {
+                    const double o = __shfl_down(sfx, m, P);
+                    if (q + m < P) sfx += o;
                 }
+                if (j0 + q < L) cum[j0 + q] = static_cast<float>((above + sfx) * inv_total);
+                above += __shfl(sfx, 0, P);
             }
             __syncthreads();
             if constexpr (!LDSCUM) {
@@ -620,10 +609,27 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
                 if (a.Pt) {
                     float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(rowk) * nb;
                     const double inv = 1.0 / mxx;
+                    if (a.psplit) {
+                        // the row's nb floats of space hold P~ = hi + lo as BF16
+                        // planes, hi = bf16(P~) at [0, nb), lo = bf16(P~ - hi) at [nb, 2 nb)
+                        unsigned short* hrow = reinterpret_cast<unsigned short*>(prow);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int k = r * P + q - s0;
-                        if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
+                        for (int r = 0; r < R; ++r) {
+                            const int k = r * P + q - s0;
+                            if (k >= 0) {
+                                const float v = static_cast<float>(G[r] * inv);
+                                const __bf16 h = static_cast<__bf16>(v);
+                                const __bf16 l = static_cast<__bf16>(v - static_cast<float>(h));
+                                hrow[k] = __builtin_bit_cast(unsigned short, h);
+                                hrow[nb + k] = __builtin_bit_cast(unsigned short, l);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int k = r * P + q - s0;
+                            if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
+                        }
                     }
                 }
                 const size_t pair = static_cast<size_t>(cell) * a.n_gslots + gslot;
@@ -783,6 +789,7 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int cls, const int2
     ka.views = sl.views;
     ka.offs = sl.offs;
     ka.Pt = sl.Pt;
+    ka.psplit = c.contract == 1;
     ka.pscale = sl.pscale;
     ka.diag = sl.diag;
     ka.P64 = sl.P64;
