@@ -571,6 +571,11 @@ def bench_plain(args):
     if args.eager:
         tuned = autotune.tune(ctx, ud, ids, cache_path=TUNE_CACHE, force=args.retune)
         launched = tuned["cfg"]
+        if args.no_persistent:
+            # the kernels and work order of the concurrent plan, launched one class after another
+            launched = [dict(c, persistent=0) for c in launched]
+            for cls, c in enumerate(launched):
+                ctx.hsd_set_class_cfg(cls, **c)
         for _ in range(args.warmup):
             ctx.hsd_solve(ud, ids, j, diag, stream)
         ctx.hsd_sync()
@@ -688,6 +693,8 @@ def main():
     ap.add_argument("--weights", default=WEIGHTS_DIR, help="c5: directory of the trained networks")
     ap.add_argument("--eager", action="store_true", help="c2/c3: time hsd_solve calls instead of plan replays")
     ap.add_argument("--retune", action="store_true", help="c2/c3 eager: time the launch configurations again")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="c2/c3 eager: every class as an ordinary grid (the plan's kernels, for counter runs)")
     ap.add_argument("--contract", choices=("bf16x3", "fp32"), default="bf16x3",
                     help="c2/c3: emission contraction: three BF16 products of split operands, or FP32")
     ap.add_argument("--train-steps", type=int, default=60000, help="c4: training steps per network")

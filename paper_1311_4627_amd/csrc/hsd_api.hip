@@ -1355,7 +1355,7 @@ hsd_status sur_select(hsd_ctx* ctx, const std::vector<int>& slots, const int32_t
     return HSD_OK;
 }
 
-constexpr long long kSurChunk = 262144;   // pair rows per inference chunk
+constexpr long long kSurChunk = 1048576;  // pair rows per inference chunk (fewer, longer launches; 1.7 GB of activations)
 
 // Surrogate spectra of every (cell, slot) pair of `slots` into j, with diag
 // entries and the energy-balance flags (bit 4, check HSD_CHECK_*) counted in
