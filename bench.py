@@ -17,7 +17,11 @@ step is one solve of that whole batch:
   paper_1311_4627_amd/weights/, trained by `bench.py --workload c4_train
   --save ...`), the in-kernel energy check at 1% and the plain solve on every
   flagged pair, reported as solves/s, speed-up over the plain path and
-  fallback fraction.
+  fallback fraction;
+* table method (the cheap alternative the surrogate is measured against):
+  plain spectra of one reference field shape at 57 log-spaced field
+  strengths per grain, interpolated in log U and scaled by each pair's
+  absorbed power, timed over the whole batch, with its band error.
 
 Fields are resident in HBM before the timed region; spectra stay on the
 device.  W untimed warm-up steps, then K timed steps of each path.  Prints
@@ -226,6 +230,28 @@ def radius_groups(grains, comp: str, n_groups: int):
     return [sel[q * G // n_groups:(q + 1) * G // n_groups] for q in range(n_groups)]
 
 
+# the table method: nodes every 1/8 dex of U over the range of the generators' fields (U 0.1 .. 1e5,
+# with a jitter of up to 30% per component), the reference shape being the unjittered field at U = 1
+TABLE_LOG10U = (-1.5, 5.5)
+TABLE_NODES = 57
+
+
+def table_method(torch, ctx, w, ids, u, j, stream=None):
+    """Table-method spectra of every (cell, grain) pair of u x ids into j; returns
+    the seconds the table build took."""
+    from synth.fields import FieldRecipe
+    u_ref = torch.tensor(make_fields(w.lam_cm, FieldRecipe(0, (1.0, 1.0), 0.0, None), 1)[0], device="cuda:0")
+    lo, hi = TABLE_LOG10U
+    table = torch.empty((len(ids), TABLE_NODES, w.n_lambda), dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.hsd_table_build(ids, u_ref, lo, hi, table, stream)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    ctx.hsd_table_eval(u, ids, u_ref, lo, hi, table, j, stream)
+    return build_s, (lambda: ctx.hsd_table_eval(u, ids, u_ref, lo, hi, table, j, stream))
+
+
 def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log, n_groups=4, band_weight=0.0, save_dir=None):
     """Per composition and range of radii: plain-solve the training cells for
     those radii, build inputs and targets, fit the statistics and train one
@@ -279,19 +305,14 @@ def train_surrogates(torch, hsd, ctx, w4, ids, steps, batch, lr, log, n_groups=4
             drn = dr.cpu().numpy().reshape(-1, 4).astype(np.float64)
             dpn = dp.cpu().numpy().reshape(-1, 4).astype(np.float64)
             rerr = np.abs((dpn[:, 2] / dpn[:, 0]) / (drn[:, 1] / drn[:, 0]) - 1)
-            # the cheap method the surrogate replaces: a table of training spectra
-            # indexed by the field's total energy alone (nearest training cell, same
-            # grain), scaled by the pair's own absorbed power
-            Xh = torch.empty((nh * G, 33), dtype=torch.float32, device="cuda:0")
-            Ah = torch.empty((nh * G,), dtype=torch.float64, device="cuda:0")
-            ctx.hsd_sur_features(uh, sel, Xh, Ah)
-            etot_t = torch.log10((10.0 ** X.view(w4.n_cells, G, 33)[:, 0, :32].double()).sum(dim=1))
-            etot_h = torch.log10((10.0 ** Xh.view(nh, G, 33)[:, 0, :32].double()).sum(dim=1))
-            nn = torch.argmin((etot_h[:, None] - etot_t[None, :]).abs(), dim=1)
-            rows = (nn[:, None] * G + torch.arange(G, device="cuda:0")[None, :]).reshape(-1)
-            jt = (10.0 ** Y.index_select(0, rows)[:, :w4.n_lambda].double()) * Ah[:, None]
-            terr = _band_error(jt.cpu().numpy(), jr.cpu().numpy().reshape(-1, w4.n_lambda), w4.lam_cm)
-            del X, Y, A, Xh, Ah, jt, jr, jp, dr, dp
+            # the cheap method the surrogate replaces: the table method (hsd_table_*),
+            # plain spectra of the reference field shape at log-spaced U, interpolated
+            # in log U and scaled by the pair's own absorbed power
+            jt = torch.empty_like(jr)
+            table_method(torch, ctx, w4, sel, uh, jt)
+            terr = _band_error(jt.cpu().numpy().reshape(-1, w4.n_lambda), jr.cpu().numpy().reshape(-1, w4.n_lambda),
+                               w4.lam_cm)
+            del X, Y, A, jt, jr, jp, dr, dp
             r0, r1 = part[0][1].radius_cm * 1e8, part[-1][1].radius_cm * 1e8
             groups.append({"radii_A": [round(r0, 1), round(r1, 1)], "train_pairs": n,
                            "heldout_band_err": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
@@ -466,6 +487,12 @@ def bench_c5(args):
                                              "within_tol": bool(e_or.max() <= BAND_TOL)}}
         log(f"against the oracle ({len(sub)} pairs): plain j max rel err {worst:.2e}; surrogate band error "
             f"max {e_or.max():.4f}")
+    # the table method over the whole batch (into the surrogate's buffer), its band error on the sample
+    build_s, tab_eval = table_method(torch, ctx, w, ids, ud, jsu, stream)
+    t_tab, _ = timed_steps(torch, tab_eval, 1, args.steps)
+    e_tab = _band_error(jsu.view(n_pairs, L).index_select(0, idx).cpu().numpy(), jr_gpu, w.lam_cm)
+    log(f"table method: {t_tab * 1e3:.1f} ms per step, sample band error median {np.median(e_tab):.4f} "
+        f"max {e_tab.max():.4f}")
     # the networks alone over one composition (HBM-write bound), HIP events on the stream
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     carb = [g for g in range(G) if w.grains[g].composition == "carbonaceous"]
@@ -511,6 +538,11 @@ def bench_c5(args):
                                        "p99": float(np.quantile(err, 0.99)), "median": float(np.median(err)),
                                        "max_surrogate_pairs": float(err[by_sur].max()) if by_sur.any() else 0.0},
         "oracle_error": oracle_err,
+        "table_method": {"nodes": TABLE_NODES, "log10U": list(TABLE_LOG10U), "build_s": build_s,
+                         "solves_per_s": n_pairs / t_tab, "ms_per_step": t_tab * 1e3,
+                         "sample_band_error_vs_plain": {"max": float(e_tab.max()),
+                                                        "p99": float(np.quantile(e_tab, 0.99)),
+                                                        "median": float(np.median(e_tab))}},
         "surrogate_roofline": {"bound": "hbm", "kernel": "network inference, one composition", "unit": "GB/s",
                                "achieved": out_bytes / t_net / 1e9, "peak": HBM_PEAK / 1e9,
                                "frac": out_bytes / t_net / HBM_PEAK, "kernel_ms": t_net * 1e3,

@@ -839,16 +839,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
             for (int c = 0; c < 8; ++c) acc[g][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int st = 0; st < S; ++st) {
+            // two subtiles at a time, so that the products into one accumulator
+            // are not issued back to back
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const bf16x8 b = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const u32x4*>(&Ws[16 * c + rl][(K / 4) * q + 8 * st]));
+            for (int c = 0; c < 8; c += 2) {
+                bf16x8 b[2];
 #pragma unroll
-                for (int g = 0; g < G; ++g)
+                for (int e = 0; e < 2; ++e)
+                    b[e] = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4*>(&Ws[16 * (c + e) + rl][(K / 4) * q + 8 * st]));
 #pragma unroll
-                    for (int h = 0; h < NT; ++h)
-                        acc[g][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[g][h][st]),
-                                                                            b, acc[g][c], 0, 0, 0);
+                for (int h = 0; h < NT; ++h)
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            acc[g][c + e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, cur[g][h][st]), b[e], acc[g][c + e], 0, 0, 0);
             }
             // keep each step's weight fragments within the step (bounds register use)
             __builtin_amdgcn_sched_barrier(0);
