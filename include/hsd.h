@@ -63,7 +63,10 @@ typedef struct hsd_ctx hsd_ctx;
 typedef struct hsd_plan hsd_plan;
 
 /* One grain size of one composition (the paper's GrainModel row plus the
- * engine's enthalpy grid, appendix on the library interface). */
+ * engine's enthalpy grid, appendix on the library interface).  There is no
+ * flags field: the one switch such a row could carry, the continuous
+ * (intrabin) heating term, is always on, and no other per-grain option
+ * exists. */
 typedef struct {
     double radius_cm;        /* grain radius: an input of the surrogate (the plain solve
                                 takes the size from C_abs); > 0 for surrogate use */
