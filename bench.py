@@ -393,14 +393,15 @@ def timed_steps(torch, fn, warmup: int, steps: int):
     return (time.perf_counter() - t0) / max(steps, 1), out
 
 
-def plain_plan(hsd, autotune, ctx, ud, ids, j, d):
+def plain_plan(hsd, autotune, ctx, ud, ids, j, d, retune=False):
     """The autotuned configuration (cached), every class as an ordinary grid,
     as one plan with phase timing and concurrent classes."""
-    tuned = autotune.tune(ctx, ud, ids, cache_path=TUNE_CACHE)
+    tuned = autotune.tune(ctx, ud, ids, cache_path=TUNE_CACHE, force=retune)
     launched = [dict(c, persistent=0) for c in tuned["cfg"]]
     for cls, c in enumerate(launched):
         ctx.hsd_set_class_cfg(cls, **c)
     plan = ctx.hsd_plan_create(ud, ids, j, d, flags=hsd.PLAN_TIMING | hsd.PLAN_CONCURRENT)
+    launched = {"classes": launched, "contract_waves": ctx.hsd_get_contract_waves()}
     return plan, launched, tuned["cached"]
 
 
@@ -449,7 +450,7 @@ def bench_c5(args):
     stream = torch.cuda.current_stream()
     jpl = torch.empty((n_cells, G, L), dtype=torch.float32, device="cuda:0")
     dpl = torch.empty((n_cells, G, 4), dtype=torch.float32, device="cuda:0")
-    plan, launched, cached = plain_plan(hsd, autotune, ctx, ud, ids, jpl, dpl)
+    plan, launched, cached = plain_plan(hsd, autotune, ctx, ud, ids, jpl, dpl, args.retune)
     log(f"launch configuration {launched} (cached: {cached})")
     t_plain, phase = timed_plan(torch, plan, stream, args.warmup, args.steps)
     log(f"plain: {t_plain * 1e3:.1f} ms per step (solve {phase[0]:.1f}, contraction {phase[1]:.1f}, "
@@ -602,12 +603,13 @@ def bench_plain(args):
     log(f"setup {setup_s:.2f} s for {len(ids)} grains; {w.n_pairs} pairs per step")
     if args.eager:
         tuned = autotune.tune(ctx, ud, ids, cache_path=TUNE_CACHE, force=args.retune)
-        launched = tuned["cfg"]
+        classes = tuned["cfg"]
         if args.no_persistent:
             # the kernels and work order of the concurrent plan, launched one class after another
-            launched = [dict(c, persistent=0) for c in launched]
-            for cls, c in enumerate(launched):
+            classes = [dict(c, persistent=0) for c in classes]
+            for cls, c in enumerate(classes):
                 ctx.hsd_set_class_cfg(cls, **c)
+        launched = {"classes": classes, "contract_waves": ctx.hsd_get_contract_waves()}
         for _ in range(args.warmup):
             ctx.hsd_solve(ud, ids, j, diag, stream)
         ctx.hsd_sync()
@@ -624,7 +626,7 @@ def bench_plain(args):
         ctx.hsd_set_timing(False)
         plan = None
     else:
-        plan, launched, _ = plain_plan(hsd, autotune, ctx, ud, ids, j, diag)
+        plan, launched, _ = plain_plan(hsd, autotune, ctx, ud, ids, j, diag, args.retune)
         t_step, phase = timed_plan(torch, plan, stream, args.warmup, args.steps)
     ctx.hsd_sync()
     log(f"{t_step * 1e3:.2f} ms per step (solve {phase[0]:.2f}, contraction {phase[1]:.2f}, diagnostics {phase[2]:.2f})")
@@ -724,7 +726,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="c5: skip the uneven workload's extra key")
     ap.add_argument("--weights", default=WEIGHTS_DIR, help="c5: directory of the trained networks")
     ap.add_argument("--eager", action="store_true", help="c2/c3: time hsd_solve calls instead of plan replays")
-    ap.add_argument("--retune", action="store_true", help="c2/c3 eager: time the launch configurations again")
+    ap.add_argument("--retune", action="store_true", help="time the launch configurations again (cache ignored)")
     ap.add_argument("--no-persistent", action="store_true",
                     help="c2/c3 eager: every class as an ordinary grid (the plan's kernels, for counter runs)")
     ap.add_argument("--contract", choices=("bf16x3", "fp32"), default="bf16x3",

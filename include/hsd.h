@@ -267,6 +267,16 @@ hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg
 hsd_status hsd_set_contract(hsd_ctx* ctx, int32_t mode);
 hsd_status hsd_get_contract(hsd_ctx* ctx, int32_t* mode_host);
 
+/* Workgroup size of the split-BF16 contraction (a tuning choice, results
+ * unchanged: every j value is the same sum in the same order; the emitted
+ * power's FP64 sum is regrouped): 4 waves (the default) walk the padded
+ * wavelengths in panels of 256 and read each grain's P~ rows once per panel,
+ * 8 waves take panels of 512 and read them once, with one workgroup per
+ * compute unit.  Other values fail with HSD_ERR_INVALID_ARG.  Affects later
+ * solves and later plans. */
+hsd_status hsd_set_contract_waves(hsd_ctx* ctx, int32_t waves);
+hsd_status hsd_get_contract_waves(hsd_ctx* ctx, int32_t* waves_host);
+
 /* ---- Autotuner ----
  * Time every configuration of every bin-count class that the listed grains
  * occupy, on the given batch, and keep the fastest per class in the context
@@ -279,14 +289,34 @@ hsd_status hsd_get_contract(hsd_ctx* ctx, int32_t* mode_host);
  * records_host[0..max_records-1]; *n_records receives the number timed.
  * Synchronous; grows the context's workspace. */
 typedef struct {
-    int32_t cls;             /* bin-count class */
-    hsd_class_cfg cfg;       /* configuration timed */
-    int32_t n_grains;        /* grains of the batch in this class */
-    double ms;               /* mean solver-phase time of the timed runs */
+    int32_t cls;             /* bin-count class; -1: a whole-plan record (hsd_autotune_plan's
+                                starting point, or its contraction candidate) */
+    hsd_class_cfg cfg;       /* configuration timed (zeros for cls = -1) */
+    int32_t contract_waves;  /* contraction workgroup size in effect */
+    int32_t n_grains;        /* grains of the batch in this class (all, for cls = -1) */
+    double ms;               /* mean time of the timed runs: the solver phase (hsd_autotune)
+                                or the whole plan replay (hsd_autotune_plan) */
 } hsd_tune_record;
 hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
                         const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
                         int32_t max_records, int32_t* n_records);
+
+/* Tuning for plans, timed as they run: every candidate is a concurrent plan
+ * (HSD_PLAN_CONCURRENT) of the given batch — all occupied classes as
+ * parallel graph branches, then the contraction, into an internal j buffer —
+ * replayed `runs` times (first replay a warm-up, the mean of the others the
+ * score).  Starting from the context's configuration with every class as an
+ * ordinary grid (persistent = 0, as concurrent plans require), it tries, one
+ * class at a time from the largest bin counts down, each other slot-group
+ * size and lane layout with the other classes fixed and keeps any that is
+ * faster, then the other contraction workgroup size
+ * (hsd_set_contract_waves).  The winners stay in the context.  One record per
+ * plan timed (the first, cls = -1, is the starting point).  Synchronous;
+ * allocates a j buffer of n_cells x n_grains x n_lambda floats and one plan
+ * workspace at a time.  On failure the context's configuration is restored. */
+hsd_status hsd_autotune_plan(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                             const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
+                             int32_t max_records, int32_t* n_records);
 
 /* ---- Plans: a batch captured once as a HIP graph ----
  * The paper keeps its data resident on the coprocessor and reuses it across

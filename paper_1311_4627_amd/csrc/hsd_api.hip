@@ -309,7 +309,7 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
         // every grain in one launch; its epilogue also writes the emitted
         // power (diag entry 1), so the diagnostics phase has no work left
         hsd::ContractLaunch cl{d.cslots, static_cast<int>(b.cslots.size()), b.c_blocks, d.Pt, d.pscale, nullptr,
-                               j, diag, c.wtrap, c.L, c.Lp, n_grains, c.contract};
+                               j, diag, c.wtrap, c.L, c.Lp, n_grains, c.contract, c.contract_waves};
         HSD_HIP(ctx, hsd::launch_contract(cl, s));
     }
     HSD_HIP(ctx, record(t, 2, s));
@@ -661,6 +661,20 @@ hsd_status hsd_get_contract(hsd_ctx* ctx, int32_t* mode) {
     return HSD_OK;
 }
 
+hsd_status hsd_set_contract_waves(hsd_ctx* ctx, int32_t waves) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (waves != 4 && waves != 8) return fail(ctx, HSD_ERR_INVALID_ARG, "contraction waves must be 4 or 8");
+    ctx->c.contract_waves = waves;
+    return HSD_OK;
+}
+
+hsd_status hsd_get_contract_waves(hsd_ctx* ctx, int32_t* waves) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (!waves) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
+    *waves = ctx->c.contract_waves;
+    return HSD_OK;
+}
+
 hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
                         const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
                         int32_t max_records, int32_t* n_records) {
@@ -716,6 +730,7 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
                         hsd_tune_record& rec = records_host[*n_records];
                         rec.cls = ci;
                         rec.cfg = hsd_class_cfg{kg, wide, pers};
+                        rec.contract_waves = c.contract_waves;
                         rec.n_grains = static_cast<int32_t>(ids.size());
                         rec.ms = mean;
                     }
@@ -733,6 +748,117 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
     if (s) hipStreamDestroy(s);
     if (st != HSD_OK) return st;
     if (he != hipSuccess) return hip_fail(ctx, he, "hsd_autotune");
+    return HSD_OK;
+}
+
+hsd_status hsd_autotune_plan(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int32_t n_grains,
+                             const int32_t* grain_ids_host, int32_t runs, hsd_tune_record* records_host,
+                             int32_t max_records, int32_t* n_records) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    if (n_cells <= 0 || n_grains <= 0 || runs < 2) return fail(ctx, HSD_ERR_INVALID_ARG, "need n_cells, n_grains > 0 and runs >= 2");
+    if (!u_dev || !grain_ids_host || !n_records || (max_records > 0 && !records_host))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int g = 0; g < n_grains; ++g)
+        if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
+    Ctx& c = ctx->c;
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    *n_records = 0;
+    // classes the batch occupies, and their grain counts
+    int cls_grains[hsd::kClasses] = {};
+    for (int g = 0; g < n_grains; ++g) {
+        const int nb = c.grains[grain_ids_host[g]].n_bins;
+        for (int ci = 0; ci < hsd::kClasses; ++ci) {
+            const int lo = ci + 1 < hsd::kClasses ? hsd::kClassHi[ci + 1] : 0;
+            if (nb > lo && nb <= hsd::kClassHi[ci]) ++cls_grains[ci];
+        }
+    }
+    const size_t jn = static_cast<size_t>(n_cells) * n_grains * c.L;
+    float* j = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipMalloc(&j, sizeof(float) * jn);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    hsd_status st = HSD_OK;
+    hsd::ClassCfg keep[hsd::kClasses];
+    for (int ci = 0; ci < hsd::kClasses; ++ci) keep[ci] = c.cfg[ci];
+    const int keep_waves = c.contract_waves;
+    // one candidate: a concurrent plan of the batch (solver classes as
+    // parallel branches, then the contraction), replayed `runs` times; the
+    // first replay is a warm-up and the mean of the others is the score
+    auto time_plan = [&](int cls, double& ms) -> bool {
+        hsd_plan* p = nullptr;
+        st = hsd_plan_create(ctx, n_cells, u_dev, n_grains, grain_ids_host, j, nullptr, HSD_PLAN_CONCURRENT, &p);
+        if (st != HSD_OK) return false;
+        double sum = 0.0;
+        for (int r = 0; r < runs && he == hipSuccess && st == HSD_OK; ++r) {
+            he = hipEventRecord(e0, s);
+            if (he != hipSuccess) break;
+            st = hsd_plan_launch(p, s);
+            if (st != HSD_OK) break;
+            he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+            if (r > 0) sum += t;
+        }
+        hsd_plan_destroy(p);
+        if (he != hipSuccess || st != HSD_OK) return false;
+        ms = sum / (runs - 1);
+        if (*n_records < max_records) {
+            hsd_tune_record& rec = records_host[*n_records];
+            rec.cls = cls;
+            rec.cfg = cls >= 0 ? hsd_class_cfg{c.cfg[cls].kg, c.cfg[cls].wide, c.cfg[cls].persistent}
+                               : hsd_class_cfg{0, 0, 0};
+            rec.contract_waves = c.contract_waves;
+            rec.n_grains = cls >= 0 ? cls_grains[cls] : n_grains;
+            rec.ms = ms;
+        }
+        ++*n_records;
+        return true;
+    };
+    // start from the current configuration as ordinary grids (a concurrent
+    // plan takes no persistent class), then one class at a time, the largest
+    // first, try each alternative with the others fixed and keep what is
+    // faster; the contraction's workgroup size last
+    for (int ci = 0; ci < hsd::kClasses; ++ci) c.cfg[ci].persistent = 0;
+    double best = 0.0;
+    bool ok = he == hipSuccess && time_plan(-1, best);
+    for (int ci = 0; ci < hsd::kClasses && ok; ++ci) {
+        if (cls_grains[ci] == 0) continue;
+        const hsd::ClassCfg cur = c.cfg[ci];
+        hsd::ClassCfg win = cur;
+        for (int wide = 0; wide <= (ci <= 1 ? 1 : 0) && ok; ++wide)
+            for (int kg = 2; kg <= 4 && ok; kg += 2) {
+                if (wide == cur.wide && kg == cur.kg) continue;
+                c.cfg[ci] = hsd::ClassCfg{kg, wide, 0};
+                double ms = 0.0;
+                ok = time_plan(ci, ms);
+                if (ok && ms < best) {
+                    best = ms;
+                    win = c.cfg[ci];
+                }
+            }
+        c.cfg[ci] = win;
+    }
+    if (ok && c.contract == HSD_CONTRACT_BF16X3) {
+        const int cur = c.contract_waves;
+        c.contract_waves = cur == 4 ? 8 : 4;
+        double ms = 0.0;
+        ok = time_plan(-1, ms);
+        if (!(ok && ms < best)) c.contract_waves = cur;
+    }
+    if (!ok) {
+        for (int ci = 0; ci < hsd::kClasses; ++ci) c.cfg[ci] = keep[ci];
+        c.contract_waves = keep_waves;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (s) hipStreamDestroy(s);
+    if (j) hipFree(j);
+    if (st != HSD_OK) return st;
+    if (he != hipSuccess) return hip_fail(ctx, he, "hsd_autotune_plan");
     return HSD_OK;
 }
 
@@ -1649,7 +1775,7 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     }
     // the flagged pairs' spectra and emitted power, every slot in one launch
     hsd::ContractLaunch cl{c.cslots, static_cast<int>(b.cslots.size()), b.c_blocks, c.Pt, c.pscale, w.cellmap,
-                           j_dev, diag_dev, c.wtrap, c.L, c.Lp, n_grains, c.contract};
+                           j_dev, diag_dev, c.wtrap, c.L, c.Lp, n_grains, c.contract, c.contract_waves};
     HSD_HIP(ctx, hsd::launch_contract(cl, s));
     return HSD_OK;
 }

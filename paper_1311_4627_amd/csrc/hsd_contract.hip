@@ -193,22 +193,25 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
 // table comes split and transposed (Bh, Bl: [Lp][nbp], zero beyond nb), so the
 // loop holds no conversions.
 //
-// A workgroup (four waves) takes 64 rows of one slot and walks the wavelengths
-// in panels of 256; each wave owns 64 x 64 of a panel as 4 x 4 blocks of
-// 16 x 16.  The P~ rows go through LDS (double buffered, one barrier per step
-// of 32 bins), since all four waves use them; each wave reads its own
-// columns of the table straight from global memory (L2: one grain's table
-// serves every row tile), each block's next step as soon as its products of
-// this step have issued.  In
-// a step, lane l supplies row (column) l % 16 of a block with bins
-// 8 (l / 16) + 0..7 of the step.
+// A workgroup of W waves (4 or 8, a tuning choice) takes 64 rows of one slot
+// and walks the wavelengths in panels of 64 W; each wave owns 64 x 64 of a
+// panel as 4 x 4 blocks of 16 x 16.  The P~ rows go through LDS (double
+// buffered, one barrier per step of 32 bins), since every wave uses them;
+// each wave reads its own columns of the table straight from global memory
+// (L2: one grain's table serves every row tile), each block's next step as
+// soon as its products of this step have issued.  Eight waves cover the
+// whole padded grid of up to 512 wavelengths in one panel, so the P~ rows are
+// read once (four waves read them once per panel) at the price of one
+// workgroup per CU.  In a step, lane l supplies row (column) l % 16 of a
+// block with bins 8 (l / 16) + 0..7 of the step.
 constexpr int KS = 32, LKA = KS + 8;        // bins per step; LDS row length of each P~ plane (ushorts)
-constexpr int PW = 256;                     // wavelengths per panel
 
-__global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
-    __shared__ __align__(16) unsigned short Ah[2][BM][LKA];
-    __shared__ __align__(16) unsigned short Al[2][BM][LKA];
-    __shared__ double emsh[4][BM];
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_contract3(ContractLaunch a) {
+    constexpr int NT = 64 * W, PW = 64 * W;
+    constexpr int NPL = W >= 8 ? 1 : 2;         // P~ planes staged per loader thread
+    __shared__ __align__(16) unsigned short As[2][2][BM][LKA];     // [plane][buffer][row][bin]
+    __shared__ double emsh[W][BM];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int b = static_cast<int>(blockIdx.x);
@@ -216,23 +219,30 @@ __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
     const int row0 = (b - sl.tile0) * BM;
     const int rl = lane & 15, q = lane >> 4;
     const int kend = (sl.nb + KS - 1) / KS * KS;
-    // P~ loader: thread t stages row t / 4, bins 8 (t % 4) + 0..7 of a step, both planes
-    // (rows past the slot's last, and bins past nb, load an in-range chunk and
-    // zero it: nb is a multiple of 16, so a chunk of 8 is wholly inside or outside)
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    // P~ loader: thread t stages row (t % 256) / 4, bins 8 (t % 4) + 0..7 of a
+    // step, of both planes (four waves) or of plane t / 256 (eight waves).
+    // Rows past the slot's last, and bins past nb, load an in-range chunk and
+    // zero it (nb is a multiple of 16, so a chunk of 8 is wholly inside or outside).
+    const int lt = tid & 255, pl0 = NPL == 1 ? (tid >> 8) : 0;
+    const int lr = lt >> 2, lk = (lt & 3) * 8;
     const bool arow_ok = (row0 + lr) < sl.rows;
     const unsigned short* Arow = reinterpret_cast<const unsigned short*>(
         a.Pt + sl.pt_off + static_cast<size_t>(min(row0 + lr, sl.rows - 1)) * sl.nb);
-    auto fetch_a = [&](int k0, u32x4c& h, u32x4c& l) {
+    auto fetch_a = [&](int k0, u32x4c (&v)[NPL]) {
         const bool ok = arow_ok && k0 + lk < sl.nb;
         const int k = ok ? k0 + lk : 0;
-        h = load16(Arow + k);
-        l = load16(Arow + sl.nb + k);
         const u32x4c z = {0u, 0u, 0u, 0u};
-        h = ok ? h : z;
-        l = ok ? l : z;
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) {
+            v[p] = load16(Arow + (pl0 + p) * sl.nb + k);
+            v[p] = ok ? v[p] : z;
+        }
     };
-    for (int r = tid; r < 4 * BM; r += 256) emsh[r / BM][r % BM] = 0.0;
+    auto stage_a = [&](int buf, const u32x4c (&v)[NPL]) {
+#pragma unroll
+        for (int p = 0; p < NPL; ++p) *reinterpret_cast<u32x4c*>(&As[pl0 + p][buf][lr][lk]) = v[p];
+    };
+    for (int r = tid; r < W * BM; r += NT) emsh[r / BM][r % BM] = 0.0;
     for (int p0 = 0; p0 < a.Lp; p0 += PW) {
         const int wc = p0 + wave * 64;           // the wave's first column
         const bool wact = wc < a.Lp;             // wave-uniform
@@ -247,25 +257,24 @@ __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[bi][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        u32x4c ah, al, bh[4], bl[4];
-        fetch_a(0, ah, al);
+        u32x4c av[NPL], bh[4], bl[4];
+        fetch_a(0, av);
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) fetch_b(0, cb, bh[cb], bl[cb]);
         __syncthreads();                         // the previous panel's readers are done with buffer 0
-        *reinterpret_cast<u32x4c*>(&Ah[0][lr][lk]) = ah;
-        *reinterpret_cast<u32x4c*>(&Al[0][lr][lk]) = al;
+        stage_a(0, av);
         __syncthreads();
         // Straight-line steps: a wave past the last column computes on an
         // in-range column and writes nothing; the last step fetches its own
         // operands again instead of the (absent) next ones.
         for (int k0 = 0, cur = 0; k0 < kend; k0 += KS, cur ^= 1) {
             const int kn = min(k0 + KS, kend - KS);
-            fetch_a(kn, ah, al);
+            fetch_a(kn, av);
             bf16x8c fh[4], fl[4];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) {
-                fh[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Ah[cur][16 * bi + rl][8 * q]));
-                fl[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&Al[cur][16 * bi + rl][8 * q]));
+                fh[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&As[0][cur][16 * bi + rl][8 * q]));
+                fl[bi] = __builtin_bit_cast(bf16x8c, *reinterpret_cast<const u32x4c*>(&As[1][cur][16 * bi + rl][8 * q]));
             }
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
@@ -279,8 +288,7 @@ __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
                 fetch_b(kn, cb, bh[cb], bl[cb]);     // in flight during the other blocks' products
             }
             // buffer cur ^ 1 was last read before the previous step's barrier
-            *reinterpret_cast<u32x4c*>(&Ah[cur ^ 1][lr][lk]) = ah;
-            *reinterpret_cast<u32x4c*>(&Al[cur ^ 1][lr][lk]) = al;
+            stage_a(cur ^ 1, av);
             __syncthreads();
         }
         if (!wact) continue;
@@ -321,7 +329,15 @@ __global__ void __launch_bounds__(256) k_contract3(ContractLaunch a) {
         const int row = row0 + tid;
         const long long cell = sl.rowmap_off >= 0 ? a.rowmap[sl.rowmap_off + row] : row;
         const long long pair = cell * a.n_gslots + sl.gslot;
-        a.diag[pair * 4 + 1] = static_cast<float>((emsh[0][tid] + emsh[1][tid]) + (emsh[2][tid] + emsh[3][tid]));
+        // the waves' sums in a fixed pairwise order
+        double e[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) e[w] = emsh[w][tid];
+#pragma unroll
+        for (int h = 1; h < W; h <<= 1)
+#pragma unroll
+            for (int w = 0; w + h < W; w += 2 * h) e[w] += e[w + h];
+        a.diag[pair * 4 + 1] = static_cast<float>(e[0]);
     }
 }
 
@@ -354,7 +370,8 @@ int contract_blocks(std::vector<ContractSlot>& slots) {
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
     if (a.n_blocks <= 0 || a.n_slots <= 0) return hipSuccess;
     if (a.Lp % BN != 0) return hipErrorInvalidValue;
-    if (a.mode == 1) hipLaunchKernelGGL(k_contract3, dim3(a.n_blocks), dim3(256), 0, s, a);
+    if (a.mode == 1 && a.waves == 8) hipLaunchKernelGGL(k_contract3<8>, dim3(a.n_blocks), dim3(512), 0, s, a);
+    else if (a.mode == 1) hipLaunchKernelGGL(k_contract3<4>, dim3(a.n_blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_contract, dim3(a.n_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -125,6 +125,7 @@ struct Ctx {
     unsigned* errword = nullptr;  // device: bit 0 set by kernels on non-finite input
     unsigned char* scratch = nullptr;   // device address of the library's fixed scratch array on this device
     int contract = 1;             // emission contraction: 0 FP32 products, 1 three BF16 products (hi/lo split)
+    int contract_waves = 4;       // waves per contraction workgroup (split BF16): 4 or 8
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -185,6 +186,7 @@ struct ContractLaunch {
     float* diag;                 // [cells][n_gslots][4] or null
     const double* wtrap;         // [L] 4 pi x trapezoid weight of each grid wavelength
     int L, Lp, n_gslots, mode;   // mode 0 FP32 products, 1 split BF16
+    int waves;                   // split BF16: waves per workgroup, 4 or 8 (wavelength panels of 64 waves)
 };
 hipError_t launch_contract(const ContractLaunch& a, hipStream_t s);
 // Host side: the slot descriptors of a batch (rows[g] P~ rows of slot g at

@@ -29,7 +29,7 @@ SYMBOLS = (
     "hsd_create", "hsd_destroy", "hsd_last_error", "hsd_add_grain", "hsd_grain_tables",
     "hsd_solve", "hsd_solve_P", "hsd_solve_from_rates", "hsd_sync", "hsd_set_timing", "hsd_phase_ms",
     "hsd_get_class_cfg", "hsd_set_class_cfg", "hsd_set_contract", "hsd_get_contract", "hsd_plan_create", "hsd_plan_launch", "hsd_plan_phase_ms",
-    "hsd_plan_destroy", "hsd_autotune",
+    "hsd_plan_destroy", "hsd_autotune", "hsd_autotune_plan", "hsd_set_contract_waves", "hsd_get_contract_waves",
     "hsd_sur_create", "hsd_sur_destroy", "hsd_sur_n_params", "hsd_sur_set_params", "hsd_sur_get_params",
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
@@ -72,8 +72,8 @@ class hsd_class_cfg(ctypes.Structure):
 
 
 class hsd_tune_record(ctypes.Structure):
-    _fields_ = [("cls", ctypes.c_int32), ("cfg", hsd_class_cfg), ("n_grains", ctypes.c_int32),
-                ("ms", ctypes.c_double)]
+    _fields_ = [("cls", ctypes.c_int32), ("cfg", hsd_class_cfg), ("contract_waves", ctypes.c_int32),
+                ("n_grains", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -125,6 +125,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_autotune.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), i32, ctypes.POINTER(hsd_tune_record), i32,
                                  ctypes.POINTER(i32)]
     lib.hsd_autotune.restype = ctypes.c_int
+    lib.hsd_autotune_plan.argtypes = lib.hsd_autotune.argtypes
+    lib.hsd_autotune_plan.restype = ctypes.c_int
+    lib.hsd_set_contract_waves.argtypes = [vp, i32]
+    lib.hsd_set_contract_waves.restype = ctypes.c_int
+    lib.hsd_get_contract_waves.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.hsd_get_contract_waves.restype = ctypes.c_int
     i64, fp = ctypes.c_int64, ctypes.POINTER(ctypes.c_float)
     lib.hsd_sur_create.argtypes = [vp, ctypes.POINTER(vp)]
     lib.hsd_sur_destroy.argtypes = [vp]
@@ -341,9 +347,7 @@ class Context:
             self._raise(st, "hsd_get_contract")
         return int(m.value)
 
-    def hsd_autotune(self, u, grain_ids: Sequence[int], runs: int = 4):
-        """Time every class configuration on this batch; the context keeps the
-        fastest per class.  Returns one dict per configuration timed."""
+    def _tune(self, fn: str, u, grain_ids: Sequence[int], runs: int):
         import torch
         n_cells = int(u.shape[0])
         ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
@@ -351,13 +355,36 @@ class Context:
         cap = 64
         recs = (hsd_tune_record * cap)()
         n = ctypes.c_int32()
-        st = self._lib.hsd_autotune(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
+        st = getattr(self._lib, fn)(self._h, n_cells, u.data_ptr(), int(ids.shape[0]),
                                     ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(runs), recs, cap,
                                     ctypes.byref(n))
         if st != HSD_OK:
-            self._raise(st, "hsd_autotune")
+            self._raise(st, fn)
         return [{"cls": r.cls, "kg": r.cfg.kg, "wide": r.cfg.wide, "persistent": r.cfg.persistent,
-                 "n_grains": r.n_grains, "ms": r.ms} for r in recs[:min(n.value, cap)]]
+                 "contract_waves": r.contract_waves, "n_grains": r.n_grains, "ms": r.ms}
+                for r in recs[:min(n.value, cap)]]
+
+    def hsd_autotune(self, u, grain_ids: Sequence[int], runs: int = 4):
+        """Time every class configuration on this batch, each class alone; the
+        context keeps the fastest per class.  One dict per configuration timed."""
+        return self._tune("hsd_autotune", u, grain_ids, runs)
+
+    def hsd_autotune_plan(self, u, grain_ids: Sequence[int], runs: int = 4):
+        """Tune for concurrent plans, each candidate timed as a whole plan
+        replay; the context keeps the winners.  One dict per plan timed."""
+        return self._tune("hsd_autotune_plan", u, grain_ids, runs)
+
+    def hsd_set_contract_waves(self, waves: int):
+        st = self._lib.hsd_set_contract_waves(self._h, int(waves))
+        if st != HSD_OK:
+            self._raise(st, "hsd_set_contract_waves")
+
+    def hsd_get_contract_waves(self) -> int:
+        w = ctypes.c_int32()
+        st = self._lib.hsd_get_contract_waves(self._h, ctypes.byref(w))
+        if st != HSD_OK:
+            self._raise(st, "hsd_get_contract_waves")
+        return int(w.value)
 
     def hsd_plan_create(self, u, grain_ids: Sequence[int], j, diag=None, flags: int = 0) -> "Plan":
         import torch

@@ -233,13 +233,64 @@ def test_autotune_keeps_fastest_and_results(hsd, c2_small, tmp_path):
         worst = max(j_rel_err(b[c, g], a[c, g].astype(np.float64)) for c in range(0, w.n_cells, 97)
                     for g in range(len(ids)))
         assert worst < 1e-5
+    finally:
+        _set_all(ctx, hsd, kg=2, wide=0, persistent=0)
+
+
+def test_plan_autotune_keeps_fastest_and_results(hsd, c2_small, tmp_path):
+    from paper_1311_4627_amd import autotune
+    w, ctx, ids, u = c2_small
+    j0, d0 = _eager(ctx, w, ids, u)
+    try:
+        _set_all(ctx, hsd, kg=2, wide=0, persistent=1)      # the tuner starts from ordinary grids
+        recs = ctx.hsd_autotune_plan(u, ids, runs=3)
+        # the start, then per occupied class the other kg x layout choices, then the other contraction size
+        occupied = sum(1 for lo, hi in hsd.CLASS_BINS if any(lo <= ctx.n_bins[g] <= hi for g in ids))
+        assert recs[0]["cls"] == -1 and recs[-1]["cls"] == -1
+        assert len(recs) == 1 + 3 + 3 + 1 + 1 + 1 if occupied == 4 else len(recs) >= 2
+        assert all(r["ms"] > 0 and math.isfinite(r["ms"]) for r in recs)
+        assert all(ctx.hsd_get_class_cfg(c)["persistent"] == 0 for c in range(hsd.N_CLASSES))
+        # coordinate descent keeps only improvements: the kept configuration is the fastest plan timed
+        best = min(recs, key=lambda r: r["ms"])
+        assert ctx.hsd_get_contract_waves() == best["contract_waves"]
+        if best["cls"] >= 0:
+            assert ctx.hsd_get_class_cfg(best["cls"]) == {k: best[k] for k in ("kg", "wide", "persistent")}
+        print("plan autotune:", [ctx.hsd_get_class_cfg(c) for c in range(hsd.N_CLASSES)],
+              ctx.hsd_get_contract_waves(), [round(r["ms"], 3) for r in recs], flush=True)
+        j1, d1 = _eager(ctx, w, ids, u)
+        a, b = j0.cpu().numpy(), j1.cpu().numpy()
+        worst = max(j_rel_err(b[c, g], a[c, g].astype(np.float64)) for c in range(0, w.n_cells, 97)
+                    for g in range(len(ids)))
+        assert worst < 1e-5
         # the JSON cache: first call times and writes, second applies the stored winners
         path = str(tmp_path / "tune.json")
         r1 = autotune.tune(ctx, u, ids, cache_path=path, runs=2)
         assert not r1["cached"]
         _set_all(ctx, hsd, kg=2, wide=0, persistent=0)
+        ctx.hsd_set_contract_waves(8 if r1["contract_waves"] == 4 else 4)
         r2 = autotune.tune(ctx, u, ids, cache_path=path)
-        assert r2["cached"] and r2["cfg"] == r1["cfg"]
+        assert r2["cached"] and r2["cfg"] == r1["cfg"] and r2["contract_waves"] == r1["contract_waves"]
         assert [ctx.hsd_get_class_cfg(c) for c in range(hsd.N_CLASSES)] == r1["cfg"]
+        assert ctx.hsd_get_contract_waves() == r1["contract_waves"]
     finally:
         _set_all(ctx, hsd, kg=2, wide=0, persistent=0)
+        ctx.hsd_set_contract_waves(4)
+
+
+def test_contraction_workgroup_sizes_agree(hsd, c2_small):
+    # 4 or 8 waves per contraction workgroup: every j value is the same sum in
+    # the same order; the emitted power's FP64 sum is only regrouped
+    w, ctx, ids, u = c2_small
+    try:
+        with pytest.raises(hsd.HsdError):
+            ctx.hsd_set_contract_waves(6)
+        j4, d4 = _eager(ctx, w, ids, u)
+        ctx.hsd_set_contract_waves(8)
+        assert ctx.hsd_get_contract_waves() == 8
+        j8, d8 = _eager(ctx, w, ids, u)
+        assert torch.equal(j4, j8)
+        a, b = d4.cpu().numpy().astype(np.float64), d8.cpu().numpy().astype(np.float64)
+        assert np.array_equal(a[..., [0, 2, 3]], b[..., [0, 2, 3]])
+        assert np.max(np.abs(b[..., 1] / a[..., 1] - 1)) < 1e-6
+    finally:
+        ctx.hsd_set_contract_waves(4)

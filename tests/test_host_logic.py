@@ -15,7 +15,7 @@ def test_batch_key_groups_bins_by_solver_class():
     ctx = _FakeCtx([1024, 128, 512, 256, 16, 544, 272])
     key = json.loads(autotune.batch_key(ctx, list(range(7)), 16384, "dev"))
     assert key["bins"] == [[544, 1024], [272, 512], [256], [16, 128]]
-    assert key["L"] == 500 and key["n_cells"] == 16384 and key["device"] == "dev"
+    assert key["L"] == 500 and key["n_cells"] == 16384 and key["device"] == "dev" and key["tuner"] == "plan"
     # the class table matches the ranges the header documents
     assert hsd.CLASS_BINS == ((513, 1024), (257, 512), (129, 256), (16, 128))
 
