@@ -199,15 +199,18 @@ __global__ void __launch_bounds__(256) k_contract(ContractLaunch a) {
 // buffered, one barrier per step of 32 bins), since every wave uses them;
 // each wave reads its own columns of the table straight from global memory
 // (L2: one grain's table serves every row tile), each block's next step as
-// soon as its products of this step have issued.  Eight waves cover the
-// whole padded grid of up to 512 wavelengths in one panel, so the P~ rows are
-// read once (four waves read them once per panel) at the price of one
-// workgroup per CU.  In a step, lane l supplies row (column) l % 16 of a
-// block with bins 8 (l / 16) + 0..7 of the step.
+// soon as its products of this step have issued; the P~ rows are fetched two
+// steps ahead (they come from HBM), and the register budget is held to three
+// waves per SIMD (measured: one step ahead at three waves 1.58 ms per batched
+// step, two steps ahead at two waves 1.64 ms, two ahead at three 1.52 ms).
+// Eight waves cover the whole padded grid of up to 512 wavelengths in one
+// panel, so the P~ rows are read once (four waves read them once per panel)
+// at the price of one workgroup per CU.  In a step, lane l supplies row
+// (column) l % 16 of a block with bins 8 (l / 16) + 0..7 of the step.
 constexpr int KS = 32, LKA = KS + 8;        // bins per step; LDS row length of each P~ plane (ushorts)
 
 template <int W>
-__global__ void __launch_bounds__(64 * W) k_contract3(ContractLaunch a) {
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3, 3))) k_contract3(ContractLaunch a) {
     constexpr int NT = 64 * W, PW = 64 * W;
     constexpr int NPL = W >= 8 ? 1 : 2;         // P~ planes staged per loader thread
     __shared__ __align__(16) unsigned short As[2][2][BM][LKA];     // [plane][buffer][row][bin]
@@ -257,8 +260,9 @@ __global__ void __launch_bounds__(64 * W) k_contract3(ContractLaunch a) {
         for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) acc[bi][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        u32x4c av[NPL], bh[4], bl[4];
+        u32x4c av[NPL], an[NPL], bh[4], bl[4];
         fetch_a(0, av);
+        fetch_a(min(KS, kend - KS), an);         // the next step's rows, two steps ahead from here on
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) fetch_b(0, cb, bh[cb], bl[cb]);
         __syncthreads();                         // the previous panel's readers are done with buffer 0
@@ -269,7 +273,7 @@ __global__ void __launch_bounds__(64 * W) k_contract3(ContractLaunch a) {
         // operands again instead of the (absent) next ones.
         for (int k0 = 0, cur = 0; k0 < kend; k0 += KS, cur ^= 1) {
             const int kn = min(k0 + KS, kend - KS);
-            fetch_a(kn, av);
+            fetch_a(min(k0 + 2 * KS, kend - KS), av);
             bf16x8c fh[4], fl[4];
 #pragma unroll
             for (int bi = 0; bi < 4; ++bi) {
@@ -288,7 +292,9 @@ __global__ void __launch_bounds__(64 * W) k_contract3(ContractLaunch a) {
                 fetch_b(kn, cb, bh[cb], bl[cb]);     // in flight during the other blocks' products
             }
             // buffer cur ^ 1 was last read before the previous step's barrier
-            stage_a(cur ^ 1, av);
+            stage_a(cur ^ 1, an);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) an[p] = av[p];
             __syncthreads();
         }
         if (!wact) continue;
