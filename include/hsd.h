@@ -434,9 +434,14 @@ hsd_status hsd_sur_loss_grad(hsd_sur* sur, int32_t n, const float* X_dev, const 
  * step's minibatch loss.  Optimiser state carries over between calls until
  * hsd_sur_set_params.  On return the parameters are the exponential moving
  * average of the call's iterates (decay min(0.999, 1 - 20 / steps), started
- * from the parameters at the call).  Synchronous. */
+ * from the parameters at the call).  Waits for the device's earlier work
+ * first; synchronous.  The steps run as one captured HIP graph replayed
+ * `steps` times (its per-step values, the minibatch counter and the step
+ * sizes, are read from device memory), unless hsd_sur_set_train_graph(0)
+ * asks for eager launches; both give the same bits. */
 hsd_status hsd_sur_train(hsd_sur* sur, int64_t n, const float* X_dev, const float* Y_dev, int32_t steps,
                          int32_t batch, float lr, uint64_t seed, float* loss_host);
+hsd_status hsd_sur_set_train_graph(hsd_sur* sur, int32_t enable);
 /* Checkpoint and resume (the paper's library is configured once and reused
  * across runs, appendix on the library interface; a trained network is kept
  * the same way).  hsd_surrogate_save writes, synchronously, to the file

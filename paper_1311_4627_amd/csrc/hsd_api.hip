@@ -1610,43 +1610,98 @@ hsd_status hsd_sur_train(hsd_sur* p, int64_t n, const float* X_dev, const float*
     if (!p->s.have_norm) return fail(ctx, HSD_ERR_STATE, "surrogate has no input/target statistics");
     hsd::Sur& s = p->s;
     HSD_HIP(ctx, hipSetDevice(ctx->c.device));
-    const hipStream_t st = nullptr;
     HSD_HIP(ctx, hsd::sur_grow(s, batch));
-    double* trace = nullptr;
-    if (loss_host && steps > 0) HSD_HIP(ctx, hipMalloc(&trace, sizeof(double) * steps));
-    hipError_t e = hipSuccess;
+    if (steps == 0) return HSD_OK;
+    HSD_HIP(ctx, hipDeviceSynchronize());          // the inputs may come from any stream
     const int warm = std::max(1, steps / 50);
     // the trained parameters are the moving average of the iterates (decay
     // min(0.999, 1 - 20 / steps)), which smooths the last steps' noise
     const float ema_decay = static_cast<float>(std::min(0.999, 1.0 - 20.0 / std::max(steps, 1)));
-    const bool ema = steps > 0 && ema_decay > 0.f;
-    if (ema) e = hipMemcpyAsync(s.we, s.w, sizeof(float) * s.n_params, hipMemcpyDeviceToDevice, st);
-    for (int k = 0; k < steps && e == hipSuccess; ++k) {
-        // linear warm-up, then cosine decay to 5% of lr
+    const bool ema = ema_decay > 0.f;
+    // step sizes of every step: linear warm-up, then cosine decay to 5% of lr,
+    // with Adam's bias corrections of steps t0 + 1 .. t0 + steps
+    const long long t0 = s.t;
+    std::vector<float2> sched(steps);
+    std::vector<float> lr_k(steps);
+    for (int k = 0; k < steps; ++k) {
         double f = 1.0;
         if (k < warm) f = static_cast<double>(k + 1) / warm;
         else f = 0.05 + 0.95 * 0.5 * (1.0 + std::cos(hsd::kPi * (k - warm) / std::max(1, steps - warm)));
-        e = hsd::sur_batch_idx(s, seed, s.t, batch, n, st);
-        if (e == hipSuccess) e = hsd::sur_gather(s, X_dev, Y_dev, batch, st);
-        if (e == hipSuccess) e = hsd::sur_forward(s, batch, s.Xb, st, true);
-        if (e == hipSuccess) e = hsd::sur_loss(s, batch, st);
-        if (e == hipSuccess && trace)
-            e = hipMemcpyAsync(trace + k, s.loss, sizeof(double), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hsd::sur_backward(s, batch, s.Xb, st);
-        if (e == hipSuccess) e = hsd::sur_adam(s, static_cast<float>(lr * f), st, ema, ema_decay);
+        lr_k[k] = static_cast<float>(lr * f);
+        sched[k] = hsd::adam_step_sizes(lr_k[k], t0 + k + 1);
+    }
+    double* trace = nullptr;
+    long long* ctr = nullptr;
+    float2* dsched = nullptr;
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess && loss_host) e = hipMalloc(&trace, sizeof(double) * steps);
+    if (e == hipSuccess && ema) e = hipMemcpyAsync(s.we, s.w, sizeof(float) * s.n_params, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && s.train_graph) {
+        // One step captured once and replayed: its per-step values (the
+        // minibatch counter, the step sizes) live in device memory, so every
+        // replay runs exactly the launches of an eager step.
+        e = hipMalloc(&ctr, sizeof(long long));
+        if (e == hipSuccess) e = hipMalloc(&dsched, sizeof(float2) * steps);
+        if (e == hipSuccess) e = hipMemcpyAsync(ctr, &t0, sizeof(long long), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dsched, sched.data(), sizeof(float2) * steps, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t ce = hsd::sur_batch_idx(s, seed, 0, batch, n, st, ctr);
+            if (ce == hipSuccess) ce = hsd::sur_gather(s, X_dev, Y_dev, batch, st);
+            if (ce == hipSuccess) ce = hsd::sur_forward(s, batch, s.Xb, st, true);
+            if (ce == hipSuccess) ce = hsd::sur_loss(s, batch, st);
+            if (ce == hipSuccess) ce = hsd::sur_backward(s, batch, s.Xb, st);
+            if (ce == hipSuccess) ce = hsd::sur_adam_sched(s, dsched, ctr, t0, st, ema, ema_decay);
+            if (ce == hipSuccess) ce = hsd::sur_step_end(ctr, t0, s.loss, trace, st);
+            e = hipStreamEndCapture(st, &graph);
+            if (e == hipSuccess) e = ce;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        for (int k = 0; k < steps && e == hipSuccess; ++k) e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess) {
+            s.t = t0 + steps;
+            s.wb_fresh = false;
+        }
+    } else {
+        for (int k = 0; k < steps && e == hipSuccess; ++k) {
+            e = hsd::sur_batch_idx(s, seed, s.t, batch, n, st);
+            if (e == hipSuccess) e = hsd::sur_gather(s, X_dev, Y_dev, batch, st);
+            if (e == hipSuccess) e = hsd::sur_forward(s, batch, s.Xb, st, true);
+            if (e == hipSuccess) e = hsd::sur_loss(s, batch, st);
+            if (e == hipSuccess && trace)
+                e = hipMemcpyAsync(trace + k, s.loss, sizeof(double), hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hsd::sur_backward(s, batch, s.Xb, st);
+            if (e == hipSuccess) e = hsd::sur_adam(s, lr_k[k], st, ema, ema_decay);
+        }
     }
     if (e == hipSuccess && ema) {
         e = hipMemcpyAsync(s.w, s.we, sizeof(float) * s.n_params, hipMemcpyDeviceToDevice, st);
         s.wb_fresh = false;
     }
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && trace) {
         std::vector<double> h(steps);
         e = hipMemcpy(h.data(), trace, sizeof(double) * steps, hipMemcpyDeviceToHost);
         for (int k = 0; k < steps; ++k) loss_host[k] = static_cast<float>(h[k] / (static_cast<double>(batch) * s.n_out));
     }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st) (void)hipStreamDestroy(st);
     if (trace) (void)hipFree(trace);
+    if (ctr) (void)hipFree(ctr);
+    if (dsched) (void)hipFree(dsched);
     if (e != hipSuccess) return hip_fail(ctx, e, "hsd_sur_train");
+    return HSD_OK;
+}
+
+hsd_status hsd_sur_set_train_graph(hsd_sur* p, int32_t enable) {
+    if (!p) return HSD_ERR_INVALID_ARG;
+    p->s.train_graph = enable != 0;
     return HSD_OK;
 }
 

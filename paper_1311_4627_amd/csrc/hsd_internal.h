@@ -247,6 +247,7 @@ struct Sur {
     float* split_work = nullptr;
     unsigned short* wb = nullptr;   // BF16 weights for inference (W1 padded to 64 inputs)
     bool wb_fresh = false;
+    bool train_graph = true;   // training steps replayed from one captured HIP graph (else eager launches)
     std::vector<float> loss_trace;
 };
 
@@ -265,9 +266,18 @@ hipError_t sur_forward(Sur& s, int B, const float* Xb, hipStream_t st, bool keep
 hipError_t sur_backward(Sur& s, int B, const float* Xb, hipStream_t st);
 hipError_t sur_loss(Sur& s, int B, hipStream_t st);
 hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t st);
-hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st);
+hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st,
+                         const long long* ctr = nullptr);
 hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st);
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st, bool ema = false, float ema_decay = 0.f);
+// Adam's bias-corrected step sizes (lr_t, eps_t) of step t (1-based).
+float2 adam_step_sizes(float lr, long long t);
+// Graph-replayable training step pieces: Adam with the step sizes of step
+// *ctr at sched[*ctr - t0]; the step's end (loss into trace[*ctr - t0] when
+// trace is given, then ++*ctr).
+hipError_t sur_adam_sched(Sur& s, const float2* sched, const long long* ctr, long long t0, hipStream_t st, bool ema,
+                          float ema_decay);
+hipError_t sur_step_end(long long* ctr, long long t0, const double* loss, double* trace, hipStream_t st);
 hipError_t sur_pack(Sur& s, hipStream_t st);
 hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double* A, long long row0, int n_sel,
                           int n_slots, const int* sel, float* j, float* emit, float* rho, unsigned short* h0,

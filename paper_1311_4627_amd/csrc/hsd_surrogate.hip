@@ -383,9 +383,13 @@ __device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
     return x ^ (x >> 31);
 }
 
-__global__ void k_batch_idx(unsigned long long seed, long long step, int B, long long n, long long* idx) {
+// The step comes from `ctr` (device memory) when given: a training step
+// replayed from a graph reads its counter there.
+__global__ void k_batch_idx(unsigned long long seed, long long step, const long long* ctr, int B, long long n,
+                            long long* idx) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
+    if (ctr) step = *ctr;
     const unsigned long long h = splitmix64(seed ^ splitmix64(static_cast<unsigned long long>(step) * B + b));
     idx[b] = static_cast<long long>(h % static_cast<unsigned long long>(n));
 }
@@ -434,10 +438,18 @@ __global__ void __launch_bounds__(256) k_colsum(const float* dz, int B, int N, f
 // Adam (Kingma & Ba) with bias correction folded into the step size.
 // One Adam step; we (if given) follows the iterates as a moving average,
 // we = ed we + (1 - ed) w.
+// With `sched`, the step sizes of step *ctr come from sched[*ctr - t0]
+// (computed on the host, as for the by-value form).
 __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m, float* v, long long n, float lr_t,
-                                              float b1, float b2, float eps_t, float* we, float ed) {
+                                              float b1, float b2, float eps_t, float* we, float ed,
+                                              const float2* sched, const long long* ctr, long long t0) {
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n) return;
+    if (sched) {
+        const float2 p = sched[*ctr - t0];
+        lr_t = p.x;
+        eps_t = p.y;
+    }
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -446,6 +458,15 @@ __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m
     const float wi = w[i] - lr_t * mi / (sqrtf(vi) + eps_t);
     w[i] = wi;
     if (we) we[i] = fmaf(ed, we[i] - wi, wi);
+}
+
+// End of a graph-replayed training step: the minibatch loss into the trace
+// (if any), then the step counter advances.
+__global__ void k_step_end(long long* ctr, long long t0, const double* loss, double* trace) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long long t = *ctr;
+    if (trace) trace[t - t0] = *loss;
+    *ctr = t + 1;
 }
 
 // ---- BF16 matrix-core GEMM ----------------------------------------------------------
@@ -1242,8 +1263,9 @@ hipError_t sur_gather(Sur& s, const float* X, const float* Y, int B, hipStream_t
     return e;
 }
 
-hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_idx, dim3((B + 255) / 256), dim3(256), 0, st, seed, step, B, n, s.idx);
+hipError_t sur_batch_idx(Sur& s, unsigned long long seed, long long step, int B, long long n, hipStream_t st,
+                         const long long* ctr) {
+    hipLaunchKernelGGL(k_batch_idx, dim3((B + 255) / 256), dim3(256), 0, st, seed, step, ctr, B, n, s.idx);
     return hipGetLastError();
 }
 
@@ -1255,17 +1277,33 @@ hipError_t sur_seq_idx(Sur& s, long long first, int B, hipStream_t st) {
     return e;
 }
 
+float2 adam_step_sizes(float lr, long long t) {
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - std::pow(b1, static_cast<double>(t));
+    const double c2 = 1.0 - std::pow(b2, static_cast<double>(t));
+    // w -= lr (m / c1) / (sqrt(v / c2) + eps) = lr sqrt(c2) / c1 * m / (sqrt(v) + eps sqrt(c2))
+    return make_float2(static_cast<float>(lr * std::sqrt(c2) / c1), static_cast<float>(eps * std::sqrt(c2)));
+}
+
 hipError_t sur_adam(Sur& s, float lr, hipStream_t st, bool ema, float ema_decay) {
     ++s.t;
     s.wb_fresh = false;
-    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
-    const double c1 = 1.0 - std::pow(b1, static_cast<double>(s.t));
-    const double c2 = 1.0 - std::pow(b2, static_cast<double>(s.t));
-    // w -= lr (m / c1) / (sqrt(v / c2) + eps) = lr sqrt(c2) / c1 * m / (sqrt(v) + eps sqrt(c2))
-    const float lr_t = static_cast<float>(lr * std::sqrt(c2) / c1);
-    const float eps_t = static_cast<float>(eps * std::sqrt(c2));
+    const float2 p = adam_step_sizes(lr, s.t);
     hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((s.n_params + 255) / 256)), dim3(256), 0, st, s.w, s.g,
-                       s.m, s.v, s.n_params, lr_t, 0.9f, 0.999f, eps_t, ema ? s.we : nullptr, ema_decay);
+                       s.m, s.v, s.n_params, p.x, 0.9f, 0.999f, p.y, ema ? s.we : nullptr, ema_decay,
+                       static_cast<const float2*>(nullptr), static_cast<const long long*>(nullptr), 0LL);
+    return hipGetLastError();
+}
+
+hipError_t sur_adam_sched(Sur& s, const float2* sched, const long long* ctr, long long t0, hipStream_t st, bool ema,
+                          float ema_decay) {
+    hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((s.n_params + 255) / 256)), dim3(256), 0, st, s.w, s.g,
+                       s.m, s.v, s.n_params, 0.f, 0.9f, 0.999f, 0.f, ema ? s.we : nullptr, ema_decay, sched, ctr, t0);
+    return hipGetLastError();
+}
+
+hipError_t sur_step_end(long long* ctr, long long t0, const double* loss, double* trace, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, st, ctr, t0, loss, trace);
     return hipGetLastError();
 }
 

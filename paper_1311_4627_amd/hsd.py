@@ -34,7 +34,7 @@ SYMBOLS = (
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
     "hsd_surrogate_save", "hsd_surrogate_load", "hsd_solve_noalloc", "hsd_sur_set_loss", "hsd_measure_exp2",
-    "hsd_table_build", "hsd_table_eval",
+    "hsd_table_build", "hsd_table_eval", "hsd_sur_set_train_graph",
 )
 
 N_CLASSES = 4
@@ -145,6 +145,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_sur_fit_norm.argtypes = [vp, i64, vp, vp]
     lib.hsd_sur_loss_grad.argtypes = [vp, i32, vp, vp, dp, fp]
     lib.hsd_sur_train.argtypes = [vp, i64, vp, vp, i32, i32, ctypes.c_float, ctypes.c_uint64, fp]
+    lib.hsd_sur_set_train_graph.argtypes = [vp, i32]
+    lib.hsd_sur_set_train_graph.restype = ctypes.c_int
     lib.hsd_sur_predict.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, vp, vp]
     lib.hsd_solve_surrogate.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.c_float,
                                         i32, vp, vp, ctypes.POINTER(i64), vp]
@@ -621,6 +623,9 @@ class Surrogate:
         self._check(self._lib.hsd_sur_train(self._h, n, X.data_ptr(), Y.data_ptr(), int(steps), int(batch),
                                             float(lr), int(seed), _fptr(trace)), "hsd_sur_train")
         return trace[:int(steps)]
+
+    def hsd_sur_set_train_graph(self, enable: bool):
+        self._check(self._lib.hsd_sur_set_train_graph(self._h, 1 if enable else 0), "hsd_sur_set_train_graph")
 
     def hsd_sur_set_loss(self, band_weight: float):
         self._check(self._lib.hsd_sur_set_loss(self._h, float(band_weight)), "hsd_sur_set_loss")

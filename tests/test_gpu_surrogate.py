@@ -339,6 +339,29 @@ def test_training_is_deterministic_and_resumes_from_a_checkpoint(hsd, small, tmp
     assert np.array_equal(t0, t1)
     assert np.array_equal(nets[0].hsd_sur_get_params(), nets[1].hsd_sur_get_params())
     print("same seed: identical weights and loss traces", flush=True)
+    # training steps replayed from one captured graph (the default) give the
+    # bits of eager launches, also over two calls with other work between them
+    def fresh_net(graph):
+        sur = hsd.Surrogate(d["ctx"])
+        sur.hsd_sur_set_params(flat)
+        sur.hsd_sur_fit_norm(d["X"], d["Y"])
+        sur.hsd_sur_set_train_graph(graph)
+        return sur
+    eager = fresh_net(False)
+    te = eager.hsd_sur_train(d["X"], d["Y"], steps=120, batch=512, lr=2e-3, seed=11)
+    assert np.array_equal(te, t0)
+    assert np.array_equal(eager.hsd_sur_get_params(), nets[0].hsd_sur_get_params())
+    g2, e2 = fresh_net(True), fresh_net(False)
+    jx = torch.empty((8, len(d["ids"]), w.n_lambda), dtype=torch.float32, device="cuda")
+    ga = g2.hsd_sur_train(d["X"], d["Y"], steps=60, batch=512, lr=2e-3, seed=11)
+    g2.hsd_sur_predict(d["ud"][:8].contiguous(), d["ids"], jx)
+    torch.cuda.synchronize()
+    gb = g2.hsd_sur_train(d["X"], d["Y"], steps=60, batch=512, lr=2e-3, seed=11)
+    ea = e2.hsd_sur_train(d["X"], d["Y"], steps=60, batch=512, lr=2e-3, seed=11)
+    eb = e2.hsd_sur_train(d["X"], d["Y"], steps=60, batch=512, lr=2e-3, seed=11)
+    assert np.array_equal(ga, ea) and np.array_equal(gb, eb)
+    assert np.array_equal(g2.hsd_sur_get_params(), e2.hsd_sur_get_params())
+    print("graph-replayed and eager training: identical weights and loss traces", flush=True)
     # checkpoint after N = 120 steps, then M = 80 more on both sides
     path = str(tmp_path / "net.hsdsur")
     nets[1].hsd_surrogate_save(path)
