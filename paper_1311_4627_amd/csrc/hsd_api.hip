@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "hsd_ckpt.h"
 #include "hsd_internal.h"
 
 using hsd::Ctx;
@@ -1293,39 +1294,6 @@ bool host_is_little_endian() {
     return b[0] == 1;
 }
 
-// The number after "key": in a one-line JSON header, or false.
-bool json_number(const std::string& h, const char* key, long long& out) {
-    const std::string k = std::string("\"") + key + "\":";
-    const size_t at = h.find(k);
-    if (at == std::string::npos) return false;
-    const char* p = h.c_str() + at + k.size();
-    char* end = nullptr;
-    out = std::strtoll(p, &end, 10);
-    return end != p;
-}
-
-bool json_real(const std::string& h, const char* key, double& out) {
-    const std::string k = std::string("\"") + key + "\":";
-    const size_t at = h.find(k);
-    if (at == std::string::npos) return false;
-    const char* p = h.c_str() + at + k.size();
-    char* end = nullptr;
-    out = std::strtod(p, &end);
-    return end != p;
-}
-
-bool json_bool(const std::string& h, const char* key, bool& out) {
-    const std::string k = std::string("\"") + key + "\":";
-    const size_t at = h.find(k);
-    if (at == std::string::npos) return false;
-    size_t q = at + k.size();
-    while (q < h.size() && h[q] == ' ') ++q;
-    if (h.compare(q, 4, "true") == 0) out = true;
-    else if (h.compare(q, 5, "false") == 0) out = false;
-    else return false;
-    return true;
-}
-
 struct SurSection {
     const char* name;
     float* dev;
@@ -1403,30 +1371,15 @@ hsd_status hsd_surrogate_load(hsd_sur* p, const char* path) {
     const bool read_err = std::ferror(f) != 0;
     std::fclose(f);
     if (read_err) return fail(ctx, HSD_ERR_INVALID_ARG, std::string("read failed: ") + path);
-    const std::string magic = "HSDSUR 1\n";
-    if (data.compare(0, magic.size(), magic) != 0) return fail(ctx, HSD_ERR_INVALID_ARG, "not a surrogate checkpoint");
-    const size_t eol = data.find('\n', magic.size());
-    if (eol == std::string::npos) return fail(ctx, HSD_ERR_INVALID_ARG, "truncated header");
-    const std::string h = data.substr(magic.size(), eol - magic.size());
-    long long np = 0, step = 0;
-    bool opt = false;
-    double bw = 0.0;
-    if (!json_number(h, "n_params", np) || !json_number(h, "step", step) || !json_bool(h, "optimizer", opt) ||
-        !json_real(h, "loss_band_weight", bw) || h.find("\"byte_order\": \"little\"") == std::string::npos)
-        return fail(ctx, HSD_ERR_INVALID_ARG, "malformed header");
-    if (!(bw >= 0.0 && bw <= 1.0)) return fail(ctx, HSD_ERR_INVALID_ARG, "loss_band_weight outside [0, 1]");
-    std::string want = "\"widths\": [";
-    for (int i = 0; i < 5; ++i) want += std::to_string(s.widths[i]) + (i < 4 ? ", " : "]");
-    if (h.find(want) == std::string::npos || np != s.n_params)
-        return fail(ctx, HSD_ERR_INVALID_ARG, "checkpoint of a network of another shape");
-    if (step < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative step count");
+    hsd::CkptHeader hd;
+    const std::string why = hsd::ckpt_parse(data, s.widths, s.n_params, hd);
+    if (!why.empty()) return fail(ctx, HSD_ERR_INVALID_ARG, why);
+    const bool opt = hd.optimizer;
+    const long long step = hd.step;
+    const double bw = hd.band_weight;
     const std::vector<SurSection> secs = sur_sections(s, opt);
-    size_t need = 0;
-    for (const SurSection& sec : secs) need += sizeof(float) * static_cast<size_t>(sec.n);
-    const size_t off0 = eol + 1;
-    if (data.size() != off0 + need) return fail(ctx, HSD_ERR_INVALID_ARG, "checkpoint size does not match its header");
     std::vector<std::vector<float>> host(secs.size());
-    size_t off = off0;
+    size_t off = hd.payload_off;
     for (size_t i = 0; i < secs.size(); ++i) {
         host[i].resize(static_cast<size_t>(secs[i].n));
         std::memcpy(host[i].data(), data.data() + off, sizeof(float) * secs[i].n);
