@@ -33,14 +33,10 @@ struct alignas(32) ColPar {
 };
 
 // Interpolation constants of a transition distance d = f - i: grid
-// coordinate b_d = ln(r^d - 1) / dln(lambda) split as -floor and fraction, and
-// the distance's share d log2(r) of the log2 rate (the upper bin's width grows
-// by r per bin).
-struct alignas(16) DPar {
+// coordinate b_d = ln(r^d - 1) / dln(lambda) split as -floor and fraction.
+struct alignas(8) DPar {
     int nib;          // -floor(b_d)
     float fb;         // b_d - floor(b_d), in [0, 1)
-    float dlr;        // d log2(r)
-    int pad;
 };
 
 // Device tables of one registered grain (all owned by the context).

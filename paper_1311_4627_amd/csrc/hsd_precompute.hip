@@ -288,14 +288,10 @@ __global__ void k_tables(int n, int L, double E_lo, double E_hi, double lnlam0, 
         split_coord(b, ib, fb);
         dpar[i].nib = -ib;
         dpar[i].fb = fb;
-        dpar[i].dlr = static_cast<float>(i * lnr / log(2.0));
-        dpar[i].pad = 0;
     } else {
         // distance 0 (a row at or below the diagonal) lands far below the grid
         dpar[0].nib = -(1 << 20);
         dpar[0].fb = 0.0f;
-        dpar[0].dlr = 0.0f;
-        dpar[0].pad = 0;
     }
     // column parameters
     const double lnEi = log(E_lo) + i * lnr;

@@ -22,14 +22,19 @@
 // log-uniform grids the transition's wavelength-grid coordinate is
 // a_f - b_(k-f) (see hsd_index.h); the log-log interpolation of
 // Omega = u_lambda C_abs (eq:interpolation) and the factor lambda^3 dE_k / (h^2 c)
-// of eq:heating fold into one exp2 of
-//     tab[jlo] + w (tab[jlo+1] - tab[jlo]) + gamma_k
+// of eq:heating give A_kf = 2^(tab[jlo] + w (tab[jlo+1] - tab[jlo])) 2^gamma_k
 // with tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) (per pair, in LDS) and
-// gamma_k = log2(dE_k) + 3 log2(lambda_0) - log2(h^2 c) (per row, in registers).
-// The exponent and exp2 are single precision; the product with X_f and every
-// sum are double precision.  Row slots are processed in groups of four with
-// straight-line bodies, so the LDS reads of a group overlap; a group wholly
-// outside the column's grid-resident rows kb..ke skips its rates.
+// gamma_k = log2(dE_k) + 3 log2(lambda_0) - log2(h^2 c).  The upper bin's width
+// dE_k grows by r per bin, so 2^gamma_k = c0 r^k depends on the row alone and
+// stays out of the per-rate arithmetic: the register of a row above the
+// diagonal holds H(k) = G(k) / (c0 r^k), updated by H(k) += 2^(...) X_f, and the
+// lane's share of the suffix sum, sum over its slots s of c0 r^(s P + q - s0) H,
+// is evaluated by Horner's rule in r^-P from the lowest slot up and scaled once
+// by the lane's factor c0 r^((R-1) P + q - s0).  The exponent and exp2 are single precision; the
+// product with X_f and every sum are double precision.  Row slots are
+// processed in groups of four with straight-line bodies, so the LDS reads of a
+// group overlap; a group wholly outside the column's grid-resident rows kb..ke
+// skips its rates.
 //
 // Continuous (intrabin) heating of row f+1 from column f adds
 // X_f Cum(jstar_f) / (E_(f+1) - E_f), Cum_j being the absorbed power of photons at
@@ -51,6 +56,10 @@ namespace {
 constexpr double kBig = 0x1p500;
 constexpr double kShrink = 0x1p-500;
 constexpr float kNoField = -1.0e30f;   // log2 table entry of a non-positive Omega
+// The pair's log2 table is shifted to a largest entry of kBias (and c0 down by
+// 2^-kBias), so single-precision exp2 keeps that much headroom below its
+// underflow for the rates of the faint parts of the field.
+constexpr float kBias = 64.0f;
 
 // v from another lane of the same 16-lane row (a full permutation, so every
 // lane has a source).
@@ -164,10 +173,10 @@ __device__ __forceinline__ int med3_i32(int x, int lo, int hi) {
 
 template <int R>
 struct Rec {
-    double G[R];       // inflow G(k) of the lane's rows, then X_k once row k is passed
+    double G[R];       // H(k) = G(k) / (c0 r^k) of the lane's rows, then X_k once row k is passed
     float intra[R];    // continuous-heating rate into each row from the row below (register variant)
     double part;       // this lane's share of sum_{k >= f} G(k) for the next step
-    double cf;         // 2^(gamma_f + off): the column's share of the rate factor
+    double lf;         // c0 r^((R-1) P + q - s0): the factor of the lane's row in the top slot
     int nres;          // rescales so far
     ColPar cnext;      // prefetched parameters of the next column
 };
@@ -175,7 +184,7 @@ struct Rec {
 struct StepEnv {
     int q, nb, Lm1;
     int s0;            // row k sits at position k + s0 (s0 = R P - nb): the tail slot holds the top bin
-    double rbin;       // cf grows by r per column
+    double irP;        // r^-P: the factor between a lane's consecutive slots, downwards (1 for given rates)
     double total;      // the pair's absorbed power (Cum_0)
     const ColPar* colpar;
     const DPar* dpar;  // LDS
@@ -189,18 +198,19 @@ struct StepEnv {
 // Per-step values the slot groups need.
 struct StepState {
     int pf, l, kb, ke;     // column position pf = f + s0, lane of the diagonal, grid-resident rows (positions)
-    double Xg;         // X_f times the column's rate factor
+    double Xg;         // X_f
     int cb;            // LDS byte address of table entry ia1 of the column
     float fa;
 };
 
 // One group of KG row slots starting at slot R0 (>= RO) for step f: rates of
-// the column into the group's rows, the FP64 update G += A X, and the group's
-// share of the next suffix sum.  Straight-line, so the group's LDS reads are
-// in flight together; skipped by a wave-uniform test when none of its rows is
-// grid-resident for this column.
+// the column into the group's rows, the FP64 update H += 2^(...) X, and the
+// group's Horner steps of the next suffix sum (acc = acc r^-P + H, lowest slot
+// first).  Straight-line, so the group's LDS reads are in flight together;
+// skipped by a wave-uniform test when none of its rows is grid-resident for
+// this column.
 template <int P, int R, int KG, bool GIVEN, int RO, int R0>
-__device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const StepState& ss, double& part) {
+__device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const StepState& ss, double& acc) {
     constexpr int NS = (R - R0) < KG ? (R - R0) : KG;
     const int q = e.q, nb = e.nb;
     const int lo_pos = R0 * P, hi_pos = (R0 + NS) * P - 1;
@@ -240,39 +250,40 @@ __device__ __forceinline__ void slot_group(Rec<R>& st, const StepEnv& e, const S
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s)
-                A[s] = static_cast<double>(__builtin_amdgcn_exp2f(fmaf(w[s], t1[s] - t0[s], t0[s]) + dp[s].dlr));
+                A[s] = static_cast<double>(__builtin_amdgcn_exp2f(fmaf(w[s], t1[s] - t0[s], t0[s])));
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) st.G[R0 + s] = fma(A[s], ss.Xg, st.G[R0 + s]);
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        if (R0 + s == RO) part += (q > ss.l) ? st.G[R0 + s] : 0.0;
-        else part += st.G[R0 + s];
+        if (R0 + s == RO) acc = (q > ss.l) ? st.G[R0 + s] : 0.0;    // the first term: acc is 0
+        else acc = fma(acc, e.irP, st.G[R0 + s]);
     }
 }
 
 template <int P, int R, int KG, bool GIVEN, int RO, int... G>
-__device__ __forceinline__ void all_groups(Rec<R>& st, const StepEnv& e, const StepState& ss, double& part,
+__device__ __forceinline__ void all_groups(Rec<R>& st, const StepEnv& e, const StepState& ss, double& acc,
                                            std::integer_sequence<int, G...>) {
-    (slot_group<P, R, KG, GIVEN, RO, RO + G * KG>(st, e, ss, part), ...);
+    (slot_group<P, R, KG, GIVEN, RO, RO + G * KG>(st, e, ss, acc), ...);
 }
 
 // All steps f = RO*P .. RO*P + P - 1 (the columns whose rows sit in slot RO).
 // Slots below RO are finished and untouched; slot RO holds the diagonal.
 //
 // The rate of column f into row k = f + d is
-//     A = exp2(tab[jlo] + w (tab[jlo+1] - tab[jlo]) + d log2 r) * cf,
-// cf = 2^(gamma_f + off) in FP64 (grown by r per column), folded into X_f.
+//     A = exp2(tab[jlo] + w (tab[jlo+1] - tab[jlo])) * c0 r^k;
+// the register of row k accumulates the exp2 terms times X_f (H units), and
+// the row factor enters once per lane and column through the Horner sum.
 // Rates need no per-lane masks: the log2 table carries a non-field sentinel
 // one entry below lambda_0 and two above lambda_(L-1), the interval index is
 // clamped into [-1, L], and distance 0 (rows at or below the diagonal) maps far
 // below the grid, so every transition off the wavelength grid evaluates to
-// exp2(-1e30-ish) = 0 exactly.  Rows past the grain's top bin (the tail of the
-// last slot) collect junk that is never summed or written.  Slots are handled
-// KG at a time as straight-line code, so the LDS reads of a group are in
-// flight together; a group wholly outside the column's grid-resident rows
-// kb..ke is skipped by a wave-uniform test.
+// exp2(-1e30-ish) = 0 exactly.  Positions below row 0 (the head of slot 0 when
+// the bin count is not a multiple of P) hold no row: they are never summed or
+// written.  Slots are handled KG at a time as straight-line code, so the LDS
+// reads of a group are in flight together; a group wholly outside the
+// column's grid-resident rows kb..ke is skipped by a wave-uniform test.
 template <int P, int R, int KG, bool GIVEN, bool LDSCUM, int RO>
 __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
     const int q = e.q, nb = e.nb, s0 = e.s0;
@@ -301,21 +312,23 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
         }
         if (q == l) st.G[RO] = Xf;
         int kb, ke;
-        double Xg = Xf;
         if constexpr (GIVEN) {
             kb = pf + 1;
             ke = nb - 1 + s0;
         } else {
             kb = max(cc.kb + s0, pf + 1);
             ke = cc.ke + s0;
-            Xg = Xf * st.cf;
-            st.cf *= e.rbin;
         }
-        double part = 0.0;
-        StepState ss{pf, l, kb, ke, Xg, 4 * cc.ia + e.tlo + 4, cc.fa};
-        all_groups<P, R, KG, GIVEN, RO>(st, e, ss, part, std::make_integer_sequence<int, (R - RO + KG - 1) / KG>{});
+        double acc = 0.0;
+        StepState ss{pf, l, kb, ke, Xf, 4 * cc.ia + e.tlo + 4, cc.fa};
+        all_groups<P, R, KG, GIVEN, RO>(st, e, ss, acc, std::make_integer_sequence<int, (R - RO + KG - 1) / KG>{});
+        double part = acc * st.lf;
         if constexpr (!GIVEN) {
-            // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1)
+            // continuous heating of row f+1 (its owner: lane l+1 of slot RO, or lane 0 of slot RO+1).
+            // Row f+1 enters only the next step's suffix sum (then it is the diagonal, masked
+            // out of the sums and overwritten by X_(f+1)), so the term counts through part
+            // alone; the write into the row's register is never read, but without it the
+            // compiler keeps far more registers live across the column loop.
             double cin = 0.0;
             if constexpr (LDSCUM) {
                 cin = (cc.jstar <= e.Lm1) ? static_cast<double>(e.cum[cc.jstar]) * e.total *
@@ -392,8 +405,15 @@ struct KArgs {
 // Every workgroup leaves the loop once the counter has passed the last item.
 // (The body stays in the kernel itself: moved into a function that takes the
 // kernel arguments by reference, it costs 10-20 more VGPRs.)
+//
+// Occupancy: the kernel is held to 128 VGPRs, 4 waves per SIMD.  The column
+// loops fit in that budget without spills; the compiler moves a few dozen
+// values of the setup and the output epilogue (run once per pair) to scratch,
+// which costs far less than the fourth wave gains in hiding the LDS and exp2
+// latencies of the rate groups (the ~1024-bin class runs 10% faster than at
+// 3 waves, the ~256-bin class 14%).
 template <int P, int R, int KG, int WAVES, bool GIVEN, bool LDSCUM, bool PERSIST>
-__global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_solve(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next;
     int item = blockIdx.x;
@@ -514,8 +534,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
                 }
                 __syncthreads();
             }
-            // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off, off = the
-            // pair's largest entry (restored through cf, so the exponent stays small).
+            // Pass 2: tab_j = log2(u_j C_abs_j) + 3 j dlog2(lambda) - off + kBias, off =
+            // the pair's largest entry (restored through c0, so the exponent stays small).
             float mx = -INFINITY;
             for (int j = q; j < L; j += P) {
                 const double om = clean_field(uc[j], bad) * gv.cabs[j];
@@ -532,14 +552,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
             const float off = (mx > -INFINITY) ? mx : 0.0f;
             for (int j = q; j < L; j += P) {
                 const float v = tab[j];
-                tab[j] = (v > kNoField) ? v - off : kNoField;
+                tab[j] = (v > kNoField) ? (v - off) + kBias : kNoField;
             }
             if (q == 0) {
                 tab[-1] = kNoField;
                 tab[L] = kNoField;
                 tab[L + 1] = kNoField;
             }
-            cf0 = exp2(gv.gam[0] + static_cast<double>(off));
+            cf0 = exp2(gv.gam[0] + static_cast<double>(off) - static_cast<double>(kBias));
             __syncthreads();
         }
 
@@ -548,13 +568,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_solve(KArgs a) {
         for (int r = 0; r < R; ++r) st.G[r] = 0.0;
         st.part = 0.0;
         st.nres = 0;
-        st.cf = cf0;
+        if constexpr (GIVEN) {
+            st.lf = 1.0;
+        } else {
+            // c0 r^((R-1) P + q - s0), the factor of the lane's row in the top slot
+            st.lf = cf0 * exp2(static_cast<double>((R - 1) * P + q - (R * P - nb)) * log2(gv.rbin));
+        }
         StepEnv env;
         env.q = q;
         env.nb = nb;
         env.s0 = R * P - nb;
         env.Lm1 = a.L - 1;
-        env.rbin = gv.rbin;
+        env.irP = GIVEN ? 1.0 : exp2(-static_cast<double>(P) * log2(gv.rbin));
         env.total = total;
         env.colpar = gv.colpar;
         env.dpar = dpar_s;
