@@ -177,6 +177,7 @@ struct Rec {
     float intra[R];    // continuous-heating rate into each row from the row below (register variant)
     double part;       // this lane's share of sum_{k >= f} G(k) for the next step
     double lf;         // c0 r^((R-1) P + q - s0): the factor of the lane's row in the top slot
+    double srep;       // LDS-table variant: the lane's finished rows' sum of X_k Cum(jrep_k) / total
     int nres;          // rescales so far
     ColPar cnext;      // prefetched parameters of the next column
 };
@@ -187,6 +188,7 @@ struct StepEnv {
     double irP;        // r^-P: the factor between a lane's consecutive slots, downwards (1 for given rates)
     double total;      // the pair's absorbed power (Cum_0)
     const ColPar* colpar;
+    const int* jrep;   // per row: first grid index of the photons it can absorb within the grid (L: none)
     const DPar* dpar;  // LDS
     const float* tab;  // LDS, this pair's log2 table
     int tlo, thi;      // LDS byte addresses of table entries -1 and L
@@ -288,6 +290,12 @@ template <int P, int R, int KG, bool GIVEN, bool LDSCUM, int RO>
 __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
     const int q = e.q, nb = e.nb, s0 = e.s0;
     if (RO * P + P - 1 < s0) return;          // only positions below row 0
+    // LDS-table variant: the representable-power share of the lane's row in this
+    // slot, added once the block's steps have made it final (its table index is
+    // fetched now, so the load's latency passes under the steps)
+    const int kro = max(RO * P + q - s0, 0);
+    int jrk = 0;
+    if constexpr (LDSCUM && !GIVEN) jrk = e.jrep[kro];
 #pragma unroll 1
     for (int l = 0; l < P; ++l) {
         const int pf = RO * P + l;
@@ -308,9 +316,11 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
             Xf *= kShrink;
 #pragma unroll
             for (int r = 0; r < R; ++r) st.G[r] *= kShrink;
+            if constexpr (LDSCUM && !GIVEN) st.srep *= kShrink;
             ++st.nres;
         }
         if (q == l) st.G[RO] = Xf;
+
         int kb, ke;
         if constexpr (GIVEN) {
             kb = pf + 1;
@@ -356,6 +366,11 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
             }
         }
         st.part = part;
+    }
+    if constexpr (LDSCUM && !GIVEN) {
+        // X of the row is final up to the exact rescales, which scale the sum too
+        const float cv = e.cum[min(jrk, e.Lm1)];
+        if (RO * P + q >= s0 && jrk <= e.Lm1) st.srep = fma(st.G[RO], static_cast<double>(cv), st.srep);
     }
 }
 
@@ -567,6 +582,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int r = 0; r < R; ++r) st.G[r] = 0.0;
         st.part = 0.0;
+        st.srep = 0.0;
         st.nres = 0;
         if constexpr (GIVEN) {
             st.lf = 1.0;
@@ -582,6 +598,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         env.irP = GIVEN ? 1.0 : exp2(-static_cast<double>(P) * log2(gv.rbin));
         env.total = total;
         env.colpar = gv.colpar;
+        env.jrep = gv.jrep;
         env.dpar = dpar_s;
         env.tab = tab;
         if constexpr (!GIVEN) {
@@ -599,40 +616,53 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         all_columns<P, R, KG, GIVEN, LDSCUM>(st, env, std::make_integer_sequence<int, R>{});
         double* G = st.G;
         const int nres = st.nres;
+        // The output addresses depend on the lane and the pair's row; made opaque
+        // here, they are formed after the recursion instead of being hoisted
+        // above it by the compiler (and kept in scratch memory across it).
+        int qo = q, rowko = rowk;
+        asm volatile("" : "+v"(qo), "+v"(rowko));
 
         // ---- normalisation (eq:renormalization) and outputs ----
         const int s0 = R * P - nb;
         double sx = 0.0, mxx = 0.0, srep = 0.0;
+        if constexpr (LDSCUM && !GIVEN) {
+            // positions below row 0 hold 0 (no rate reaches them and no step ends
+            // there); the representable power was accumulated block by block
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int k = r * P + q - s0;
-            if (k >= 0) {
+            for (int r = 0; r < R; ++r) {
                 sx += G[r];
                 mxx = fmax(mxx, G[r]);
-                float rv = rep[r];
-                if constexpr (LDSCUM && !GIVEN) {
-                    const int jr = gv.jrep[k];
-                    rv = jr < a.L ? cum[jr] : 0.0f;
-                }
-                srep += G[r] * static_cast<double>(rv);
             }
+            srep = seg_sum<P>(st.srep);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = r * P + qo - s0;
+                if (k >= 0) {
+                    sx += G[r];
+                    mxx = fmax(mxx, G[r]);
+                    float rv = rep[r];
+                    asm volatile("" : "+v"(rv));   // converted here, not before the recursion
+                    srep += G[r] * static_cast<double>(rv);
+                }
+            }
+            srep = seg_sum<P>(srep);
         }
         sx = seg_sum<P>(sx);
         mxx = seg_max<P>(mxx);
-        srep = seg_sum<P>(srep);
         bad = seg_maxf<P>(bad ? 1.0f : 0.0f) > 0.0f;
         if (live) {
             if (a.P64) {
                 double* prow = a.P64 + static_cast<size_t>(cell) * nb;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int k = r * P + q - s0;
+                    const int k = r * P + qo - s0;
                     if (k >= 0) prow[k] = G[r] / sx;
                 }
             }
             if constexpr (!GIVEN) {
                 if (a.Pt) {
-                    float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(rowk) * nb;
+                    float* prow = a.Pt + a.offs[gslot] + static_cast<size_t>(rowko) * nb;
                     const double inv = 1.0 / mxx;
                     if (a.psplit) {
                         // the row's nb floats of space hold P~ = hi + lo as BF16
@@ -640,7 +670,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                         unsigned short* hrow = reinterpret_cast<unsigned short*>(prow);
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            const int k = r * P + q - s0;
+                            const int k = r * P + qo - s0;
                             if (k >= 0) {
                                 const float v = static_cast<float>(G[r] * inv);
                                 const __bf16 h = static_cast<__bf16>(v);
@@ -652,7 +682,7 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
                     } else {
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            const int k = r * P + q - s0;
+                            const int k = r * P + qo - s0;
                             if (k >= 0) prow[k] = static_cast<float>(G[r] * inv);
                         }
                     }
