@@ -72,7 +72,10 @@ __device__ __forceinline__ double dpp_f64(double v) {
 
 // Column parameters are read with wave-uniform addresses from memory the
 // kernel never writes; the constant address space lets them come in through
-// scalar loads into SGPRs.
+// scalar loads into SGPRs.  Each step loads its own column's: a copy carried
+// over from the step before (a prefetch) is kept in VGPRs by the compiler and
+// costs seven moves per step, more than the load's latency, which the other
+// waves of the SIMD cover.
 typedef const __attribute__((address_space(4))) ColPar* ConstColPar;
 
 __device__ __forceinline__ ColPar load_colpar(const ColPar* p, int i) {
@@ -179,7 +182,6 @@ struct Rec {
     double lf;         // c0 r^((R-1) P + q - s0): the factor of the lane's row in the top slot
     double srep;       // LDS-table variant: the lane's finished rows' sum of X_k Cum(jrep_k) / total
     int nres;          // rescales so far
-    ColPar cnext;      // prefetched parameters of the next column
 };
 
 struct StepEnv {
@@ -303,8 +305,7 @@ __device__ __forceinline__ void column_block(Rec<R>& st, const StepEnv& e) {
         if (f < 0) continue;
         ColPar cc{};
         if constexpr (!GIVEN) {
-            cc = st.cnext;
-            st.cnext = load_colpar(e.colpar, min(f + 1, nb - 1));      // prefetch the next column
+            cc = load_colpar(e.colpar, f);
         }
         double Xf = 1.0;
         if (f > 0) {
@@ -610,8 +611,6 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
         if constexpr (GIVEN) {
             env.Ap = a.A + static_cast<size_t>(cellc) * nb * nb;
             env.cp = a.cool + static_cast<size_t>(cellc) * nb;
-        } else {
-            st.cnext = load_colpar(gv.colpar, 0);
         }
         all_columns<P, R, KG, GIVEN, LDSCUM>(st, env, std::make_integer_sequence<int, R>{});
         double* G = st.G;
