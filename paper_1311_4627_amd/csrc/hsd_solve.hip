@@ -30,11 +30,11 @@
 // diagonal holds H(k) = G(k) / (c0 r^k), updated by H(k) += 2^(...) X_f, and the
 // lane's share of the suffix sum, sum over its slots s of c0 r^(s P + q - s0) H,
 // is evaluated by Horner's rule in r^-P from the lowest slot up and scaled once
-// by the lane's factor c0 r^((R-1) P + q - s0).  The exponent and exp2 are single precision; the
-// product with X_f and every sum are double precision.  Row slots are
-// processed in groups of four with straight-line bodies, so the LDS reads of a
-// group overlap; a group wholly outside the column's grid-resident rows kb..ke
-// skips its rates.
+// by the lane's factor c0 r^((R-1) P + q - s0).  The exponent and exp2 are
+// single precision; the product with X_f and every sum are double precision.
+// Row slots are processed in groups of KG (2 or 4, chosen per bin class by the
+// autotuner) with straight-line bodies, so the LDS reads of a group overlap; a
+// group wholly outside the column's grid-resident rows kb..ke skips its rates.
 //
 // Continuous (intrabin) heating of row f+1 from column f adds
 // X_f Cum(jstar_f) / (E_(f+1) - E_f), Cum_j being the absorbed power of photons at
