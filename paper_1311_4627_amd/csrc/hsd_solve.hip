@@ -422,12 +422,13 @@ struct KArgs {
 // (The body stays in the kernel itself: moved into a function that takes the
 // kernel arguments by reference, it costs 10-20 more VGPRs.)
 //
-// Occupancy: the kernel is held to 128 VGPRs, 4 waves per SIMD.  The column
-// loops fit in that budget without spills; the compiler moves a few dozen
-// values of the setup and the output epilogue (run once per pair) to scratch,
-// which costs far less than the fourth wave gains in hiding the LDS and exp2
-// latencies of the rate groups (the ~1024-bin class runs 10% faster than at
-// 3 waves, the ~256-bin class 14%).
+// Occupancy: the kernel is held to 128 VGPRs, 4 waves per SIMD, where the
+// fourth wave hides the LDS and exp2 latencies of the rate groups (the
+// ~1024-bin class runs 10% faster than at 3 waves, the ~256-bin class 14%).
+// The ordinary-grid kernels fit that budget with no scratch (the epilogue's
+// inputs are made opaque after the recursion, below, so the compiler does not
+// hoist their address arithmetic above it and park the results in scratch);
+// the persistent variants keep a few dozen values in scratch, once per item.
 template <int P, int R, int KG, int WAVES, bool GIVEN, bool LDSCUM, bool PERSIST>
 __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(4))) k_solve(KArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
