@@ -353,6 +353,40 @@ def test_maximum_sizes_match_oracle(hsd):
         assert e < J_TOL
 
 
+def test_wide_enthalpy_range_matches_oracle(hsd):
+    # Enthalpy grids spanning ten decades (1e-6 .. 2e4 eV), so the rows' rate
+    # factor c0 r^k, which the solver applies once per lane and step (Horner
+    # sums in r^-P), ranges over as many; one grain with 528 bins (15.5 of the
+    # 32 slots of its layout lie below row 0) and one with 1024.  Faint,
+    # attenuated fields and bright ones: j and the representable absorbed
+    # power against the oracle.
+    lam = synth.wavelength_grid_cm(500)
+    ev = oracle.EV
+    grains = [synth.make_grain("carbonaceous", 8e-8, lam, n_bins=528, E_range_erg=(1e-6 * ev, 2e4 * ev)),
+              synth.make_grain("silicate", 30e-8, lam, n_bins=1024, E_range_erg=(1e-6 * ev, 2e4 * ev))]
+    ctx = hsd.Context(lam)
+    gids = [ctx.add_grain(g) for g in grains]
+    faint = make_fields(lam, synth.FieldRecipe(seed=91, U_range=(0.1, 1.0), jitter=0.0, tau_V_range=(5.0, 20.0)), 2)
+    bright = make_fields(lam, synth.FieldRecipe(seed=92, U_range=(1e3, 1e5), jitter=0.3, tau_V_range=None), 2)
+    u = np.concatenate([faint, bright])
+    ud = torch.tensor(u, device="cuda")
+    j = torch.empty((4, 2, 500), dtype=torch.float32, device="cuda")
+    diag = torch.empty((4, 2, 4), dtype=torch.float32, device="cuda")
+    ctx.hsd_solve(ud, gids, j, diag)
+    ctx.hsd_sync()
+    jj = j.cpu().numpy().astype(np.float64)
+    dd = diag.cpu().numpy().astype(np.float64)
+    for gi, g in enumerate(grains):
+        for c in range(4):
+            _, jr, d = oracle.solve_pair(u[c], g, lam, with_diag=True)
+            e = j_rel_err(jj[c, gi], jr)
+            ea = abs(dd[c, gi, 2] / d["A_rep"] - 1.0)
+            print(f"wide E range: grain {gi} ({g.n_bins} bins) cell {c}: j rel err {e:.2e}, A_rep rel err {ea:.2e}",
+                  flush=True)
+            assert e < J_TOL
+            assert ea < 1e-4
+
+
 def test_size_convolution_matches_oracle(hsd):
     # four radii of the batched workload, three cells: the library's solve and
     # convolution against the oracle's spectra and its weighted sum
