@@ -204,6 +204,24 @@ hsd_status hsd_table_eval(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, in
                           const int32_t* grain_ids_host, const double* u_ref_dev, int32_t n_nodes, double log10U_lo,
                           double log10U_hi, const float* table_dev, float* j_dev, void* stream);
 
+/* The energy budget of a table, as the reference of the surrogate's
+ * HSD_CHECK_TABLE check: per grain, the emitted power per unit absorbed power
+ * of each node spectrum, rho_k = 4 pi int 2^(y_k) dlambda (trapezoid on the
+ * grid; FP64), and the reference field's energy int u_ref dlambda.  A pair's
+ * budget is then A rho(t), rho interpolated linearly in the cell's node-grid
+ * coordinate t (its log10 U, as hsd_table_eval looks it up): the power the
+ * plain model's solves of the reference shape emit at the cell's field
+ * strength, from plain solves alone and none of the network's outputs (the
+ * energy balance of eq:steady-state as the discrete model realises it).
+ *   table_dev, u_ref_dev, n_nodes, log10U_lo/hi: a table as hsd_table_build
+ *   wrote it for grain_ids_host (n_grains distinct registered grains).
+ * Replaces any budget set before; the check then covers these grains only.
+ * Reads the table on `stream` and waits for it; the table may be freed
+ * afterwards. */
+hsd_status hsd_set_energy_budget(hsd_ctx* ctx, int32_t n_grains, const int32_t* grain_ids_host,
+                                 const double* u_ref_dev, int32_t n_nodes, double log10U_lo, double log10U_hi,
+                                 const float* table_dev, void* stream);
+
 /* Measurement aid: the number of single-precision exponentials per second
  * the context's device issues (one per heating rate in the solver; the
  * benchmark quotes it beside the solver's roofline).  Runs a calibration
@@ -475,9 +493,16 @@ hsd_status hsd_surrogate_load(hsd_sur* sur, const char* path);
  *   HSD_CHECK_MODEL     flag it when |E / (rho A) - 1| > tol, rho = 10^y_L
  *                       the network's prediction of the plain model's own
  *                       ratio E / A: the spectrum must carry the power the
- *                       discrete model absorbs. */
+ *                       discrete model absorbs;
+ *   HSD_CHECK_TABLE     flag it when |E / B - 1| > tol, B the table budget
+ *                       of hsd_set_energy_budget (the plain model's emitted
+ *                       power at the cell's field strength, for the
+ *                       reference field shape): a reference that does not
+ *                       come from the network.  Every grain of the batch
+ *                       needs a budget (else HSD_ERR_STATE). */
 #define HSD_CHECK_ABSORBED 0
 #define HSD_CHECK_MODEL 1
+#define HSD_CHECK_TABLE 2
 /* Surrogate spectra of every (cell, grain) pair: j_dev as in hsd_solve;
  * diag_dev (optional) = (A, 4 pi int j dlambda, rho A, flags) with flags
  * bit 3 set (value from the surrogate) and bit 4 set where the
@@ -488,10 +513,11 @@ hsd_status hsd_sur_predict(hsd_sur* sur, int32_t n_cells, const double* u_dev, i
 /* The surrogate with the plain solve as fallback: every pair is first
  * evaluated by the network surs_host[g] of its grain (one network may serve
  * several grains); a pair that fails the energy check `check`
- * (HSD_CHECK_ABSORBED or HSD_CHECK_MODEL, relative tolerance tol; the
- * energy balance of eq:steady-state) is re-solved by the plain path, in
- * place.  j_dev and diag_dev as in hsd_solve; surrogate pairs carry diag
- * flag bit 3 and entry 2 = the power the check compares with (A or rho A),
+ * (HSD_CHECK_ABSORBED, HSD_CHECK_MODEL or HSD_CHECK_TABLE, relative
+ * tolerance tol; the energy balance of eq:steady-state) is re-solved by the
+ * plain path, in place.  j_dev and diag_dev as in hsd_solve; surrogate pairs
+ * carry diag flag bit 3 and entry 2 = the power the check compares with (A,
+ * rho A or B),
  * re-solved pairs carry the plain solve's diagnostics.  *n_fallback_host
  * receives the number of re-solved pairs.  Waits for the stream once (to
  * size the fallback). */

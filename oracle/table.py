@@ -12,7 +12,9 @@ energy relative to the reference, U = int u dlambda / int u_ref dlambda (both
 trapezoid on the grid, clamped to the node range), and gets
 A(u) 2^((1 - w) y_k + w y_(k+1)) with k, w its position on the node grid; a
 node value without emission (y = -inf) gives none unless the weight puts the
-whole value on the other node.
+whole value on the other node.  The table's energy budget (the reference of
+the surrogate's table check) is each node spectrum's emitted power per unit
+absorbed power, interpolated linearly at a field's node coordinate.
 """
 
 from __future__ import annotations
@@ -45,16 +47,37 @@ def build_table(grain, lam: np.ndarray, u_ref: np.ndarray, lo: float, hi: float,
     return y
 
 
+def node_coordinate(u: np.ndarray, u_ref: np.ndarray, lam: np.ndarray, lo: float, hi: float, K: int):
+    """Where field u sits on the node grid: t = (log10 U - lo) / step clamped
+    to [0, K - 1], U = int u dlambda / int u_ref dlambda; returns the lower
+    node k (at most K - 2) and the weight w = t - k of the upper one."""
+    E = float(np.trapezoid(u, lam))
+    Eref = float(np.trapezoid(u_ref, lam))
+    t = (math.log10(E / Eref) - lo) / ((hi - lo) / (K - 1)) if E > 0.0 and Eref > 0.0 else 0.0
+    t = min(max(t, 0.0), K - 1.0)
+    k = min(int(math.floor(t)), K - 2)
+    return k, t - k
+
+
+def node_ratios(y: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """The energy budget of a table: for each node, the emitted power of its
+    spectrum per unit absorbed power, 4 pi int 2^(y_k) dlambda (trapezoid on
+    the grid; no emission where y_k = -inf)."""
+    return 4.0 * math.pi * np.trapezoid(np.where(np.isfinite(y), np.exp2(y), 0.0), lam, axis=-1)
+
+
+def budget_ratio(rho: np.ndarray, lo: float, hi: float, u: np.ndarray, u_ref: np.ndarray, lam: np.ndarray) -> float:
+    """The budget's emitted / absorbed power for field u: the node ratios rho
+    interpolated linearly at u's node coordinate."""
+    k, w = node_coordinate(u, u_ref, lam, lo, hi, rho.shape[0])
+    return float((1.0 - w) * rho[k] + w * rho[k + 1])
+
+
 def lookup(y: np.ndarray, lo: float, hi: float, u: np.ndarray, u_ref: np.ndarray, cabs: np.ndarray,
            lam: np.ndarray) -> np.ndarray:
     """The table's spectrum for field u."""
     K = y.shape[0]
-    E = float(np.trapezoid(u, lam))
-    Eref = float(np.trapezoid(u_ref, lam))
-    t = (math.log10(E / Eref) - lo) / ((hi - lo) / (K - 1)) if E > 0.0 else 0.0
-    t = min(max(t, 0.0), K - 1.0)
-    k = min(int(math.floor(t)), K - 2)
-    w = t - k
+    k, w = node_coordinate(u, u_ref, lam, lo, hi, K)
     if w == 0.0:
         yy = y[k]
     elif w == 1.0:

@@ -82,11 +82,24 @@ struct TableWork {
     const double** cabs = nullptr; size_t cabs_cap = 0;   // C_abs table of each listed grain
 };
 
+// Energy budget of the HSD_CHECK_TABLE check (hsd_set_energy_budget).
+struct Budget {
+    std::vector<int32_t> ids;                            // grains with a budget: row r of rho is ids[r]'s
+    int K = 0;                                           // nodes (0: no budget set)
+    double lo = 0.0, step = 0.0;                         // node grid in log10 U
+    double* rho = nullptr;        size_t rho_cap = 0;    // [rows][K] emitted / absorbed power of the node spectra
+    double* eref = nullptr;       size_t eref_cap = 0;   // [1] the reference field's energy
+    int* row = nullptr;           size_t row_cap = 0;    // per slot of a call: its row of rho
+    double* energy = nullptr;     size_t energy_cap = 0; // per cell of a call: the field's energy
+    double* t = nullptr;          size_t t_cap = 0;      // per cell of a call: node-grid coordinate
+};
+
 struct hsd_ctx {
     Ctx c;
     Batch batch;     // host description of the last eager solve
     SurWork sw;
     TableWork tw;
+    Budget bud;
 };
 
 struct hsd_sur {
@@ -478,6 +491,8 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(w.cellmap); hipFree(w.pairs);
     TableWork& tw = ctx->tw;
     hipFree(tw.u); hipFree(tw.j); hipFree(tw.A); hipFree(tw.energy); hipFree(tw.cabs);
+    Budget& bd = ctx->bud;
+    hipFree(bd.rho); hipFree(bd.eref); hipFree(bd.row); hipFree(bd.energy); hipFree(bd.t);
     hipFree(c.Pt);
     hipFree(c.pscale);
     hipFree(c.diag_tmp);
@@ -1140,6 +1155,33 @@ hsd_status hsd_table_eval(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, in
     return HSD_OK;
 }
 
+hsd_status hsd_set_energy_budget(hsd_ctx* ctx, int32_t n_grains, const int32_t* grain_ids_host,
+                                 const double* u_ref_dev, int32_t n_nodes, double log10U_lo, double log10U_hi,
+                                 const float* table_dev, void* stream) {
+    if (!ctx) return HSD_ERR_INVALID_ARG;
+    hsd_status st = table_args(ctx, n_grains, grain_ids_host, n_nodes, log10U_lo, log10U_hi);
+    if (st != HSD_OK) return st;
+    if (!u_ref_dev || !table_dev) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
+    for (int a = 0; a < n_grains; ++a)
+        for (int b = 0; b < a; ++b)
+            if (grain_ids_host[a] == grain_ids_host[b]) return fail(ctx, HSD_ERR_INVALID_ARG, "repeated grain id");
+    Ctx& c = ctx->c;
+    Budget& bd = ctx->bud;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HSD_HIP(ctx, hipSetDevice(c.device));
+    bd.K = 0;                                   // no budget until this one is complete
+    HSD_HIP(ctx, grow(bd.rho, bd.rho_cap, static_cast<size_t>(n_grains) * n_nodes));
+    HSD_HIP(ctx, grow(bd.eref, bd.eref_cap, 1));
+    HSD_HIP(ctx, hsd::launch_budget_nodes(table_dev, n_nodes, n_grains, c.L, c.lam, bd.rho, s));
+    HSD_HIP(ctx, hsd::launch_cell_energies(u_ref_dev, c.lam, 1, c.L, 0, nullptr, bd.eref, nullptr, s));
+    HSD_HIP(ctx, hipStreamSynchronize(s));
+    bd.ids.assign(grain_ids_host, grain_ids_host + n_grains);
+    bd.lo = log10U_lo;
+    bd.step = (log10U_hi - log10U_lo) / (n_nodes - 1);
+    bd.K = n_nodes;
+    return HSD_OK;
+}
+
 hsd_status hsd_measure_exp2(hsd_ctx* ctx, double* per_second_host) {
     if (!ctx) return HSD_ERR_INVALID_ARG;
     if (!per_second_host) return fail(ctx, HSD_ERR_INVALID_ARG, "null output");
@@ -1463,9 +1505,13 @@ hsd_status sur_run(hsd_ctx* ctx, hsd::Sur& sur, int32_t n_cells, const double* u
                                     s));
         HSD_HIP(ctx, hsd::sur_infer_rows(sur, static_cast<int>(n), w.xb, w.A, r0, n_sel, n_grains, w.sel, j, w.emit,
                                          w.rho, w.h0, w.h1, s));
-        if (diag)
-            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, check == HSD_CHECK_MODEL ? w.rho : nullptr, r0, n,
-                                       n_sel, n_grains, w.sel, tol, diag, w.cnt, list, list_cap, s));
+        if (diag) {
+            const Budget& bd = ctx->bud;
+            const bool tab = check == HSD_CHECK_TABLE;
+            HSD_HIP(ctx, hsd::sur_diag(w.A, w.emit, n_parts, check == HSD_CHECK_MODEL ? w.rho : nullptr,
+                                       tab ? bd.rho : nullptr, bd.row, bd.K, bd.t, r0, n, n_sel, n_grains, w.sel, tol,
+                                       diag, w.cnt, list, list_cap, s));
+        }
     }
     return HSD_OK;
 }
@@ -1692,16 +1738,35 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     if (!u_dev || !grain_ids_host || !surs_host || !j_dev || !diag_dev)
         return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
     if (!(tol >= 0.f)) return fail(ctx, HSD_ERR_INVALID_ARG, "tol must be >= 0");
-    if (check != HSD_CHECK_ABSORBED && check != HSD_CHECK_MODEL)
-        return fail(ctx, HSD_ERR_INVALID_ARG, "check must be HSD_CHECK_ABSORBED or HSD_CHECK_MODEL");
+    if (check != HSD_CHECK_ABSORBED && check != HSD_CHECK_MODEL && check != HSD_CHECK_TABLE)
+        return fail(ctx, HSD_ERR_INVALID_ARG, "check must be HSD_CHECK_ABSORBED, HSD_CHECK_MODEL or HSD_CHECK_TABLE");
     for (int g = 0; g < n_grains; ++g) {
         if (!grain_ok(ctx, grain_ids_host[g])) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown grain id");
         if (!surs_host[g] || surs_host[g]->ctx != ctx) return fail(ctx, HSD_ERR_INVALID_ARG, "missing or foreign surrogate");
+    }
+    Budget& bd = ctx->bud;
+    std::vector<int> rows;
+    if (check == HSD_CHECK_TABLE) {
+        if (bd.K == 0) return fail(ctx, HSD_ERR_STATE, "HSD_CHECK_TABLE needs hsd_set_energy_budget first");
+        for (int g = 0; g < n_grains; ++g) {
+            const auto it = std::find(bd.ids.begin(), bd.ids.end(), grain_ids_host[g]);
+            if (it == bd.ids.end()) return fail(ctx, HSD_ERR_STATE, "a grain of the batch has no energy budget");
+            rows.push_back(static_cast<int>(it - bd.ids.begin()));
+        }
     }
     Ctx& c = ctx->c;
     SurWork& w = ctx->sw;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     HSD_HIP(ctx, hipSetDevice(c.device));
+    if (check == HSD_CHECK_TABLE) {
+        // each cell's position on the budget's node grid, each slot's row of it
+        HSD_HIP(ctx, grow(bd.row, bd.row_cap, static_cast<size_t>(n_grains)));
+        HSD_HIP(ctx, grow(bd.energy, bd.energy_cap, static_cast<size_t>(n_cells)));
+        HSD_HIP(ctx, grow(bd.t, bd.t_cap, static_cast<size_t>(n_cells)));
+        HSD_HIP(ctx, hipMemcpyAsync(bd.row, rows.data(), sizeof(int) * n_grains, hipMemcpyHostToDevice, s));
+        HSD_HIP(ctx, hsd::launch_cell_energies(u_dev, c.lam, n_cells, c.L, 0, nullptr, bd.energy, nullptr, s));
+        HSD_HIP(ctx, hsd::launch_node_coord(bd.energy, bd.eref, n_cells, bd.lo, bd.step, bd.K, bd.t, s));
+    }
     HSD_HIP(ctx, grow(w.bands, w.bands_cap, static_cast<size_t>(n_cells) * 32));
     HSD_HIP(ctx, grow(w.cnt, w.cnt_cap, static_cast<size_t>(n_grains) + 1));
     HSD_HIP(ctx, hipMemsetAsync(w.cnt, 0, sizeof(unsigned) * (n_grains + 1), s));

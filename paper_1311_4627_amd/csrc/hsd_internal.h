@@ -194,6 +194,12 @@ hipError_t launch_node_fields(const double* u_ref, double lo, double step, int n
 hipError_t launch_cell_energies(const double* u, const double* lam, int n_cells, int L, int G,
                                 const double* const* cabs, double* energy, double* A, hipStream_t s);
 hipError_t launch_table_logs(const float* j, const double* A, int n_nodes, int G, int L, float* table, hipStream_t s);
+// Energy budget of a table (rho [G][n_nodes]: 4 pi int 2^y dlambda per node
+// spectrum) and the cells' node-grid coordinates, for the HSD_CHECK_TABLE check.
+hipError_t launch_budget_nodes(const float* table, int n_nodes, int G, int L, const double* lam, double* rho,
+                               hipStream_t s);
+hipError_t launch_node_coord(const double* energy, const double* ref_energy, int n_cells, double lo, double step,
+                             int n_nodes, double* t, hipStream_t s);
 hipError_t launch_table_eval(const double* energy, const double* ref_energy, const double* A, const float* table,
                              int n_nodes, double lo, double step, int n_cells, int G, int L, float* j, hipStream_t s);
 // Exponentials per second that the device issues (hsd_measure.hip).
@@ -279,8 +285,11 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
                           int n_slots, const int* sel, float* j, float* emit, float* rho, unsigned short* h0,
                           unsigned short* h1, hipStream_t st);
 int sur_emit_parts(int n_out);
-hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
-                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
+// rho: the network's ratios (HSD_CHECK_MODEL) or null; bud: the table budget
+// [rows][bud_K] with bud_row per slot and cell_t per cell (HSD_CHECK_TABLE) or null.
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, const double* bud,
+                    const int* bud_row, int bud_K, const double* cell_t, long long row0, long long n, int n_sel,
+                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
                     long long list_cap, hipStream_t st);
 hipError_t sur_fb_scatter_list(const long long* list, long long n, int n_slots, const int* seg_off, unsigned* cursor,
                                int* cellmap, long long* pairs, hipStream_t st);

@@ -640,9 +640,13 @@ hipError_t gemm_splitk(GemmArgs g, int nz, float* work, hipStream_t s) {
 // in slice order (a fixed order, so the check decides the same way on every
 // run).  Row r of the chunk is selection entry off0 + r of cells from cell0 on
 // (n + n_sel < 2^31).
+// The reference power of the check: A (rho and bud null), rho A (the
+// network's predicted ratio), or the table's budget: A times the slot's node
+// ratios bud[row][k] interpolated linearly at the cell's node coordinate t.
 __global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* emit, int n_parts, const float* rho,
-                                                  long long cell0, int off0, int n, int n_sel, int n_slots,
-                                                  const int* sel, float tol, float* diag, unsigned* cnt,
+                                                  const double* bud, const int* bud_row, int bud_K,
+                                                  const double* cell_t, long long cell0, int off0, int n, int n_sel,
+                                                  int n_slots, const int* sel, float tol, float* diag, unsigned* cnt,
                                                   long long* list, long long list_cap) {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
@@ -650,7 +654,14 @@ __global__ void __launch_bounds__(256) k_sur_diag(const double* A, const float* 
     const long long cell = cell0 + rs / static_cast<unsigned>(n_sel);
     const int slot = sel[rs % static_cast<unsigned>(n_sel)];
     const double a = A[r];
-    const double ref = rho ? a * static_cast<double>(rho[r]) : a;
+    double ref = rho ? a * static_cast<double>(rho[r]) : a;
+    if (bud) {
+        const double t = cell_t[cell];
+        const int k = min(static_cast<int>(t), bud_K - 2);
+        const double w = t - k;
+        const double* br = bud + static_cast<long long>(bud_row[slot]) * bud_K;
+        ref = a * ((1.0 - w) * br[k] + w * br[k + 1]);
+    }
     float e = 0.f;
     for (int x = 0; x < n_parts; ++x) e += emit[static_cast<long long>(x) * n + r];
     const bool bad = !(fabs(static_cast<double>(e) / ref - 1.0) <= tol);
@@ -1381,15 +1392,17 @@ hipError_t sur_infer_rows(Sur& s, int M, const unsigned short* xb, const double*
 
 int sur_emit_parts(int n_out) { return (n_out + 127) / 128; }
 
-hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, long long row0, long long n,
-                    int n_sel, int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
+hipError_t sur_diag(const double* A, const float* emit, int n_parts, const float* rho, const double* bud,
+                    const int* bud_row, int bud_K, const double* cell_t, long long row0, long long n, int n_sel,
+                    int n_slots, const int* sel, float tol, float* diag, unsigned* cnt, long long* list,
                     long long list_cap, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (n + n_sel >= (1LL << 31)) return hipErrorInvalidValue;
     const long long cell0 = row0 / n_sel;
     const int off0 = static_cast<int>(row0 - cell0 * n_sel);
     hipLaunchKernelGGL(k_sur_diag, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, A, emit, n_parts,
-                       rho, cell0, off0, static_cast<int>(n), n_sel, n_slots, sel, tol, diag, cnt, list, list_cap);
+                       rho, bud, bud_row, bud_K, cell_t, cell0, off0, static_cast<int>(n), n_sel, n_slots, sel, tol,
+                       diag, cnt, list, list_cap);
     return hipGetLastError();
 }
 

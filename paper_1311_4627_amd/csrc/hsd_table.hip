@@ -108,6 +108,42 @@ __global__ void __launch_bounds__(256) k_table_eval(const double* energy, const 
     }
 }
 
+// Energy budget of the table (the reference of the HSD_CHECK_TABLE check):
+// for each grain g and node k, the node spectrum's emitted power per unit
+// absorbed power, rho[g][k] = 4 pi int 2^(y_k) dlambda (trapezoid on the grid,
+// no emission where y_k holds none).  One wave per (g, k); FP64 sums in a
+// fixed order (lane strides, then a shuffle tree).
+__global__ void __launch_bounds__(256) k_budget_nodes(const float* table, int rows, int L, const double* lam,
+                                                      double* rho) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= rows) return;
+    const int lane = threadIdx.x & 63;
+    const float* y = table + static_cast<long long>(row) * L;
+    double s = 0.0;
+    for (int l = lane; l < L; l += 64) {
+        double w = 0.0;
+        if (l > 0) w += 0.5 * (lam[l] - lam[l - 1]);
+        if (l + 1 < L) w += 0.5 * (lam[l + 1] - lam[l]);
+        const float v = y[l];
+        if (v > kNoEmission) s += w * exp2(static_cast<double>(v));
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) rho[row] = 4.0 * M_PI * s;
+}
+
+// Each cell's position on the table's node grid, t = (log10(E / E_ref) - lo)
+// / step clamped to [0, n_nodes - 1], E the field's energy (the lookup of
+// k_table_eval).
+__global__ void __launch_bounds__(256) k_node_coord(const double* energy, const double* ref_energy, int n_cells,
+                                                    double lo, double step, int n_nodes, double* t) {
+    const int cell = blockIdx.x * 256 + threadIdx.x;
+    if (cell >= n_cells) return;
+    const double e = energy[cell], eref = *ref_energy;
+    const double x = (e > 0.0 && eref > 0.0) ? (log10(e / eref) - lo) / step : 0.0;
+    t[cell] = fmin(fmax(x, 0.0), static_cast<double>(n_nodes - 1));
+}
+
 }  // namespace
 
 hipError_t launch_node_fields(const double* u_ref, double lo, double step, int n_nodes, int L, double* u_out,
@@ -129,6 +165,22 @@ hipError_t launch_table_logs(const float* j, const double* A, int n_nodes, int G
     const long long n = static_cast<long long>(n_nodes) * G * L;
     hipLaunchKernelGGL(k_table_logs, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, j, A, n_nodes, G,
                        L, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_budget_nodes(const float* table, int n_nodes, int G, int L, const double* lam, double* rho,
+                               hipStream_t s) {
+    const int rows = n_nodes * G;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_budget_nodes, dim3((rows + 3) / 4), dim3(256), 0, s, table, rows, L, lam, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_coord(const double* energy, const double* ref_energy, int n_cells, double lo, double step,
+                             int n_nodes, double* t, hipStream_t s) {
+    if (n_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_coord, dim3((n_cells + 255) / 256), dim3(256), 0, s, energy, ref_energy, n_cells, lo,
+                       step, n_nodes, t);
     return hipGetLastError();
 }
 

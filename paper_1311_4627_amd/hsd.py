@@ -34,7 +34,7 @@ SYMBOLS = (
     "hsd_sur_set_norm", "hsd_sur_get_norm", "hsd_sur_features", "hsd_sur_targets", "hsd_sur_fit_norm",
     "hsd_sur_loss_grad", "hsd_sur_train", "hsd_sur_predict", "hsd_solve_surrogate", "hsd_size_convolve",
     "hsd_surrogate_save", "hsd_surrogate_load", "hsd_solve_noalloc", "hsd_sur_set_loss", "hsd_measure_exp2",
-    "hsd_table_build", "hsd_table_eval", "hsd_sur_set_train_graph",
+    "hsd_table_build", "hsd_table_eval", "hsd_sur_set_train_graph", "hsd_set_energy_budget",
 )
 
 N_CLASSES = 4
@@ -45,6 +45,7 @@ PLAN_TIMING = 1
 PLAN_CONCURRENT = 2
 CHECK_ABSORBED = 0      # surrogate energy check against the absorbed power A
 CHECK_MODEL = 1         # ... against rho A, rho the predicted energy ratio of the plain model
+CHECK_TABLE = 2         # ... against the table budget of hsd_set_energy_budget
 SAVE_WEIGHTS_ONLY = 1   # checkpoint without the Adam moments
 
 
@@ -163,6 +164,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.hsd_table_eval.argtypes = [vp, i32, vp, i32, ctypes.POINTER(i32), vp, i32, ctypes.c_double, ctypes.c_double,
                                    vp, vp, vp]
     lib.hsd_table_eval.restype = ctypes.c_int
+    lib.hsd_set_energy_budget.argtypes = [vp, i32, ctypes.POINTER(i32), vp, i32, ctypes.c_double, ctypes.c_double,
+                                          vp, vp]
+    lib.hsd_set_energy_budget.restype = ctypes.c_int
     lib.hsd_measure_exp2.argtypes = [vp, dp]
     lib.hsd_measure_exp2.restype = ctypes.c_int
     lib.hsd_sur_set_loss.argtypes = [vp, ctypes.c_float]
@@ -491,6 +495,19 @@ class Context:
                                       j.data_ptr(), _stream_ptr(stream))
         if st != HSD_OK:
             self._raise(st, "hsd_table_eval")
+
+    def hsd_set_energy_budget(self, grain_ids: Sequence[int], u_ref, log10U_lo: float, log10U_hi: float, table,
+                              stream=None):
+        import torch
+        ids = np.ascontiguousarray(grain_ids, dtype=np.int32)
+        G, K = int(ids.shape[0]), int(table.shape[1])
+        _check_dev(u_ref, torch.float64, (self.L,), "u_ref")
+        _check_dev(table, torch.float32, (G, K, self.L), "table")
+        st = self._lib.hsd_set_energy_budget(self._h, G, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             u_ref.data_ptr(), K, float(log10U_lo), float(log10U_hi),
+                                             table.data_ptr(), _stream_ptr(stream))
+        if st != HSD_OK:
+            self._raise(st, "hsd_set_energy_budget")
 
     def hsd_measure_exp2(self) -> float:
         r = ctypes.c_double()

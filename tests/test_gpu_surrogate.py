@@ -10,8 +10,9 @@ reference MLP (oracle/mlp.py), the plain solve and the FP64 oracle.
   that of an emissivity table indexed by the field strength alone (the cheap
   method the surrogate replaces);
 * the fallback: pairs failing the 1% energy check are re-solved by the plain
-  path bit for bit, the others pass the check; tol = 0 reproduces the plain
-  solve exactly.
+  path bit for bit, the others pass the check (against the network's rho A,
+  the absorbed power A, or a table's energy budget); tol = 0 reproduces the
+  plain solve exactly.
 """
 
 import math
@@ -230,6 +231,24 @@ def test_fallback_is_the_plain_solve(hsd, small):
     assert nfa == int(np.sum(~surp))
     assert np.all(np.abs(dd[surp][:, 1] / dd[surp][:, 0] - 1) <= 0.01 + 1e-6)
     assert np.array_equal(dd[surp][:, 2], dd[surp][:, 0])
+    fb = torch.tensor(~surp, device="cuda")
+    assert torch.equal(j[fb], je[fb]) and torch.equal(diag[fb], de[fb])
+    # the check against a table's energy budget (the table built by the plain
+    # path for these grains): B in diag entry 2, the same fallback rule
+    from synth.fields import FieldRecipe
+    u_ref = torch.tensor(make_fields(w.lam_cm, FieldRecipe(0, (1.0, 1.0), 0.0, None), 1)[0], device="cuda")
+    table = torch.empty((G, 25, w.n_lambda), dtype=torch.float32, device="cuda")
+    ctx.hsd_table_build(ids, u_ref, -2.0, 6.0, table)
+    ctx.hsd_set_energy_budget(ids, u_ref, -2.0, 6.0, table)
+    del table
+    nft = ctx.hsd_solve_surrogate(d["ud"], ids, [sur] * G, j, diag, tol=0.01, check=hsd.CHECK_TABLE)
+    ctx.hsd_sync()
+    dd = diag.cpu().numpy()
+    surp = (dd[..., 3].astype(np.int32) & 8) != 0
+    print(f"fallback (check against the table budget) {nft} of {n_cells * G} pairs", flush=True)
+    assert nft == int(np.sum(~surp))
+    assert np.all(np.abs(dd[surp][:, 1] / dd[surp][:, 2] - 1) <= 0.01 + 1e-6)
+    assert np.all(np.isfinite(dd[surp][:, 2])) and np.all(dd[surp][:, 2] > 0)
     fb = torch.tensor(~surp, device="cuda")
     assert torch.equal(j[fb], je[fb]) and torch.equal(diag[fb], de[fb])
     # tol = 0: every pair falls back and the output is the plain solve

@@ -340,3 +340,43 @@ def test_table_method_twin():
     assert got[7] == 0.0 and got[8] > 0.0
     got = otab.lookup(yz, lo, hi, 100.0 * u_ref, u_ref, g.cabs_cm2, lam)    # exactly node 3 (w = 0)
     assert got[7] > 0.0
+    # the table's energy budget: node k's ratio times its absorbed power is
+    # the emitted power of that node's solve, as the oracle's diagnostics
+    # integrate it
+    rho = otab.node_ratios(y, lam)
+    for k in (0, 2, 4):
+        u = 10.0 ** x[k] * u_ref
+        _, _, d = oracle.solve_pair(u, g, lam, with_diag=True)
+        A = otab.absorbed_power(u, g.cabs_cm2, lam)
+        assert abs(rho[k] * A / d["emitted"] - 1.0) < 1e-12
+        # and the interpolated budget at a node is that node's ratio
+        assert otab.budget_ratio(rho, lo, hi, u, u_ref, lam) == pytest.approx(rho[k], rel=1e-14)
+
+
+def test_table_budget_closed_forms():
+    # node_ratios: 4 pi int 2^y dlambda, exact for spectra linear in lambda
+    # (the trapezoid rule), a node value without emission contributing nothing;
+    # budget_ratio: linear in the node coordinate, clamped at both ends
+    from oracle import table as otab
+    lam = synth.wavelength_grid_cm(300)
+    l0, l1 = lam[0], lam[-1]
+    K = 4
+    a = np.array([1.0, 2.0, 0.5, 3.0])
+    b = np.array([0.0, 1e3, -4.0, 5e2])           # a + b lambda > 0 on the grid
+    y = np.log2(a[:, None] + b[:, None] * lam[None, :])
+    rho = otab.node_ratios(y, lam)
+    exact = 4 * math.pi * (a * (l1 - l0) + 0.5 * b * (l1 ** 2 - l0 ** 2))
+    assert np.allclose(rho, exact, rtol=1e-12)
+    yz = np.zeros((1, lam.shape[0]))
+    yz[0, 5] = -np.inf                    # j / A = 1 except at node 5
+    w5 = 0.5 * (lam[6] - lam[4])
+    assert otab.node_ratios(yz, lam)[0] == pytest.approx(4 * math.pi * (l1 - l0 - w5), rel=1e-13)
+    lo, hi = 0.0, 3.0
+    u_ref = np.ones_like(lam)
+    x = otab.node_log10U(lo, hi, K)
+    for k in range(K):
+        assert otab.budget_ratio(rho, lo, hi, 10.0 ** x[k] * u_ref, u_ref, lam) == pytest.approx(rho[k], rel=1e-14)
+    mid = 10.0 ** (0.5 * (x[1] + x[2]))
+    assert otab.budget_ratio(rho, lo, hi, mid * u_ref, u_ref, lam) == pytest.approx(0.5 * (rho[1] + rho[2]), rel=1e-12)
+    assert otab.budget_ratio(rho, lo, hi, 1e-3 * u_ref, u_ref, lam) == pytest.approx(rho[0], rel=1e-14)
+    assert otab.budget_ratio(rho, lo, hi, 1e6 * u_ref, u_ref, lam) == pytest.approx(rho[-1], rel=1e-14)
