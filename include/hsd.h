@@ -248,11 +248,12 @@ hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, co
  * own kernel shape: class 0 holds 513..1024 bins, class 1 257..512, class 2
  * 129..256 and class 3 16..128.  Per class:
  *   kg          row slots evaluated per straight-line group: 2 or 4;
- *   wide        the alternate lane layout, classes 0 and 1 only.  Class 0:
- *               0 = 32 lanes per pair with 32 row slots each and the
- *               absorbed-power table in LDS, 1 = 64 lanes with 16 slots;
- *               class 1: 0 = 32 lanes with 16 slots, 1 = 16 lanes with 32
- *               slots and the absorbed-power table in LDS;
+ *   wide        the alternate lane layout, classes 0, 1 and 3 (1 is refused
+ *               for class 2).  Class 0: 0 = 32 lanes per pair with 32 row
+ *               slots each and the absorbed-power table in LDS, 1 = 64 lanes
+ *               with 16 slots; class 1: 0 = 32 lanes with 16 slots, 1 = 16
+ *               lanes with 32 slots and the absorbed-power table in LDS;
+ *               class 3: 0 = 16 lanes with 8 slots, 1 = 8 lanes with 16;
  *   persistent  0 = one workgroup per work item (items in an order that
  *               gives each XCD whole cell blocks), 1 = a grid of the
  *               workgroups that fit on the device at once, fed items longest

@@ -652,8 +652,8 @@ hsd_status hsd_set_class_cfg(hsd_ctx* ctx, int32_t cls, const hsd_class_cfg* cfg
     if (!ctx) return HSD_ERR_INVALID_ARG;
     if (!cfg || cls < 0 || cls >= hsd::kClasses) return fail(ctx, HSD_ERR_INVALID_ARG, "bad class or null config");
     if (cfg->kg != 2 && cfg->kg != 4) return fail(ctx, HSD_ERR_INVALID_ARG, "kg must be 2 or 4");
-    if (cfg->wide != 0 && (cfg->wide != 1 || cls > 1))
-        return fail(ctx, HSD_ERR_INVALID_ARG, "wide is 0 or 1, and 1 only for classes 0 and 1");
+    if (cfg->wide != 0 && (cfg->wide != 1 || !hsd::class_has_wide(cls)))
+        return fail(ctx, HSD_ERR_INVALID_ARG, "wide is 0 or 1, and 1 only for classes 0, 1 and 3");
     if (cfg->persistent != 0 && cfg->persistent != 1) return fail(ctx, HSD_ERR_INVALID_ARG, "persistent is 0 or 1");
     hsd::ClassCfg& k = ctx->c.cfg[cls];
     k.kg = cfg->kg;
@@ -723,7 +723,7 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
         const hsd::ClassCfg keep = c.cfg[ci];
         hsd::ClassCfg best = keep;
         double best_ms = 1e300;
-        for (int wide = 0; wide <= (ci <= 1 ? 1 : 0) && st == HSD_OK; ++wide)
+        for (int wide = 0; wide <= (hsd::class_has_wide(ci) ? 1 : 0) && st == HSD_OK; ++wide)
             for (int pers = 0; pers <= 1 && st == HSD_OK; ++pers)
                 for (int kg = 2; kg <= 4 && st == HSD_OK; kg += 2) {
                     c.cfg[ci] = hsd::ClassCfg{kg, wide, pers};
@@ -845,7 +845,7 @@ hsd_status hsd_autotune_plan(hsd_ctx* ctx, int32_t n_cells, const double* u_dev,
         if (cls_grains[ci] == 0) continue;
         const hsd::ClassCfg cur = c.cfg[ci];
         hsd::ClassCfg win = cur;
-        for (int wide = 0; wide <= (ci <= 1 ? 1 : 0) && ok; ++wide)
+        for (int wide = 0; wide <= (hsd::class_has_wide(ci) ? 1 : 0) && ok; ++wide)
             for (int kg = 2; kg <= 4 && ok; kg += 2) {
                 if (wide == cur.wide && kg == cur.kg) continue;
                 c.cfg[ci] = hsd::ClassCfg{kg, wide, 0};

@@ -82,9 +82,12 @@ constexpr int kClassHi[kClasses] = {1024, 512, 256, 128};   // class c holds kCl
 struct ClassCfg {
     int kg = 2;          // row slots per straight-line group: 2 or 4
     int wide = 0;        // alternate lane layout: > 512 bins: 0 = 32 lanes x 32 slots with Cum in LDS,
-                         // 1 = 64 x 16; 257..512 bins: 0 = 32 x 16, 1 = 16 x 32 with Cum in LDS
+                         // 1 = 64 x 16; 257..512 bins: 0 = 32 x 16, 1 = 16 x 32 with Cum in LDS;
+                         // <= 128 bins: 0 = 16 x 8, 1 = 8 x 16
     int persistent = 0;  // 1 = persistent grid fed by an atomic item counter
 };
+// Classes with an alternate lane layout.
+constexpr bool class_has_wide(int cls) { return cls == 0 || cls == 1 || cls == 3; }
 
 // One grain slot of a batch for the grouped emission contraction.
 struct ContractSlot {

@@ -2,7 +2,7 @@
 // normalised P, for a batch of (cell, grain) pairs.
 //
 // Layout.  A pair is served by a segment of P consecutive lanes of one
-// wavefront (P = 16, 32 or 64, so a wave serves 64/P pairs of the same grain
+// wavefront (P = 8, 16, 32 or 64, so a wave serves 64/P pairs of the same grain
 // and different cells).  Lane q of the segment owns the enthalpy rows
 // k = r * P + q, r = 0..R-1, and keeps for each of them, in registers, the
 // inflow G(k) = sum_{j<f} A_kj X_j from the columns already processed; once the
@@ -118,7 +118,7 @@ __device__ __forceinline__ double seg_sum(double v) {
     v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);   // row_half_mirror
-    v += dpp_f64<0x140>(v);   // row_mirror
+    if constexpr (P >= 16) v += dpp_f64<0x140>(v);   // row_mirror
     if constexpr (P >= 32) {
         double a, b;
         swap_halves<true>(v, a, b);
@@ -137,7 +137,7 @@ __device__ __forceinline__ double seg_max(double v) {
     v = fmax(v, dpp_f64<0xB1>(v));
     v = fmax(v, dpp_f64<0x4E>(v));
     v = fmax(v, dpp_f64<0x141>(v));
-    v = fmax(v, dpp_f64<0x140>(v));
+    if constexpr (P >= 16) v = fmax(v, dpp_f64<0x140>(v));
     if constexpr (P >= 32) {
         double a, b;
         swap_halves<true>(v, a, b);
@@ -790,7 +790,11 @@ constexpr int kWaves = 4;
 }  // namespace
 
 // Bin-count classes: lanes per pair P and row slots per lane R (P R >= bins).
-//   <= 128 bins: P 16, R 8;  <= 256: P 16, R 16;
+//   <= 128 bins: P 16, R 8, or (alternate layout) P 8, R 16: twice the rows
+//           per lane and step, a segmented sum one step shorter, eight pairs
+//           per wave (the LDS tables of 32 pairs per workgroup allow two
+//           workgroups per CU);
+//   <= 256: P 16, R 16;
 //   <= 512: P 32, R 16, or (alternate layout) P 16, R 32 with the Cum table
 //           kept in LDS: twice the rows per lane and step, so the per-step
 //           work (suffix sums, the column's X) is spread over twice the rates;
@@ -799,6 +803,7 @@ namespace {
 int class_lanes(const ClassCfg& cfg, int cls) {
     if (cls == 0) return cfg.wide ? 64 : 32;
     if (cls == 1) return cfg.wide ? 16 : 32;
+    if (cls == 3) return cfg.wide ? 8 : 16;
     return 16;
 }
 bool class_ldscum(const ClassCfg& cfg, int cls) { return (cls == 0 && !cfg.wide) || (cls == 1 && cfg.wide); }
@@ -818,7 +823,9 @@ int solve_capacity(const Ctx& c, int cls) {
     const ClassCfg& cfg = c.cfg[cls];
     const int ts = tab_stride(c, cls);
     switch (cls) {
-        case 3: return cap_phys<16, 8, kWaves, false>(cfg.kg, ts);
+        case 3:
+            if (cfg.wide) return cap_phys<8, 16, kWaves, false>(cfg.kg, ts);
+            return cap_phys<16, 8, kWaves, false>(cfg.kg, ts);
         case 2: return cap_phys<16, 16, kWaves, false>(cfg.kg, ts);
         case 1:
             if (cfg.wide) return cap_phys<16, 32, kWaves, true>(cfg.kg, ts);
@@ -857,7 +864,9 @@ hipError_t launch_solve(const Ctx& c, const SolveLaunch& sl, int cls, const int2
     if (cfg.persistent && !queue) return hipErrorInvalidValue;
     ka.tabstride = tab_stride(c, cls);
     switch (cls) {
-        case 3: return launch_phys<16, 8, kWaves, false>(ka, n_items, cfg.kg, q, s);
+        case 3:
+            if (cfg.wide) return launch_phys<8, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
+            return launch_phys<16, 8, kWaves, false>(ka, n_items, cfg.kg, q, s);
         case 2: return launch_phys<16, 16, kWaves, false>(ka, n_items, cfg.kg, q, s);
         case 1:
             if (cfg.wide) return launch_phys<16, 32, kWaves, true>(ka, n_items, cfg.kg, q, s);

@@ -387,6 +387,48 @@ def test_wide_enthalpy_range_matches_oracle(hsd):
             assert ea < 1e-4
 
 
+@pytest.mark.parametrize("wide", [0, 1])
+def test_lane_layouts_match_oracle(hsd, wide):
+    # Each bin-count class in both of its lane layouts (the alternate one where
+    # the class has it), with bin counts that leave part of the layout empty:
+    # 992, 304, 208, 128, 96 and 16 bins (in the 128-bin class, 96 bins leave
+    # 32 positions below row 0: four slots of the 8-lane layout); faint
+    # attenuated, moderate and bright fields.  j, emitted and representable
+    # absorbed power against the oracle.
+    lam = synth.wavelength_grid_cm(500)
+    bins = [992, 304, 208, 128, 96, 16]
+    radii = [3.5e-8, 12e-8, 25e-8, 60e-8, 120e-8, 400e-8]
+    grains = [synth.make_grain("carbonaceous" if i % 2 == 0 else "silicate", a, lam, n_bins=n)
+              for i, (a, n) in enumerate(zip(radii, bins))]
+    ctx = hsd.Context(lam)
+    gids = [ctx.add_grain(g) for g in grains]
+    for c in range(hsd.N_CLASSES):
+        ctx.hsd_set_class_cfg(c, kg=4 if wide else 2, wide=wide if c != 2 else 0, persistent=0)
+    u = np.concatenate([
+        make_fields(lam, synth.FieldRecipe(seed=93, U_range=(0.1, 1.0), jitter=0.0, tau_V_range=(5.0, 20.0)), 1),
+        make_fields(lam, synth.FieldRecipe(seed=94, U_range=(1.0, 100.0), jitter=0.3, tau_V_range=None), 1),
+        make_fields(lam, synth.FieldRecipe(seed=95, U_range=(1e3, 1e5), jitter=0.3, tau_V_range=None), 1)])
+    ud = torch.tensor(u, device="cuda")
+    j = torch.empty((3, len(gids), 500), dtype=torch.float32, device="cuda")
+    diag = torch.empty((3, len(gids), 4), dtype=torch.float32, device="cuda")
+    print(f"lane layouts: wide {wide}, bins {bins}", flush=True)
+    ctx.hsd_solve(ud, gids, j, diag)
+    ctx.hsd_sync()
+    jj = j.cpu().numpy().astype(np.float64)
+    dd = diag.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for gi, g in enumerate(grains):
+        for c in range(3):
+            _, jr, d = oracle.solve_pair(u[c], g, lam, with_diag=True)
+            e = j_rel_err(jj[c, gi], jr)
+            worst = max(worst, e)
+            assert e < J_TOL, (g.n_bins, c, e)
+            assert abs(dd[c, gi, 1] / d["emitted"] - 1) < J_TOL
+            assert abs(dd[c, gi, 2] / d["A_rep"] - 1) < J_TOL
+    print(f"lane layouts (wide {wide}): worst j rel err {worst:.2e}", flush=True)
+    ctx.close()
+
+
 def test_size_convolution_matches_oracle(hsd):
     # four radii of the batched workload, three cells: the library's solve and
     # convolution against the oracle's spectra and its weighted sum

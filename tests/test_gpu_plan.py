@@ -62,7 +62,7 @@ def _eager(ctx, w, ids, u):
 def _set_all(ctx, hsd, **kw):
     for c in range(hsd.N_CLASSES):
         cfg = dict(kw)
-        if c > 1:
+        if c == 2:                     # no alternate layout
             cfg["wide"] = 0
         ctx.hsd_set_class_cfg(c, **cfg)
 
