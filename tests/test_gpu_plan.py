@@ -220,8 +220,8 @@ def test_autotune_keeps_fastest_and_results(hsd, c2_small, tmp_path):
     j0, d0 = _eager(ctx, w, ids, u)
     try:
         recs = ctx.hsd_autotune(u, ids, runs=3)
-        # classes 0 and 1: kg x persistent x layout; classes 2 and 3: kg x persistent
-        assert len(recs) == 8 + 8 + 4 + 4
+        # classes 0, 1 and 3: kg x persistent x layout; class 2: kg x persistent
+        assert len(recs) == 8 + 8 + 4 + 8
         assert all(r["ms"] > 0 and math.isfinite(r["ms"]) for r in recs)
         for c in range(hsd.N_CLASSES):
             mine = [r for r in recs if r["cls"] == c]
@@ -247,7 +247,7 @@ def test_plan_autotune_keeps_fastest_and_results(hsd, c2_small, tmp_path):
         # the start, then per occupied class the other kg x layout choices, then the other contraction size
         occupied = sum(1 for lo, hi in hsd.CLASS_BINS if any(lo <= ctx.n_bins[g] <= hi for g in ids))
         assert recs[0]["cls"] == -1 and recs[-1]["cls"] == -1
-        assert len(recs) == 1 + 3 + 3 + 1 + 1 + 1 if occupied == 4 else len(recs) >= 2
+        assert len(recs) == 1 + 3 + 3 + 1 + 3 + 1 if occupied == 4 else len(recs) >= 2
         assert all(r["ms"] > 0 and math.isfinite(r["ms"]) for r in recs)
         assert all(ctx.hsd_get_class_cfg(c)["persistent"] == 0 for c in range(hsd.N_CLASSES))
         # coordinate descent keeps only improvements: the kept configuration is the fastest plan timed
