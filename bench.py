@@ -11,8 +11,9 @@ step is one solve of that whole batch:
 
 * plain path (the line's `value`): the fused rates/recursion kernels, the
   emission contraction and the diagnostics for every pair, replayed from a
-  plan (HIP graphs, solver classes as parallel branches), launch
-  configuration from the autotuner's cache;
+  plan (HIP graphs, solver classes as parallel branches, each smaller
+  class's spectra contracted on its branch as soon as its solve ends),
+  launch configuration from the autotuner's cache;
 * table method (the cheap alternative the surrogate is measured against):
   plain spectra of one reference field shape at 57 log-spaced field
   strengths per grain, interpolated in log U and scaled by each pair's
@@ -40,8 +41,9 @@ the emitted power; bar 2%).  The surrogate's band error is also given on the
 whole 1% sample against the plain GPU solve.
 
 Roofline (the dominant kernel: the fused rates/recursion solver, timed with
-HIP events on its stream inside the timed steps): the solver is bound by
-vector-ALU issue.  Algorithmic work per on-grid upward rate (a transition
+HIP events on its stream inside the timed steps; the span of its four class
+launches, which the smaller classes' contractions share while the largest
+class still solves): the solver is bound by vector-ALU issue.  Algorithmic work per on-grid upward rate (a transition
 whose photon wavelength lies on the grid): the log-grid index and the
 log-log interpolation (six single-precision and integer operations), one
 exponential (issued at half the lane rate on gfx950: two lane-cycles) and

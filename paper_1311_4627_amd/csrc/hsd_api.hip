@@ -26,6 +26,14 @@ struct Batch {
     long long rows = 0;
     std::vector<hsd::ContractSlot> cslots;   // the grouped contraction's slots (those with rows)
     int c_blocks = 0;                        // its workgroups
+    // The same slots by bin-count class, each class's workgroups numbered from
+    // 0 (a concurrent plan contracts a class's spectra on its own branch), and
+    // the class the plan contracts last, after every branch has joined (the
+    // one with the most solver work, which finishes last).
+    std::vector<hsd::ContractSlot> cslots_cls;
+    int ccls_begin[hsd::kClasses + 1] = {0, 0, 0, 0, 0};
+    int ccls_blocks[hsd::kClasses] = {0, 0, 0, 0};
+    int c_last = 0;
 };
 
 // The contraction slots of a batch whose slot g holds rows[g] P~ rows at
@@ -50,6 +58,27 @@ void contract_slots(const Ctx& c, int32_t n_grains, const int32_t* ids, const st
         b.cslots.push_back(sl);
     }
     b.c_blocks = hsd::contract_blocks(b.cslots);
+    b.cslots_cls.clear();
+    double most = -1.0;
+    for (int ci = 0; ci < hsd::kClasses; ++ci) {
+        const int hi = hsd::kClassHi[ci];
+        const int lo = ci + 1 < hsd::kClasses ? hsd::kClassHi[ci + 1] : 0;
+        std::vector<hsd::ContractSlot> mine;
+        double work = 0.0;
+        for (const hsd::ContractSlot& sl : b.cslots)
+            if (sl.nb > lo && sl.nb <= hi) {
+                mine.push_back(sl);
+                work += static_cast<double>(sl.rows) * sl.nb * sl.nb;   // rates grow as bins^2
+            }
+        b.ccls_begin[ci] = static_cast<int>(b.cslots_cls.size());
+        b.ccls_blocks[ci] = hsd::contract_blocks(mine);
+        b.cslots_cls.insert(b.cslots_cls.end(), mine.begin(), mine.end());
+        if (!mine.empty() && work > most) {
+            most = work;
+            b.c_last = ci;
+        }
+    }
+    b.ccls_begin[hsd::kClasses] = static_cast<int>(b.cslots_cls.size());
 }
 
 // Workspace of surrogate solves (grown on demand, kept with the context).
@@ -120,6 +149,7 @@ struct hsd_plan {
     int2* items = nullptr;
     unsigned* queue = nullptr;
     hsd::ContractSlot* cslots = nullptr;
+    hsd::ContractSlot* cslots_cls = nullptr;
     hipStream_t cap = nullptr;
     hipStream_t side[hsd::kClasses] = {};
     hipEvent_t sev[hsd::kClasses + 1] = {};
@@ -268,6 +298,7 @@ struct Bufs {
     int2* items;
     unsigned* queue;     // kClasses counters
     hsd::ContractSlot* cslots;
+    hsd::ContractSlot* cslots_cls;   // by class (concurrent plans), or null
 };
 
 struct Events {
@@ -281,7 +312,12 @@ hipError_t record(const Events& t, int i, hipStream_t s) {
 
 // Enqueue the whole batch on stream s: the solver classes (on the side
 // streams, in parallel, when `side` is given), then the contraction of every
-// grain's spectra, whose epilogue also writes the emitted power.
+// grain's spectra, whose epilogue also writes the emitted power.  With side
+// streams and the slots by class, each class except the last (b.c_last) is
+// contracted on its own branch right after its solve, beside the solves
+// still running (the contraction runs on the matrix cores, the solver on
+// the vector ALUs), and the last class after the branches join; with phases,
+// those early contractions belong to the solver phase.
 constexpr int kPhaseSolve = 1, kPhaseContract = 2, kPhaseAll = 3;
 
 hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells, const double* u, int32_t n_grains,
@@ -299,6 +335,15 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
     sl.diag = diag;
     sl.P64 = P64;
     sl.errword = c.errword;
+    const bool by_cls = side && d.cslots_cls && j;
+    auto contract_class = [&](int ci, hipStream_t st) -> hsd_status {
+        const int n_sl = b.ccls_begin[ci + 1] - b.ccls_begin[ci];
+        if (n_sl == 0) return HSD_OK;
+        hsd::ContractLaunch cl{d.cslots_cls + b.ccls_begin[ci], n_sl, b.ccls_blocks[ci], d.Pt, d.pscale, nullptr,
+                               j, diag, c.wtrap, c.L, c.Lp, n_grains, c.contract, c.contract_waves};
+        HSD_HIP(ctx, hsd::launch_contract(cl, st));
+        return HSD_OK;
+    };
     HSD_HIP(ctx, record(t, 0, s));
     if (!(phases & kPhaseSolve)) {
     } else if (side) {
@@ -308,6 +353,10 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
             if (n_it == 0) continue;
             HSD_HIP(ctx, hipStreamWaitEvent(side[ci], sev[0], 0));
             HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, d.items + b.cls_begin[ci], n_it, d.queue + ci, side[ci]));
+            if (by_cls && ci != b.c_last) {
+                const hsd_status st = contract_class(ci, side[ci]);
+                if (st != HSD_OK) return st;
+            }
             HSD_HIP(ctx, hipEventRecord(sev[1 + ci], side[ci]));
             HSD_HIP(ctx, hipStreamWaitEvent(s, sev[1 + ci], 0));
         }
@@ -319,7 +368,10 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
         }
     }
     HSD_HIP(ctx, record(t, 1, s));
-    if (j && (phases & kPhaseContract)) {
+    if (by_cls && (phases & kPhaseContract)) {
+        const hsd_status st = contract_class(b.c_last, s);
+        if (st != HSD_OK) return st;
+    } else if (j && (phases & kPhaseContract)) {
         // every grain in one launch; its epilogue also writes the emitted
         // power (diag entry 1), so the diagnostics phase has no work left
         hsd::ContractLaunch cl{d.cslots, static_cast<int>(b.cslots.size()), b.c_blocks, d.Pt, d.pscale, nullptr,
@@ -367,7 +419,7 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
     HSD_HIP(ctx, grow(c.cslots, c.cslots_cap, std::max<size_t>(b.cslots.size(), 1)));
-    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue, c.cslots};
+    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue, c.cslots, nullptr};
     return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s);
 }
 
@@ -608,7 +660,8 @@ hsd_status hsd_solve_noalloc(hsd_ctx* ctx, int32_t n_cells, const double* u_dev,
     unsigned char* base = c.scratch;
     Bufs d{reinterpret_cast<float*>(base + o_pt), reinterpret_cast<float*>(base + o_pscale),
            reinterpret_cast<hsd::GrainView*>(base + o_views), reinterpret_cast<long long*>(base + o_offs),
-           reinterpret_cast<int2*>(base + o_items), c.queue, reinterpret_cast<hsd::ContractSlot*>(base + o_cslots)};
+           reinterpret_cast<int2*>(base + o_items), c.queue, reinterpret_cast<hsd::ContractSlot*>(base + o_cslots),
+           nullptr};
     return run_batch(ctx, d, n_cells, u_dev, n_grains, grain_ids_host, j_dev, diag_dev, nullptr,
                      static_cast<hipStream_t>(stream));
 }
@@ -898,6 +951,7 @@ void hsd_plan_destroy(hsd_plan* p) {
     hipFree(p->views);
     hipFree(p->offs);
     hipFree(p->items);
+    hipFree(p->cslots_cls);
     hipFree(p->queue);
     hipFree(p->cslots);
     delete p;
@@ -944,6 +998,7 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
     al(p->items, p->b.items.size());
     al(p->queue, static_cast<size_t>(hsd::kClasses));
     al(p->cslots, p->b.cslots.size());
+    if (conc) al(p->cslots_cls, p->b.cslots_cls.size());
     if (e == hipSuccess)
         e = hipMemcpy(p->views, p->b.views.data(), sizeof(hsd::GrainView) * n_grains, hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -952,6 +1007,9 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
         e = hipMemcpy(p->items, p->b.items.data(), sizeof(int2) * p->b.items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !p->b.cslots.empty())
         e = hipMemcpy(p->cslots, p->b.cslots.data(), sizeof(hsd::ContractSlot) * p->b.cslots.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && conc && !p->b.cslots_cls.empty())
+        e = hipMemcpy(p->cslots_cls, p->b.cslots_cls.data(), sizeof(hsd::ContractSlot) * p->b.cslots_cls.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->queue, 0, sizeof(unsigned) * hsd::kClasses);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
@@ -967,7 +1025,7 @@ hsd_status hsd_plan_create(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, i
         hsd_plan_destroy(p);
         return hip_fail(ctx, e, "hsd_plan_create");
     }
-    Bufs d{p->Pt, p->pscale, p->views, p->offs, p->items, p->queue, p->cslots};
+    Bufs d{p->Pt, p->pscale, p->views, p->offs, p->items, p->queue, p->cslots, conc ? p->cslots_cls : nullptr};
     const Events none{{nullptr, nullptr, nullptr, nullptr}};
     // Without timing the whole batch is one graph.  With timing, the solver
     // and the contraction (whose epilogue writes the diagnostics) are graphs
