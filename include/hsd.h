@@ -322,7 +322,8 @@ hsd_status hsd_autotune(hsd_ctx* ctx, int32_t n_cells, const double* u_dev, int3
 
 /* Tuning for plans, timed as they run: every candidate is a concurrent plan
  * (HSD_PLAN_CONCURRENT) of the given batch — all occupied classes as
- * parallel graph branches, then the contraction, into an internal j buffer —
+ * parallel graph branches with their contractions, into an internal j
+ * buffer —
  * replayed `runs` times (first replay a warm-up, the mean of the others the
  * score).  Starting from the context's configuration with every class as an
  * ordinary grid (persistent = 0, as concurrent plans require), it tries, one
@@ -354,8 +355,14 @@ hsd_status hsd_autotune_plan(hsd_ctx* ctx, int32_t n_cells, const double* u_dev,
  *          and writes the milliseconds of the solver, the contraction and the
  *          diagnostics (always 0, as for hsd_phase_ms) to ms_host[0..2].
  *          HSD_PLAN_CONCURRENT: the solver classes run as parallel branches
- *          of the graph, so one class's tail overlaps the next class.  Every
- *          class must then be configured with persistent = 0, else the call
+ *          of the graph, so one class's tail overlaps the next class, and
+ *          each class except the one with the most solver work (bins^2 x
+ *          cells) is contracted on its own branch as soon as its solve ends;
+ *          that class is contracted after the branches join.  With
+ *          HSD_PLAN_TIMING the early contractions count in the solver's
+ *          milliseconds.  The results are the same bit for bit as without
+ *          the flag.  Every class must then be configured with persistent =
+ *          0, else the call
  *          fails with HSD_ERR_INVALID_ARG (a persistent grid takes every
  *          workgroup slot of the device and would hold the other branches
  *          off it).
