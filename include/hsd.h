@@ -231,17 +231,22 @@ hsd_status hsd_measure_exp2(hsd_ctx* ctx, double* per_second_host);
 
 /* The emissivity of a whole size distribution (Sec. 2.3, eq:convolution on
  * the discrete size grid): out[c][l] = sum_g w_g j[c][g][l], multiplied by
- * lambda_l when lambda_weighted != 0 (lambda j_lambda = nu j_nu, the form the
- * paper's library returns).  The weights w_g are the caller's quadrature of
- * the size distribution, per H atom for the paper's units (then out is
- * erg s^-1 sr^-1 per H; divide by 1 eV in erg for the paper's eV).
+ * lambda_l when flags has HSD_SIZE_LAMBDA (lambda j_lambda = nu j_nu, the
+ * form the paper's library returns) and divided by 1 eV in erg
+ * (1.602176634e-12) when it has HSD_SIZE_EV.  The weights w_g are the
+ * caller's quadrature of the size distribution, per H atom for the paper's
+ * units: with both flags out is then in the paper's eV s^-1 sr^-1 per H
+ * (erg s^-1 sr^-1 per H without HSD_SIZE_EV).
  *   j_dev        [n_cells][n_grains][n_lambda] float (as from hsd_solve)
  *   weights_host [n_grains] double, finite
+ *   flags        0, or HSD_SIZE_LAMBDA and/or HSD_SIZE_EV (other bits: HSD_ERR_INVALID_ARG)
  *   out_dev      [n_cells][n_lambda] double
  * FP64 sums.  Waits for `stream` once (to reuse the weight buffer), then
  * enqueues on it. */
+#define HSD_SIZE_LAMBDA 1
+#define HSD_SIZE_EV 2
 hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, const float* j_dev,
-                             const double* weights_host, int32_t lambda_weighted, double* out_dev, void* stream);
+                             const double* weights_host, int32_t flags, double* out_dev, void* stream);
 
 /* ---- Launch configuration (read and set by the autotuner) ----
  * The solver groups grains into four bin-count classes, each served by its

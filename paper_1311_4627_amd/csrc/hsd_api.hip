@@ -1094,9 +1094,10 @@ hsd_status hsd_plan_phase_ms(hsd_plan* p, double* ms) {
 }
 
 hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, const float* j_dev,
-                             const double* weights_host, int32_t lambda_weighted, double* out_dev, void* stream) {
+                             const double* weights_host, int32_t flags, double* out_dev, void* stream) {
     if (!ctx) return HSD_ERR_INVALID_ARG;
     if (n_cells < 0 || n_grains < 0) return fail(ctx, HSD_ERR_INVALID_ARG, "negative size");
+    if (flags & ~(HSD_SIZE_LAMBDA | HSD_SIZE_EV)) return fail(ctx, HSD_ERR_INVALID_ARG, "unknown flag");
     if (n_cells == 0) return HSD_OK;
     if (!j_dev || !out_dev || (n_grains > 0 && !weights_host)) return fail(ctx, HSD_ERR_INVALID_ARG, "null pointer");
     for (int g = 0; g < n_grains; ++g)
@@ -1108,7 +1109,7 @@ hsd_status hsd_size_convolve(hsd_ctx* ctx, int32_t n_cells, int32_t n_grains, co
     HSD_HIP(ctx, grow(c.sizew, c.sizew_cap, static_cast<size_t>(std::max(n_grains, 1))));
     if (n_grains > 0)
         HSD_HIP(ctx, hipMemcpy(c.sizew, weights_host, sizeof(double) * n_grains, hipMemcpyHostToDevice));
-    HSD_HIP(ctx, hsd::launch_sizedist(j_dev, c.sizew, c.lam, n_cells, n_grains, c.L, lambda_weighted ? 1 : 0, out_dev, s));
+    HSD_HIP(ctx, hsd::launch_sizedist(j_dev, c.sizew, c.lam, n_cells, n_grains, c.L, flags, out_dev, s));
     return HSD_OK;
 }
 

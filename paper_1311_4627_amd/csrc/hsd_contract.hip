@@ -350,8 +350,9 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3, 
 // Size-distribution convolution (Sec. 2.3, eq:convolution on the size grid):
 // out[c][l] = (lambda_l if lw) * sum_g w_g j[c][g][l], FP64 sums; one thread
 // per (cell, wavelength), consecutive threads on consecutive wavelengths.
+// flags: bit 0 weights by lambda, bit 1 divides by 1 eV in erg (the paper's units).
 __global__ void __launch_bounds__(256) k_sizedist(const float* j, const double* w, const double* lam, int n_cells,
-                                                  int G, int L, int lw, double* out) {
+                                                  int G, int L, int flags, double* out) {
     const long long i = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= static_cast<long long>(n_cells) * L) return;
     const long long c = i / L;
@@ -359,7 +360,8 @@ __global__ void __launch_bounds__(256) k_sizedist(const float* j, const double* 
     const float* jc = j + c * G * L + l;
     double acc = 0.0;
     for (int g = 0; g < G; ++g) acc = fma(w[g], static_cast<double>(jc[static_cast<long long>(g) * L]), acc);
-    out[i] = lw ? acc * lam[l] : acc;
+    if (flags & 1) acc *= lam[l];
+    out[i] = (flags & 2) ? acc / 1.602176634e-12 : acc;
 }
 
 }  // namespace
@@ -382,12 +384,12 @@ hipError_t launch_contract(const ContractLaunch& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int lw,
+hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int flags,
                            double* out, hipStream_t s) {
     const long long n = static_cast<long long>(n_cells) * L;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sizedist, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, j, w, lam, n_cells, G,
-                       L, lw, out);
+                       L, flags, out);
     return hipGetLastError();
 }
 

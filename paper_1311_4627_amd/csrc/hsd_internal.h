@@ -207,7 +207,8 @@ hipError_t launch_table_eval(const double* energy, const double* ref_energy, con
                              int n_nodes, double lo, double step, int n_cells, int G, int L, float* j, hipStream_t s);
 // Exponentials per second that the device issues (hsd_measure.hip).
 hipError_t measure_exp2(double* per_s);
-hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int lw,
+// flags as hsd_size_convolve's: bit 0 lambda-weighted, bit 1 in eV.
+hipError_t launch_sizedist(const float* j, const double* w, const double* lam, int n_cells, int G, int L, int flags,
                            double* out, hipStream_t s);
 
 // ---- learned surrogate (hsd_surrogate.hip) ----

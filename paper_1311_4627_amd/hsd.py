@@ -47,6 +47,8 @@ CHECK_ABSORBED = 0      # surrogate energy check against the absorbed power A
 CHECK_MODEL = 1         # ... against rho A, rho the predicted energy ratio of the plain model
 CHECK_TABLE = 2         # ... against the table budget of hsd_set_energy_budget
 SAVE_WEIGHTS_ONLY = 1   # checkpoint without the Adam moments
+SIZE_LAMBDA = 1         # size convolution: lambda j_lambda
+SIZE_EV = 2             # ... in eV instead of erg
 
 
 class HsdError(RuntimeError):
@@ -456,7 +458,7 @@ class Context:
             self._raise(st, "hsd_solve_surrogate")
         return int(nfb.value)
 
-    def hsd_size_convolve(self, j, weights, out, lambda_weighted: bool = True, stream=None):
+    def hsd_size_convolve(self, j, weights, out, lambda_weighted: bool = True, per_ev: bool = False, stream=None):
         import torch
         n_cells, G = int(j.shape[0]), int(j.shape[1])
         w = np.ascontiguousarray(weights, dtype=np.float64)
@@ -464,8 +466,9 @@ class Context:
             raise ValueError("one weight per grain")
         _check_dev(j, torch.float32, (n_cells, G, self.L), "j")
         _check_dev(out, torch.float64, (n_cells, self.L), "out")
-        st = self._lib.hsd_size_convolve(self._h, n_cells, G, j.data_ptr(), _dptr(w), 1 if lambda_weighted else 0,
-                                         out.data_ptr(), _stream_ptr(stream))
+        flags = (SIZE_LAMBDA if lambda_weighted else 0) | (SIZE_EV if per_ev else 0)
+        st = self._lib.hsd_size_convolve(self._h, n_cells, G, j.data_ptr(), _dptr(w), flags, out.data_ptr(),
+                                         _stream_ptr(stream))
         if st != HSD_OK:
             self._raise(st, "hsd_size_convolve")
 

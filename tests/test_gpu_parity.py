@@ -456,3 +456,16 @@ def test_size_convolution_matches_oracle(hsd):
         e = j_rel_err(got[c], ref)
         print(f"size convolution cell {c}: rel err {e:.2e}", flush=True)
         assert e < J_TOL
+    # the paper's units: the same sums in eV (1 eV = 1.602176634e-12 erg), and
+    # without the lambda weight
+    out2 = torch.empty_like(out)
+    ctx.hsd_size_convolve(j, weights, out2, per_ev=True)
+    ctx.hsd_sync()
+    assert np.allclose(out2.cpu().numpy(), mine / oracle.EV, rtol=1e-12, atol=0)
+    ctx.hsd_size_convolve(j, weights, out2, lambda_weighted=False)
+    ctx.hsd_sync()
+    assert np.allclose(out2.cpu().numpy() * w.lam_cm[None, :], mine, rtol=1e-12, atol=0)
+    # an unknown flag bit is refused (through the C ABI: the binding passes known bits only)
+    w64 = np.ascontiguousarray(weights, dtype=np.float64)
+    st = ctx._lib.hsd_size_convolve(ctx._h, 3, 4, j.data_ptr(), hsd._dptr(w64), 4, out2.data_ptr(), None)
+    assert hsd.STATUS_NAMES.get(st) == "HSD_ERR_INVALID_ARG"
