@@ -624,7 +624,8 @@ def bench_plain(args):
         tuned = autotune.tune(ctx, ud, ids, cache_path=TUNE_CACHE, force=args.retune)
         classes = tuned["cfg"]
         if args.no_persistent:
-            # the kernels and work order of the concurrent plan, launched one class after another
+            # the kernels and work order of the concurrent plan as eager calls (one dispatch per
+            # class; counter collection runs the dispatches one at a time)
             classes = [dict(c, persistent=0) for c in classes]
             for cls, c in enumerate(classes):
                 ctx.hsd_set_class_cfg(cls, **c)

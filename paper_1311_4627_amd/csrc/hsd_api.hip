@@ -386,9 +386,12 @@ hsd_status enqueue(hsd_ctx* ctx, const Batch& b, const Bufs& d, int32_t n_cells,
 // Copy the batch's host description into the device buffers d and enqueue
 // its launches (eager solves: hsd_solve, hsd_solve_P, hsd_solve_noalloc).
 hsd_status run_batch(hsd_ctx* ctx, const Bufs& d, int32_t n_cells, const double* u, int32_t n_grains,
-                     const int32_t* ids, float* j, float* diag, double* P64, hipStream_t s) {
+                     const int32_t* ids, float* j, float* diag, double* P64, hipStream_t s, bool branches = false) {
     Ctx& c = ctx->c;
     const Batch& b = ctx->batch;
+    if (branches && d.cslots_cls && !b.cslots_cls.empty())
+        HSD_HIP(ctx, hipMemcpyAsync(d.cslots_cls, b.cslots_cls.data(), sizeof(hsd::ContractSlot) * b.cslots_cls.size(),
+                                    hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(d.views, b.views.data(), sizeof(hsd::GrainView) * n_grains,
                                 hipMemcpyHostToDevice, s));
     HSD_HIP(ctx, hipMemcpyAsync(d.offs, b.offs.data(), sizeof(long long) * n_grains, hipMemcpyHostToDevice, s));
@@ -401,9 +404,29 @@ hsd_status run_batch(hsd_ctx* ctx, const Bufs& d, int32_t n_cells, const double*
     Events t{{nullptr, nullptr, nullptr, nullptr}};
     if (c.timing)
         for (int i = 0; i < 4; ++i) t.ev[i] = c.ev[i];
-    hsd_status st = enqueue(ctx, b, d, n_cells, u, n_grains, ids, j, diag, P64, s, t, nullptr, nullptr);
+    hsd_status st = enqueue(ctx, b, d, n_cells, u, n_grains, ids, j, diag, P64, s, t, branches ? c.side : nullptr,
+                            branches ? c.sev : nullptr);
     if (st == HSD_OK && c.timing) c.timed = true;
     return st;
+}
+
+// Whether eager solves run their classes as concurrent branches: yes unless
+// a class is configured persistent (its grid takes every workgroup slot);
+// the branch streams and events are made on first use, at the default
+// priority.
+bool side_streams(hsd_ctx* ctx) {
+    Ctx& c = ctx->c;
+    for (int ci = 0; ci < hsd::kClasses; ++ci)
+        if (c.cfg[ci].persistent) return false;
+    if (c.sev[hsd::kClasses]) return true;
+    for (int i = 0; i < hsd::kClasses; ++i)
+        if (!c.side[i] && hipStreamCreateWithFlags(&c.side[i], hipStreamNonBlocking) != hipSuccess) return false;
+    for (int i = 0; i <= hsd::kClasses; ++i)
+        if (!c.sev[i] && hipEventCreateWithFlags(&c.sev[i], hipEventDisableTiming) != hipSuccess) {
+            c.sev[i] = nullptr;       // made again on the next call; the others are kept
+            return false;
+        }
+    return true;
 }
 
 // Eager solve on the context's workspace (hsd_solve and hsd_solve_P).
@@ -419,8 +442,11 @@ hsd_status run_solve(hsd_ctx* ctx, int32_t n_cells, const double* u, int32_t n_g
     HSD_HIP(ctx, grow(c.offs, c.offs_cap, static_cast<size_t>(n_grains)));
     HSD_HIP(ctx, grow(c.items, c.items_cap, std::max<size_t>(b.items.size(), 1)));
     HSD_HIP(ctx, grow(c.cslots, c.cslots_cap, std::max<size_t>(b.cslots.size(), 1)));
-    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue, c.cslots, nullptr};
-    return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s);
+    const bool branches = side_streams(ctx);
+    if (branches) HSD_HIP(ctx, grow(c.cslots_cls, c.cslots_cls_cap, std::max<size_t>(b.cslots_cls.size(), 1)));
+    Bufs d{want_pt ? c.Pt : nullptr, c.pscale, c.views, c.offs, c.items, c.queue, c.cslots,
+           branches ? c.cslots_cls : nullptr};
+    return run_batch(ctx, d, n_cells, u, n_grains, ids, j, diag, P64, s, branches);
 }
 
 // ---- fixed device scratch for hsd_solve_noalloc ----
@@ -551,8 +577,13 @@ void hsd_destroy(hsd_ctx* ctx) {
     hipFree(c.views);
     hipFree(c.offs);
     hipFree(c.items);
+    hipFree(c.cslots_cls);
     for (auto& e : c.ev)
         if (e) hipEventDestroy(e);
+    for (auto& e : c.sev)
+        if (e) hipEventDestroy(e);
+    for (auto& st : c.side)
+        if (st) hipStreamDestroy(st);
     delete ctx;
 }
 
@@ -1900,6 +1931,33 @@ hsd_status hsd_solve_surrogate(hsd_ctx* ctx, int32_t n_cells, const double* u_de
     sl.cellmap = w.cellmap;
     sl.seg_off = w.seg_off;
     sl.seg_cnt = w.seg_cnt;
+    if (side_streams(ctx)) {
+        // the classes as concurrent branches, each smaller class's spectra and
+        // emitted power contracted on its branch, the largest after the join
+        HSD_HIP(ctx, grow(c.cslots_cls, c.cslots_cls_cap, std::max<size_t>(b.cslots_cls.size(), 1)));
+        HSD_HIP(ctx, hipMemcpyAsync(c.cslots_cls, b.cslots_cls.data(), sizeof(hsd::ContractSlot) * b.cslots_cls.size(),
+                                    hipMemcpyHostToDevice, s));
+        auto contract_class = [&](int ci, hipStream_t st) -> hipError_t {
+            const int n_sl = b.ccls_begin[ci + 1] - b.ccls_begin[ci];
+            if (n_sl == 0) return hipSuccess;
+            hsd::ContractLaunch cl{c.cslots_cls + b.ccls_begin[ci], n_sl, b.ccls_blocks[ci], c.Pt, c.pscale,
+                                   w.cellmap, j_dev, diag_dev, c.wtrap, c.L, c.Lp, n_grains, c.contract,
+                                   c.contract_waves};
+            return hsd::launch_contract(cl, st);
+        };
+        HSD_HIP(ctx, hipEventRecord(c.sev[0], s));
+        for (int ci = 0; ci < hsd::kClasses; ++ci) {
+            const int n_it = b.cls_begin[ci + 1] - b.cls_begin[ci];
+            if (n_it == 0) continue;
+            HSD_HIP(ctx, hipStreamWaitEvent(c.side[ci], c.sev[0], 0));
+            HSD_HIP(ctx, hsd::launch_solve(c, sl, ci, c.items + b.cls_begin[ci], n_it, c.queue + ci, c.side[ci]));
+            if (ci != b.c_last) HSD_HIP(ctx, contract_class(ci, c.side[ci]));
+            HSD_HIP(ctx, hipEventRecord(c.sev[1 + ci], c.side[ci]));
+            HSD_HIP(ctx, hipStreamWaitEvent(s, c.sev[1 + ci], 0));
+        }
+        HSD_HIP(ctx, contract_class(b.c_last, s));
+        return HSD_OK;
+    }
     for (int ci = 0; ci < hsd::kClasses; ++ci) {
         const int n_it = b.cls_begin[ci + 1] - b.cls_begin[ci];
         if (n_it == 0) continue;

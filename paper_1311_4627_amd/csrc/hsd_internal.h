@@ -128,6 +128,12 @@ struct Ctx {
     bool timing = false;
     bool timed = false;           // events of the last solve are recorded
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // eager solves: the classes as concurrent branches on these streams (made
+    // on first use), each smaller class contracted on its branch from these
+    // slots by class
+    hipStream_t side[kClasses] = {};
+    hipEvent_t sev[kClasses + 1] = {};
+    ContractSlot* cslots_cls = nullptr; size_t cslots_cls_cap = 0;
 };
 
 // Gauss-Legendre rules used by the precompute kernels (nodes on [-1, 1]).
