@@ -118,6 +118,10 @@ def test_energy_budget_matches_oracle(hsd, twin):
         ctx.hsd_solve_surrogate(ud, ids, [sur] * G, j, diag, check=hsd.CHECK_TABLE)
     with pytest.raises(hsd.HsdError):                            # a grain twice
         ctx.hsd_set_energy_budget([ids[0], ids[0]], ur, LO, HI, table[:2])
+    with pytest.raises(hsd.HsdError):                            # an empty node range
+        ctx.hsd_set_energy_budget(ids, ur, HI, LO, table)
+    with pytest.raises(hsd.HsdError):                            # a grain the context does not know
+        ctx.hsd_set_energy_budget([ids[0], 999], ur, LO, HI, table[:2])
     ctx.hsd_set_energy_budget(ids[:2], ur, LO, HI, table[:2])
     with pytest.raises(hsd.HsdError):                            # grains 2, 3 have none
         ctx.hsd_solve_surrogate(ud, ids, [sur] * G, j, diag, check=hsd.CHECK_TABLE)
