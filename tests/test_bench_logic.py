@@ -1,6 +1,7 @@
 """Host logic of the benchmark: how the surrogate's radius ranges are formed,
-and the error measures it reports (band errors, relative error of j against
-the oracle)."""
+the error measures it reports (band errors, relative error of j against the
+oracle), its roofline accounting, and when it reports the recorded HBM
+traffic."""
 
 import numpy as np
 
@@ -82,3 +83,23 @@ def test_oracle_pairs_are_the_oracle_spectra():
     for k, c in enumerate((3, 40)):
         assert np.array_equal(spectra[(c, 0)], oracle.solve_pair(u[k], w.grains[0], w.lam_cm)[1])
     assert rec["kind"] == "oracle" and rec["value"] > 0 and rec["cores"] == bench.CPU_PROCS
+
+
+def test_traffic_reported_only_for_the_recorded_solver_sources(tmp_path, monkeypatch):
+    # the committed counter summary names the solver sources' hash; the bench
+    # reports its bytes while the sources hash to it and null once they change
+    import os
+    import shutil
+    for f in bench.SOLVER_SOURCES:
+        os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+        shutil.copy(os.path.join(bench.ROOT, f), tmp_path / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    summary = tmp_path / "profiles" / "solve_c5_hbm_traffic.md"
+    summary.write_text("solve_phase_hbm_bytes_per_step: 1.5e+09\n"
+                       f"solver_sources_sha256_16: {bench.solver_hash()}\n")
+    assert bench.recorded_traffic("c5_surrogate") == 1.5e9
+    assert bench.recorded_traffic("c2_batched") is None           # no summary for this workload
+    with open(tmp_path / bench.SOLVER_SOURCES[0], "a") as fh:
+        fh.write("\n")
+    assert bench.recorded_traffic("c5_surrogate") is None
